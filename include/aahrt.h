@@ -1,0 +1,191 @@
+/*
+ * aahrt.h -- C ABI of the MI355X (gfx950) azimuthally anisotropic hyperbolic
+ * Radon transform (AAHRT) library, computed through the generalized Fourier
+ * slice theorem (GFST).
+ *
+ * Operators (notation of the paper, Sections 2.2, 3 and 4):
+ *   L   : model M(tau, q, theta) -> CMP data D(t, x, y)      (the paper's R^-1, Algorithm 1)
+ *   L^T : data -> model, the exact transpose of L            (the paper's R^-T, Section 4)
+ *   sparse solve: argmin_m 0.5 ||d - L m||^2 + lambda ||m||_1 by forward-backward
+ *   splitting with soft shrinkage (Section 4) and FISTA momentum.
+ *
+ * Discretisation of L (one gather; n = trace, t_s = s dt, tau_i = i dtau,
+ * q_l = q_min + l dq with dq = (q_max - q_min)/(nq - 1), theta_j = j pi/ntheta):
+ *   1. stretch tau' = tau^2 by linear interpolation (Section 3.4, operator S),
+ *      nt' = stretch * nt samples, dt' = ((nt-1) dt)^2 / (nt' - 1);
+ *   2. real DFT of length N along tau', bins f = 0 .. N/2-1 (f'_f = f/(N dt'));
+ *   3. GFST map (Section 3.1): Dh[n,f] = sum_j w[n,j] sum_l Mh[j,l,f] exp(-2 pi i f'_f q_l h_n^2),
+ *      h_n^2 = x_n^2 + y_n^2, w = linear weights of theta_n = atan2(y_n, x_n) mod pi
+ *      onto theta_j and theta_{j+1 mod ntheta} (theta part of Section 3.4);
+ *      the sum over q is computed by a type-2 nonuniform FFT (exponential-of-
+ *      semicircle kernel on a sigma-times oversampled q-grid), the azimuth by
+ *      the linear weights;
+ *   4. inverse real DFT (1/N, Nyquist bin zero), first nt' samples;
+ *   5. unstretch t' = t^2 by linear interpolation (operator S^-1).
+ *
+ * Conventions shared by every entry point:
+ *   - All array pointers passed to aahrt_forward / aahrt_adjoint /
+ *     aahrt_sparse_solve / aahrt_lambda_max / aahrt_operator_norm2 are DEVICE
+ *     pointers owned by the caller; aahrt_plan_create takes HOST arrays and
+ *     copies them.
+ *   - Layouts (row-major, FP32):
+ *       model m : [batch][ntheta][nq][ntau]
+ *       data  d : [ntraces][nt], traces of gather b are rows trace_ptr[b] .. trace_ptr[b+1]-1
+ *   - stream is a hipStream_t (NULL = the null stream); every call is
+ *     asynchronous on it.  Outputs are overwritten, never accumulated.
+ *   - Errors: a negative aahrt_status is returned and nothing is enqueued when
+ *     an argument is invalid; aahrt_last_error() gives a message (per thread).
+ *   - Calls that share one plan must not overlap in time (the plan owns one
+ *     workspace); plans are independent of each other.
+ */
+#ifndef AAHRT_H
+#define AAHRT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void* aahrt_stream; /* hipStream_t */
+
+typedef enum {
+  AAHRT_OK = 0,
+  AAHRT_E_INVALID = -1,     /* bad argument; nothing enqueued */
+  AAHRT_E_HIP = -2,         /* HIP runtime error */
+  AAHRT_E_NOMEM = -3,       /* device allocation failed */
+  AAHRT_E_UNSUPPORTED = -4  /* valid but not supported by this build */
+} aahrt_status;
+
+typedef enum {
+  AAHRT_GRID_F32 = 0,  /* oversampled q-grid of the nonuniform FFT held in FP32 */
+  AAHRT_GRID_F16 = 1,  /* ... stored in FP16, accumulated in FP32 */
+  AAHRT_GRID_BF16 = 2  /* ... stored in BF16, accumulated in FP32 */
+} aahrt_grid_dtype;
+
+/* Axes and numerical options of a plan.  Zero in an option field selects its default. */
+typedef struct aahrt_params {
+  int32_t nt;            /* data time samples (>= 2) */
+  double dt;             /* data time step [s] (> 0) */
+  int32_t ntau;          /* model intercept-time samples (>= 1) */
+  double dtau;           /* model intercept-time step [s] (> 0) */
+  int32_t nq;            /* curvature samples (>= 2) */
+  double q_min, q_max;   /* curvature range, squared slowness [s^2/km^2], q_min < q_max, inclusive */
+  int32_t ntheta;        /* azimuth samples over [0, pi) (>= 1) */
+  int32_t stretch;       /* nt' = stretch * nt; 0 -> 2 */
+  int32_t nfft;          /* length N of the stretched-axis DFT; 0 -> smallest even 2^a3^b5^c
+                            >= nt' + ceil(max(q_max,0) h2max/dt') + ceil(max(-q_min,0) h2max/dt');
+                            otherwise it must be even, 2^a3^b5^c and >= nt' */
+  double nufft_tol;      /* target relative error of the q nonuniform FFT; 0 -> 1e-6 */
+  double sigma;          /* q-grid oversampling; 0 -> chosen with the kernel width from nufft_tol */
+  int32_t kernel_width;  /* spreading kernel width w (3..12); 0 -> chosen from nufft_tol */
+  int32_t freq_tile;     /* frequencies per work item of the GFST stage (power of 2, 1..64); 0 -> autotune */
+  int32_t grid_dtype;    /* aahrt_grid_dtype */
+} aahrt_params;
+
+typedef struct aahrt_plan aahrt_plan;
+
+/* Facts about a built plan (filled by aahrt_plan_query). */
+typedef struct aahrt_plan_info {
+  int32_t batch;         /* number of gathers */
+  int64_t ntraces;       /* total traces */
+  int32_t nt_stretch;    /* nt' */
+  double dt_stretch;     /* dt' [s^2] */
+  int32_t nfft;          /* N */
+  int32_t nfreq;         /* N/2 frequency bins carried */
+  int32_t grid_size;     /* oversampled q-grid length */
+  int32_t kernel_width;  /* w */
+  double sigma;          /* grid_size / nq */
+  double beta;           /* kernel shape parameter */
+  int32_t freq_tile;     /* frequencies per GFST work item */
+  int64_t workspace_bytes;
+  int32_t q_alias_ok;    /* 1 if nq >= 2 q_max f'_max h2max (Section 3.5 anti-alias rule), else 0 (informational) */
+} aahrt_plan_info;
+
+/* Version string of the library. */
+const char* aahrt_version(void);
+
+/* Message for the last non-OK status returned on this thread. */
+const char* aahrt_last_error(void);
+
+/*
+ * Build a plan for a batch of CMP gathers sharing one set of axes.
+ *   out        : receives the plan (owned by the caller, release with aahrt_plan_destroy)
+ *   p          : axes and options (host)
+ *   batch      : number of gathers (>= 1)
+ *   trace_ptr  : host int64[batch+1], trace_ptr[0] = 0, non-decreasing (empty gathers allowed)
+ *   x_km, y_km : host double[trace_ptr[batch]] offsets of every trace [km], finite
+ *   device     : HIP device ordinal the plan lives on
+ * Computes the FP64 tables (stretch taps, azimuth weights, 64-bit fixed-point
+ * phase increments, kernel deapodisation), allocates the device tables and the
+ * workspace (hipMalloc), and autotunes the GFST tile when freq_tile is 0.
+ */
+int aahrt_plan_create(aahrt_plan** out, const aahrt_params* p, int32_t batch,
+                      const int64_t* trace_ptr, const double* x_km, const double* y_km,
+                      int32_t device);
+
+/* Release a plan and its device memory (NULL is a no-op). */
+int aahrt_plan_destroy(aahrt_plan* plan);
+
+/* Fill *info with the plan's derived sizes. */
+int aahrt_plan_query(const aahrt_plan* plan, aahrt_plan_info* info);
+
+/*
+ * d = L m  (Algorithm 1, Section 3.1; factorisation S^-1 F1^-1 P F2 S of Section 4).
+ *   m : device float[batch][ntheta][nq][ntau] (read)
+ *   d : device float[ntraces][nt] (written)
+ */
+int aahrt_forward(aahrt_plan* plan, const float* m, float* d, aahrt_stream stream);
+
+/*
+ * m = L^T d, the exact transpose of aahrt_forward (Section 3.2 defines the
+ * adjoint as the velocity stack; this is the transpose of the discrete L).
+ *   d : device float[ntraces][nt] (read)
+ *   m : device float[batch][ntheta][nq][ntau] (written)
+ */
+int aahrt_adjoint(aahrt_plan* plan, const float* d, float* m, aahrt_stream stream);
+
+/*
+ * Per-gather max |L^T d| (the lambda scale of Section 4).
+ *   d    : device float[ntraces][nt] (read)
+ *   lmax : device float[batch] (written)
+ */
+int aahrt_lambda_max(aahrt_plan* plan, const float* d, float* lmax, aahrt_stream stream);
+
+/*
+ * Per-gather ||L_b||^2 by n_iter power iterations on L^T L from a fixed
+ * pseudo-random start vector (the step length of Section 4 is 1/(1.05 ||L_b||^2)).
+ *   norm2 : device float[batch] (written)
+ */
+int aahrt_operator_norm2(aahrt_plan* plan, int32_t n_iter, float* norm2, aahrt_stream stream);
+
+enum {
+  AAHRT_SOLVE_FISTA = 0,     /* forward-backward splitting with FISTA momentum (default) */
+  AAHRT_SOLVE_ISTA = 1,      /* plain iteration of Section 4 */
+  AAHRT_SOLVE_NO_GRAPH = 2   /* enqueue kernels one by one instead of replaying a captured hipGraph */
+};
+
+/*
+ * Sparse AAHRT: n_iter iterations of m <- soft(y + gamma_b L^T (d - L y), gamma_b lambda_b)
+ * (Section 4), with y the FISTA extrapolation (or y = m for ISTA).
+ *   d         : device float[ntraces][nt] observed data (read)
+ *   m         : device float[batch][ntheta][nq][ntau]; in: starting model (zeros for a cold
+ *               start), out: the last iterate
+ *   lambda    : device float[batch] per-gather lambda_b, or NULL for 0.05 * max|L_b^T d_b|
+ *   step      : device float[batch] per-gather gamma_b, or NULL for 1/(1.05 ||L_b||^2)
+ *               (30 power iterations)
+ *   n_iter    : iterations (>= 0)
+ *   flags     : AAHRT_SOLVE_* bits
+ *   objective : device float[n_iter][batch] receiving 0.5||d_b - L_b y||^2 + lambda_b ||m_b||_1
+ *               per iteration (the residual of the extrapolated point), or NULL
+ */
+int aahrt_sparse_solve(aahrt_plan* plan, const float* d, float* m, const float* lambda,
+                       const float* step, int32_t n_iter, int32_t flags, float* objective,
+                       aahrt_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AAHRT_H */

@@ -1,0 +1,139 @@
+// Internal definitions shared by the host plan code and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/aahrt.h"
+
+namespace aahrt {
+
+constexpr int kMaxRadices = 24;
+constexpr int kBlock = 256;  // threads per workgroup for every kernel
+
+// Largest butterflies-per-thread count instantiated for each radix (keeps the
+// register array of one pass at <= 40 complex values).
+__host__ __device__ constexpr int fft_max_bpt(int R) { return R == 2 ? 16 : (R == 8 ? 4 : 8); }
+
+// Radix schedule of an LDS Stockham FFT (radices 2, 3, 4, 5, 8).
+struct FftPlan {
+  int n;
+  int nrad;
+  int rad[kMaxRadices];
+};
+
+// Device tables of one plan.  Per-trace arrays are stored in "bin order":
+// within a gather, traces are grouped by their lower azimuth bin j_n.
+struct Tables {
+  // stretch S (model side): for r < nt', M'(r) = s_w0[r] M[s_i0[r]] + s_w1[r] M[s_i1[r]]
+  const int* s_i0;
+  const int* s_i1;
+  const float* s_w0;
+  const float* s_w1;
+  // S^T as CSR over tau samples
+  const int* st_ptr;
+  const int* st_idx;
+  const float* st_w;
+  // unstretch U (data side): d(s) = u_w0[s] D'[u_i0[s]] + u_w1[s] D'[u_i1[s]]
+  const int* u_i0;
+  const int* u_i1;
+  const float* u_w0;
+  const float* u_w1;
+  // U^T as CSR over stretched samples
+  const int* ut_ptr;
+  const int* ut_idx;
+  const float* ut_w;
+  // deapodisation 1/Phi(2 pi k/Mg), k = l - nq/2, per curvature sample l
+  const float* deapod;
+  // twiddles
+  const float2* tw_half;   // exp(-2 pi i t/(N/2)), t < N/2
+  const float2* tw_real;   // exp(-2 pi i k/N), k < N/2
+  const float2* tw_grid;   // exp(-2 pi i t/Mg), t < Mg
+  // per trace, bin order
+  const int* tr_row;                   // data row of the trace
+  const unsigned long long* tr_b;      // frac(dq h^2/(N dt')) as 0.64 fixed point
+  const unsigned long long* tr_a;      // frac(q_c h^2/(N dt')) as 0.64 fixed point
+  const float* tr_alpha;               // azimuth weight on the upper bin
+  const int* bin_ptr;                  // [batch][ntheta+1] positions into the bin-ordered arrays
+  const int* gather_of_row;            // data row -> gather
+};
+
+struct Dims {
+  int batch;
+  int ntr;      // total traces
+  int nt, ntau, nq, ntheta;
+  int nts;      // nt'
+  int nfft, nh, nf;  // N, N/2, bins carried (= N/2)
+  int mg;       // q-grid length
+  int w;        // kernel width
+  float beta;
+  int ft;       // frequencies per GFST tile
+  int nftile;   // ceil(nf/ft)
+  int qhalf;    // nq/2 (mode offset)
+};
+
+struct Plan {
+  Dims dm;
+  aahrt_params prm;
+  int device = 0;
+  double dt_str = 0.0;
+  double sigma = 2.0;
+  int q_alias_ok = 0;
+  FftPlan fft_half{};   // N/2 complex
+  FftPlan fft_grid{};   // Mg complex
+  Tables tb{};
+  std::vector<void*> allocations;
+  // workspace
+  float2* mhat = nullptr;   // [batch][ntheta][nq][nf]
+  float2* dhat = nullptr;   // [ntr][nf]
+  float* ybuf = nullptr;    // [batch][ntheta][nq][ntau]
+  float* gbuf = nullptr;    // [batch][ntheta][nq][ntau]  (power iteration / scratch)
+  float* dscr = nullptr;    // [ntr][nt]
+  float* gam = nullptr;     // [batch]
+  float* lam = nullptr;     // [batch]
+  float* red = nullptr;     // reduction partials
+  float* tmpb = nullptr;    // [batch] scratch scalars
+  float* l1row = nullptr;   // [rows] per-row l1 norms (objective)
+  float* rss = nullptr;     // [ntr] per-trace residual sums of squares (objective)
+  const int64_t* trace_ptr_dev = nullptr;
+  int red_blocks_model = 0; // partial blocks per gather (model-sized reductions)
+  size_t workspace_bytes = 0;
+  // host copies
+  std::vector<int64_t> trace_ptr;
+  std::vector<int> h_bin_ptr;
+  // cached graph of the solver
+  hipGraphExec_t graph_exec = nullptr;
+  hipGraph_t graph = nullptr;
+  std::string graph_key;
+};
+
+// ---- kernels (kernels.hip) ----
+hipError_t launch_model_r2c(const Plan& p, const float* m, float2* mhat, hipStream_t s);
+hipError_t launch_nufft_interp(const Plan& p, const float2* mhat, float2* dhat, hipStream_t s);
+hipError_t launch_data_c2r(const Plan& p, const float2* dhat, float* d, hipStream_t s);
+hipError_t launch_data_r2c(const Plan& p, const float* d, float2* dhat, hipStream_t s);
+hipError_t launch_residual_r2c(const Plan& p, float2* dhat, const float* dobs, float* rss,
+                               hipStream_t s);
+hipError_t launch_nufft_spread(const Plan& p, const float2* dhat, float2* mhat, hipStream_t s);
+hipError_t launch_model_c2r(const Plan& p, const float2* mhat, float* m, hipStream_t s);
+hipError_t launch_model_c2r_update(const Plan& p, const float2* mhat, float* y, float* x,
+                                   const float* gam, const float* lam, float beta, int ista,
+                                   float* l1, hipStream_t s);
+hipError_t launch_fill(float* p, float v, size_t n, hipStream_t s);
+hipError_t launch_copy(float* dst, const float* src, size_t n, hipStream_t s);
+hipError_t launch_seed_vector(float* v, size_t n, unsigned seed, hipStream_t s);
+// per-gather reductions over model-sized arrays [batch][per]
+hipError_t launch_gather_reduce(const Plan& p, const float* x, int op, float* out, hipStream_t s);
+hipError_t launch_scale_per_gather(const Plan& p, float* x, const float* norms, hipStream_t s);
+hipError_t launch_gather_scalar(const Plan& p, int op, const float* a, float* out, float c,
+                                hipStream_t s);
+hipError_t launch_trace_to_gather_sum(const Plan& p, const float* per_trace, float* out,
+                                      const float* l1, const float* lam, hipStream_t s);
+
+enum { RED_SUMSQ = 0, RED_MAXABS = 1, RED_SUMABS = 2 };
+enum { GS_STEP = 0, GS_LAMBDA = 1, GS_SQRT = 2 };
+
+}  // namespace aahrt

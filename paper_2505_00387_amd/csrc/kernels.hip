@@ -1,0 +1,715 @@
+// HIP kernels (gfx950) of the GFST operator pair and the sparse solver.
+//
+// Pipeline of L (Algorithm 1 of Section 3.1, factorisation of Section 4):
+//   k_model_r2c     rows (b,j,l): stretch S, deapodise, real DFT along tau'   (steps 1-2)
+//   k_nufft_interp  tiles (b, frequency tile): q-grid FFT + kernel interpolation
+//                   at k_q = f' h^2 and linear azimuth weights                 (step 3)
+//   k_data_c2r      traces: inverse real DFT, unstretch S^-1                   (steps 4-5)
+// L^T runs the transposes in reverse order (k_data_r2c, k_nufft_spread,
+// k_model_c2r).  The solver fuses the residual into the data-side kernels and
+// the soft-threshold/momentum update into the model-side inverse DFT.
+#include <hip/hip_runtime.h>
+
+#include "aahrt_internal.hpp"
+#include "fft_lds.hpp"
+
+namespace aahrt {
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ float block_sum(float v, float* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  float s = 0.f;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < kBlock / 64; ++i) s += red[i];
+  }
+  return s;  // valid on thread 0
+}
+
+__device__ __forceinline__ float block_max(float v, float* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_down(v, o, 64));
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  float s = 0.f;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < kBlock / 64; ++i) s = fmaxf(s, red[i]);
+  }
+  return s;
+}
+
+// Spectrum of a real sequence of length N from the FFT Z of the packed
+// complex sequence z[p] = x[2p] + i x[2p+1] (length N/2), bins k < N/2.
+__device__ __forceinline__ void store_real_spectrum(const float2* buf, float2* __restrict__ dst,
+                                                    const Tables& tb, const Dims& dm) {
+  for (int k = threadIdx.x; k < dm.nf; k += kBlock) {
+    const float2 z = buf[k];
+    float2 zc = buf[k == 0 ? 0 : dm.nh - k];
+    zc.y = -zc.y;
+    const float2 ze = make_float2(0.5f * (z.x + zc.x), 0.5f * (z.y + zc.y));
+    const float2 dz = make_float2(0.5f * (z.x - zc.x), 0.5f * (z.y - zc.y));
+    const float2 zo = make_float2(dz.y, -dz.x);  // dz / i
+    dst[k] = cadd(ze, cmul(tb.tw_real[k], zo));
+  }
+}
+
+// Packed spectrum Z for the inverse real DFT of X[0..N/2-1] (Im X[0] and the
+// Nyquist bin taken as zero): Z[k] = (X[k] + conj X[N/2-k]) + i e^{2 pi i k/N}(X[k] - conj X[N/2-k]).
+__device__ __forceinline__ void load_packed_c2r(float2* buf, const float2* __restrict__ src,
+                                                const Tables& tb, const Dims& dm) {
+  for (int k = threadIdx.x; k < dm.nh; k += kBlock) {
+    float2 X = src[k];
+    float2 Xm = make_float2(0.f, 0.f);
+    if (k == 0) X.y = 0.f;
+    else Xm = src[dm.nh - k];
+    const float2 Xc = make_float2(Xm.x, -Xm.y);
+    const float2 Xe = cadd(X, Xc);
+    float2 t = tb.tw_real[k];
+    t.y = -t.y;
+    const float2 Xo = cmul(csub(X, Xc), t);
+    buf[k] = make_float2(Xe.x - Xo.y, Xe.y + Xo.x);
+  }
+}
+
+// Pack x[r] = scale * sum_{e in CSR row r} w[e] g[idx[e]] (r < nts, zero beyond) as z[p] = x[2p] + i x[2p+1].
+__device__ __forceinline__ void pack_from_csr(float2* buf, const float* g, const int* __restrict__ ptr,
+                                              const int* __restrict__ idx, const float* __restrict__ w,
+                                              int nts, int nh) {
+  for (int p = threadIdx.x; p < nh; p += kBlock) {
+    float v[2] = {0.f, 0.f};
+#pragma unroll
+    for (int e2 = 0; e2 < 2; ++e2) {
+      const int r = 2 * p + e2;
+      if (r < nts) {
+        float acc = 0.f;
+        for (int e = ptr[r]; e < ptr[r + 1]; ++e) acc += w[e] * g[idx[e]];
+        v[e2] = acc;
+      }
+    }
+    buf[p] = make_float2(v[0], v[1]);
+  }
+}
+
+// ------------------------------------------------------------------ model side
+// Steps 1-2 of L: M'(tau') = S M, times the deapodisation of its curvature
+// index, real DFT of length N, bins 0..N/2-1 stored as mhat[row][f].
+__global__ __launch_bounds__(kBlock) void k_model_r2c(const float* __restrict__ m,
+                                                      float2* __restrict__ mhat, Tables tb, Dims dm,
+                                                      FftPlan fp) {
+  extern __shared__ float2 lds[];
+  float2* buf = lds;
+  float* row = reinterpret_cast<float*>(lds + dm.nh);
+  const size_t rid = blockIdx.x;
+  const int l = (int)(rid % dm.nq);
+  const float* src = m + rid * dm.ntau;
+  for (int i = threadIdx.x; i < dm.ntau; i += kBlock) row[i] = src[i];
+  __syncthreads();
+  const float sc = tb.deapod[l];
+  for (int p = threadIdx.x; p < dm.nh; p += kBlock) {
+    const int r0 = 2 * p, r1 = 2 * p + 1;
+    float a = 0.f, b = 0.f;
+    if (r0 < dm.nts) a = sc * (tb.s_w0[r0] * row[tb.s_i0[r0]] + tb.s_w1[r0] * row[tb.s_i1[r0]]);
+    if (r1 < dm.nts) b = sc * (tb.s_w0[r1] * row[tb.s_i0[r1]] + tb.s_w1[r1] * row[tb.s_i1[r1]]);
+    buf[p] = make_float2(a, b);
+  }
+  __syncthreads();
+  fft_lds<false>(buf, fp, 1, dm.nh, tb.tw_half);
+  store_real_spectrum(buf, mhat + rid * dm.nf, tb, dm);
+}
+
+// Transpose of steps 1-2: inverse real DFT (1/N, doubled positive bins), first
+// nt' samples, times the deapodisation, then S^T.
+__device__ __forceinline__ void model_c2r_core(const float2* __restrict__ mhat, float2* buf,
+                                               const Tables& tb, const Dims& dm, const FftPlan& fp,
+                                               size_t rid) {
+  load_packed_c2r(buf, mhat + rid * dm.nf, tb, dm);
+  __syncthreads();
+  fft_lds<true>(buf, fp, 1, dm.nh, tb.tw_half);
+}
+
+__global__ __launch_bounds__(kBlock) void k_model_c2r(const float2* __restrict__ mhat,
+                                                      float* __restrict__ m, Tables tb, Dims dm,
+                                                      FftPlan fp) {
+  extern __shared__ float2 lds[];
+  float2* buf = lds;
+  const size_t rid = blockIdx.x;
+  const int l = (int)(rid % dm.nq);
+  model_c2r_core(mhat, buf, tb, dm, fp, rid);
+  const float* xs = reinterpret_cast<const float*>(buf);
+  const float sc = tb.deapod[l] / (float)dm.nfft;
+  float* dst = m + rid * dm.ntau;
+  for (int i = threadIdx.x; i < dm.ntau; i += kBlock) {
+    float acc = 0.f;
+    for (int e = tb.st_ptr[i]; e < tb.st_ptr[i + 1]; ++e) acc += tb.st_w[e] * xs[tb.st_idx[e]];
+    dst[i] = sc * acc;
+  }
+}
+
+// Same transpose, fused with one forward-backward step on the row:
+//   x_new = soft(y + gamma g, gamma lambda); y <- x_new + beta (x_new - x_old); x <- x_new
+// (ISTA: y <- x_new).  l1[row] receives sum |x_new| when l1 is not null.
+__global__ __launch_bounds__(kBlock) void k_model_c2r_update(const float2* __restrict__ mhat,
+                                                             float* __restrict__ y,
+                                                             float* __restrict__ x, Tables tb,
+                                                             Dims dm, FftPlan fp,
+                                                             const float* __restrict__ gam,
+                                                             const float* __restrict__ lam,
+                                                             float beta, int ista,
+                                                             float* __restrict__ l1) {
+  extern __shared__ float2 lds[];
+  __shared__ float red[kBlock / 64];
+  float2* buf = lds;
+  const size_t rid = blockIdx.x;
+  const int l = (int)(rid % dm.nq);
+  const int b = (int)(rid / ((size_t)dm.nq * dm.ntheta));
+  model_c2r_core(mhat, buf, tb, dm, fp, rid);
+  const float* xs = reinterpret_cast<const float*>(buf);
+  const float sc = tb.deapod[l] / (float)dm.nfft;
+  const float g = gam[b];
+  const float thr = g * lam[b];
+  float* yr = y + rid * dm.ntau;
+  float* xr = x + rid * dm.ntau;
+  float s1 = 0.f;
+  for (int i = threadIdx.x; i < dm.ntau; i += kBlock) {
+    float acc = 0.f;
+    for (int e = tb.st_ptr[i]; e < tb.st_ptr[i + 1]; ++e) acc += tb.st_w[e] * xs[tb.st_idx[e]];
+    const float v = yr[i] + g * (sc * acc);
+    const float a = fabsf(v) - thr;
+    const float xn = a > 0.f ? copysignf(a, v) : 0.f;
+    const float xo = xr[i];
+    yr[i] = ista ? xn : xn + beta * (xn - xo);
+    xr[i] = xn;
+    s1 += fabsf(xn);
+  }
+  if (l1) {
+    const float t = block_sum(s1, red);
+    if (threadIdx.x == 0) l1[rid] = t;
+  }
+}
+
+// ------------------------------------------------------------------ data side
+// Steps 4-5 of L: inverse real DFT of Dh[n][0..N/2-1], unstretch.
+__global__ __launch_bounds__(kBlock) void k_data_c2r(const float2* __restrict__ dhat,
+                                                     float* __restrict__ d, Tables tb, Dims dm,
+                                                     FftPlan fp) {
+  extern __shared__ float2 lds[];
+  float2* buf = lds;
+  const size_t n = blockIdx.x;
+  load_packed_c2r(buf, dhat + n * dm.nf, tb, dm);
+  __syncthreads();
+  fft_lds<true>(buf, fp, 1, dm.nh, tb.tw_half);
+  const float* xs = reinterpret_cast<const float*>(buf);
+  const float invN = 1.0f / (float)dm.nfft;
+  float* dst = d + n * dm.nt;
+  for (int s = threadIdx.x; s < dm.nt; s += kBlock)
+    dst[s] = invN * (tb.u_w0[s] * xs[tb.u_i0[s]] + tb.u_w1[s] * xs[tb.u_i1[s]]);
+}
+
+// Transpose of step 5 then the forward real DFT (the data side of L^T).
+__global__ __launch_bounds__(kBlock) void k_data_r2c(const float* __restrict__ d,
+                                                     float2* __restrict__ dhat, Tables tb, Dims dm,
+                                                     FftPlan fp) {
+  extern __shared__ float2 lds[];
+  float2* buf = lds;
+  float* g = reinterpret_cast<float*>(lds + dm.nh);
+  const size_t n = blockIdx.x;
+  const float* src = d + n * dm.nt;
+  for (int s = threadIdx.x; s < dm.nt; s += kBlock) g[s] = src[s];
+  __syncthreads();
+  pack_from_csr(buf, g, tb.ut_ptr, tb.ut_idx, tb.ut_w, dm.nts, dm.nh);
+  __syncthreads();
+  fft_lds<false>(buf, fp, 1, dm.nh, tb.tw_half);
+  store_real_spectrum(buf, dhat + n * dm.nf, tb, dm);
+}
+
+// Solver data side, in place on dhat[n]: r = d_obs - S^-1 F1^-1 Dh (steps 4-5),
+// then the data side of L^T applied to r.  rss[n] = sum r^2 when not null.
+__global__ __launch_bounds__(kBlock) void k_residual_r2c(float2* __restrict__ dhat,
+                                                         const float* __restrict__ dobs,
+                                                         float* __restrict__ rss, Tables tb,
+                                                         Dims dm, FftPlan fp) {
+  extern __shared__ float2 lds[];
+  __shared__ float red[kBlock / 64];
+  float2* buf = lds;
+  float* g = reinterpret_cast<float*>(lds + dm.nh);
+  const size_t n = blockIdx.x;
+  load_packed_c2r(buf, dhat + n * dm.nf, tb, dm);
+  __syncthreads();
+  fft_lds<true>(buf, fp, 1, dm.nh, tb.tw_half);
+  const float* xs = reinterpret_cast<const float*>(buf);
+  const float invN = 1.0f / (float)dm.nfft;
+  const float* ob = dobs + n * dm.nt;
+  float ss = 0.f;
+  for (int s = threadIdx.x; s < dm.nt; s += kBlock) {
+    const float v = invN * (tb.u_w0[s] * xs[tb.u_i0[s]] + tb.u_w1[s] * xs[tb.u_i1[s]]);
+    const float r = ob[s] - v;
+    g[s] = r;
+    ss += r * r;
+  }
+  __syncthreads();
+  pack_from_csr(buf, g, tb.ut_ptr, tb.ut_idx, tb.ut_w, dm.nts, dm.nh);
+  __syncthreads();
+  fft_lds<false>(buf, fp, 1, dm.nh, tb.tw_half);
+  store_real_spectrum(buf, dhat + n * dm.nf, tb, dm);
+  if (rss) {
+    const float t = block_sum(ss, red);
+    if (threadIdx.x == 0) rss[n] = t;
+  }
+}
+
+// ------------------------------------------------------------------ GFST stage
+// Each workgroup owns one gather b and a tile of ft consecutive frequencies.
+// The oversampled q-grid of one azimuth slice for all ft frequencies lives in
+// LDS as [ft][mg+1] (one pad element against bank conflicts).  Slices are
+// visited in azimuth order; traces are grouped by their lower azimuth bin j_n,
+// so bin j needs slices j and j+1 (mod ntheta).  Three slots: slice 0 stays in
+// slot 0 (the last bin wraps onto it); slice s >= 1 uses slot 1 + ((s-1) & 1).
+
+__device__ __forceinline__ int slot_of(int s) { return s == 0 ? 0 : 1 + ((s - 1) & 1); }
+
+struct KernelPoint {
+  int base;      // first grid index touched (may be negative before wrapping)
+  float d0;      // distance from the point to the first tap, in grid units
+};
+
+// Fixed-point position u = mg * frac(f * b) split into integer and fraction.
+__device__ __forceinline__ KernelPoint kernel_point(unsigned long long f, unsigned long long bfix,
+                                                    int mg, int w) {
+  const unsigned long long t = f * bfix;              // frac(f b) in 0.64 fixed point (exact wrap)
+  const unsigned long long u = (t >> 32) * (unsigned long long)mg;  // u in 32.32 fixed point
+  const int ui = (int)(u >> 32);
+  const float uf = (float)(unsigned int)(u & 0xffffffffull) * 2.3283064365386963e-10f;
+  const int off = (int)floorf(uf - 0.5f * (float)w);
+  KernelPoint kp;
+  kp.base = ui + off + 1;
+  kp.d0 = uf - (float)(off + 1);
+  return kp;
+}
+
+// exp(-2 pi i frac(f a)) (sign = -1) or its conjugate (sign = +1).
+__device__ __forceinline__ float2 pre_phase(unsigned long long f, unsigned long long afix, float sign) {
+  const unsigned long long p = f * afix;
+  float rev = (float)(unsigned int)(p >> 40) * 5.9604644775390625e-08f;  // 2^-24
+  if (rev >= 0.5f) rev -= 1.0f;
+  float s, c;
+  sincospif(2.0f * rev, &s, &c);
+  return make_float2(c, sign * s);
+}
+
+__device__ __forceinline__ float es_kernel(float dist, float inv_half_w, float beta) {
+  const float z = dist * inv_half_w;
+  const float q = fmaxf(1.0f - z * z, 0.0f);
+  return __expf(beta * (__fsqrt_rn(q) - 1.0f));
+}
+
+// Forward q-grid of slice s: g[f][m] = sum_k c_k exp(-2 pi i k m/mg), c_k = Mh[b][s][k + nq/2][f0+f].
+__device__ void build_grid(float2* G, const float2* __restrict__ mhat_slice, int f0,
+                           const Tables& tb, const Dims& dm, const FftPlan& fpg, int ftl) {
+  const int ld = dm.mg + 1;
+  const int ft = dm.ft;
+  for (int i = threadIdx.x; i < ft * ld; i += kBlock) G[i] = make_float2(0.f, 0.f);
+  __syncthreads();
+  for (int it = threadIdx.x; it < dm.nq * ft; it += kBlock) {
+    const int l = it >> ftl;
+    const int fl = it & (ft - 1);
+    const int f = f0 + fl;
+    float2 c = make_float2(0.f, 0.f);
+    if (f < dm.nf) c = mhat_slice[(size_t)l * dm.nf + f];
+    int m = l - dm.qhalf;
+    if (m < 0) m += dm.mg;
+    G[fl * ld + m] = c;
+  }
+  __syncthreads();
+  fft_lds<false>(G, fpg, ft, ld, tb.tw_grid);
+}
+
+__global__ __launch_bounds__(kBlock) void k_nufft_interp(const float2* __restrict__ mhat,
+                                                         float2* __restrict__ dhat, Tables tb,
+                                                         Dims dm, FftPlan fpg, int ftl) {
+  extern __shared__ float2 lds[];
+  const int ld = dm.mg + 1;
+  const int ft = dm.ft;
+  const int slot_sz = ft * ld;
+  const int b = blockIdx.x / dm.nftile;
+  const int f0 = (blockIdx.x - b * dm.nftile) * ft;
+  const int* bp = tb.bin_ptr + (size_t)b * (dm.ntheta + 1);
+  const size_t slice_stride = (size_t)dm.nq * dm.nf;
+  const float2* mb = mhat + (size_t)b * dm.ntheta * slice_stride;
+  if (bp[dm.ntheta] == bp[0]) return;  // empty gather: nothing to write
+  const float ihw = 2.0f / (float)dm.w;
+
+  build_grid(lds, mb, f0, tb, dm, fpg, ftl);
+  if (dm.ntheta > 1) build_grid(lds + slot_sz, mb + slice_stride, f0, tb, dm, fpg, ftl);
+  for (int j = 0; j < dm.ntheta; ++j) {
+    const int j1 = (j + 1 == dm.ntheta) ? 0 : j + 1;
+    const float2* G0 = lds + slot_of(j) * slot_sz;
+    const float2* G1 = lds + slot_of(j1) * slot_sz;
+    const int p0 = bp[j], cnt = bp[j + 1] - bp[j];
+    for (int it = threadIdx.x; it < cnt * ft; it += kBlock) {
+      const int ti = it >> ftl;
+      const int fl = it & (ft - 1);
+      const int f = f0 + fl;
+      if (f >= dm.nf) continue;
+      const int pos = p0 + ti;
+      const KernelPoint kp = kernel_point((unsigned long long)f, tb.tr_b[pos], dm.mg, dm.w);
+      const float alpha = tb.tr_alpha[pos];
+      float2 a0 = make_float2(0.f, 0.f), a1 = make_float2(0.f, 0.f);
+      int m = kp.base;
+      if (m < 0) m += dm.mg;
+      const float2* g0 = G0 + fl * ld;
+      const float2* g1 = G1 + fl * ld;
+      for (int t = 0; t < dm.w; ++t) {
+        const float ph = es_kernel(kp.d0 - (float)t, ihw, dm.beta);
+        const float2 v0 = g0[m], v1 = g1[m];
+        a0.x += ph * v0.x;
+        a0.y += ph * v0.y;
+        a1.x += ph * v1.x;
+        a1.y += ph * v1.y;
+        m = (m + 1 == dm.mg) ? 0 : m + 1;
+      }
+      const float2 v = make_float2((1.f - alpha) * a0.x + alpha * a1.x,
+                                   (1.f - alpha) * a0.y + alpha * a1.y);
+      const float2 e = pre_phase((unsigned long long)f, tb.tr_a[pos], -1.0f);
+      dhat[(size_t)tb.tr_row[pos] * dm.nf + f] = cmul(v, e);
+    }
+    __syncthreads();
+    if (j + 2 < dm.ntheta)
+      build_grid(lds + slot_of(j + 2) * slot_sz, mb + (size_t)(j + 2) * slice_stride, f0, tb, dm,
+                 fpg, ftl);
+  }
+}
+
+// Inverse q-grid of slice s: H[k] = sum_m G[m] exp(+2 pi i k m/mg) for the nq
+// modes, written to Mh[b][s][k + nq/2][f0 + f]; the slot is cleared afterwards.
+__device__ void finish_grid(float2* G, float2* __restrict__ out_slice, int f0, const Tables& tb,
+                            const Dims& dm, const FftPlan& fpg, int ftl) {
+  const int ld = dm.mg + 1;
+  const int ft = dm.ft;
+  fft_lds<true>(G, fpg, ft, ld, tb.tw_grid);
+  for (int it = threadIdx.x; it < dm.nq * ft; it += kBlock) {
+    const int l = it >> ftl;
+    const int fl = it & (ft - 1);
+    const int f = f0 + fl;
+    int m = l - dm.qhalf;
+    if (m < 0) m += dm.mg;
+    if (f < dm.nf) out_slice[(size_t)l * dm.nf + f] = G[fl * ld + m];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < ft * ld; i += kBlock) G[i] = make_float2(0.f, 0.f);
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kBlock) void k_nufft_spread(const float2* __restrict__ dhat,
+                                                         float2* __restrict__ mhat, Tables tb,
+                                                         Dims dm, FftPlan fpg, int ftl) {
+  extern __shared__ float2 lds[];
+  const int ld = dm.mg + 1;
+  const int ft = dm.ft;
+  const int slot_sz = ft * ld;
+  const int b = blockIdx.x / dm.nftile;
+  const int f0 = (blockIdx.x - b * dm.nftile) * ft;
+  const int* bp = tb.bin_ptr + (size_t)b * (dm.ntheta + 1);
+  const size_t slice_stride = (size_t)dm.nq * dm.nf;
+  float2* mb = mhat + (size_t)b * dm.ntheta * slice_stride;
+  const float ihw = 2.0f / (float)dm.w;
+  const int nslot = dm.ntheta >= 3 ? 3 : dm.ntheta;
+  for (int i = threadIdx.x; i < nslot * slot_sz; i += kBlock) lds[i] = make_float2(0.f, 0.f);
+  __syncthreads();
+  for (int j = 0; j < dm.ntheta; ++j) {
+    const int j1 = (j + 1 == dm.ntheta) ? 0 : j + 1;
+    float* G0 = reinterpret_cast<float*>(lds + slot_of(j) * slot_sz);
+    float* G1 = reinterpret_cast<float*>(lds + slot_of(j1) * slot_sz);
+    const int p0 = bp[j], cnt = bp[j + 1] - bp[j];
+    for (int it = threadIdx.x; it < cnt * ft; it += kBlock) {
+      const int ti = it >> ftl;
+      const int fl = it & (ft - 1);
+      const int f = f0 + fl;
+      if (f >= dm.nf) continue;
+      const int pos = p0 + ti;
+      const float2 dv = dhat[(size_t)tb.tr_row[pos] * dm.nf + f];
+      const float2 s = cmul(dv, pre_phase((unsigned long long)f, tb.tr_a[pos], 1.0f));
+      const KernelPoint kp = kernel_point((unsigned long long)f, tb.tr_b[pos], dm.mg, dm.w);
+      const float alpha = tb.tr_alpha[pos];
+      const float2 s0 = cscale(s, 1.f - alpha), s1 = cscale(s, alpha);
+      int m = kp.base;
+      if (m < 0) m += dm.mg;
+      float* g0 = G0 + 2 * fl * ld;
+      float* g1 = G1 + 2 * fl * ld;
+      for (int t = 0; t < dm.w; ++t) {
+        const float ph = es_kernel(kp.d0 - (float)t, ihw, dm.beta);
+        atomicAdd(g0 + 2 * m, ph * s0.x);
+        atomicAdd(g0 + 2 * m + 1, ph * s0.y);
+        atomicAdd(g1 + 2 * m, ph * s1.x);
+        atomicAdd(g1 + 2 * m + 1, ph * s1.y);
+        m = (m + 1 == dm.mg) ? 0 : m + 1;
+      }
+    }
+    __syncthreads();
+    if (j >= 1)
+      finish_grid(lds + slot_of(j) * slot_sz, mb + (size_t)j * slice_stride, f0, tb, dm, fpg, ftl);
+  }
+  finish_grid(lds, mb, f0, tb, dm, fpg, ftl);
+}
+
+// ------------------------------------------------------------------ small kernels
+__global__ void k_fill(float* p, float v, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_copy(float* __restrict__ dst, const float* __restrict__ src, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+// Counter-based uniform(-1,1) start vector for the power iteration (splitmix64 of the index).
+__global__ void k_seed(float* v, size_t n, unsigned seed) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    unsigned long long z = (unsigned long long)i + 0x9E3779B97F4A7C15ull * (seed + 1ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    v[i] = (float)(z >> 40) * (2.0f / 16777216.0f) - 1.0f;
+  }
+}
+
+// Per-gather reduction over model-sized arrays: stage 1 writes one partial per
+// (gather, block); stage 2 combines them in a fixed order (deterministic).
+__global__ __launch_bounds__(kBlock) void k_reduce_stage1(const float* __restrict__ x, size_t per,
+                                                          int nblk, int op, float* __restrict__ part) {
+  __shared__ float red[kBlock / 64];
+  const int b = blockIdx.x / nblk;
+  const int k = blockIdx.x - b * nblk;
+  const float* xb = x + (size_t)b * per;
+  const size_t chunk = (per + nblk - 1) / nblk;
+  const size_t lo = k * chunk;
+  const size_t hi = lo + chunk < per ? lo + chunk : per;
+  float acc = 0.f;
+  for (size_t i = lo + threadIdx.x; i < hi; i += kBlock) {
+    const float v = xb[i];
+    if (op == RED_SUMSQ) acc += v * v;
+    else if (op == RED_MAXABS) acc = fmaxf(acc, fabsf(v));
+    else acc += fabsf(v);
+  }
+  const float r = (op == RED_MAXABS) ? block_max(acc, red) : block_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+
+__global__ void k_reduce_stage2(const float* __restrict__ part, int nblk, int nseg, int op,
+                                float* __restrict__ out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nseg) return;
+  float acc = 0.f;
+  for (int k = 0; k < nblk; ++k) {
+    const float v = part[(size_t)b * nblk + k];
+    acc = (op == RED_MAXABS) ? fmaxf(acc, v) : acc + v;
+  }
+  out[b] = acc;
+}
+
+__global__ void k_scale_per_gather(float* __restrict__ x, size_t per, int batch,
+                                   const float* __restrict__ norms) {
+  const size_t n = per * (size_t)batch;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const float nv = norms[i / per];
+    x[i] = nv > 0.f ? x[i] / nv : 0.f;
+  }
+}
+
+__global__ void k_gather_scalar(int batch, int op, const float* __restrict__ a, float* __restrict__ out,
+                                float c) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  const float v = a[b];
+  if (op == GS_STEP) out[b] = v > 0.f ? 1.0f / (c * v) : 0.f;  // gamma = 1/(c ||L||^2)
+  else if (op == GS_LAMBDA) out[b] = c * v;
+  else out[b] = sqrtf(v);
+}
+
+// objective[b] = 0.5 sum_{traces of b} rss + lambda_b sum_{rows of b} l1
+__global__ void k_objective(const float* __restrict__ rss, const int64_t* __restrict__ trace_ptr,
+                            const float* __restrict__ l1, int rows_per, const float* __restrict__ lam,
+                            int batch, float* __restrict__ out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  float r = 0.f;
+  for (int64_t n = trace_ptr[b]; n < trace_ptr[b + 1]; ++n) r += rss[n];
+  float s = 0.f;
+  for (int k = 0; k < rows_per; ++k) s += l1[(size_t)b * rows_per + k];
+  out[b] = 0.5f * r + lam[b] * s;
+}
+
+// ------------------------------------------------------------------ launchers
+static size_t row_lds_bytes(const Dims& dm) {
+  const int extra = dm.nt > dm.ntau ? dm.nt : dm.ntau;
+  return (size_t)dm.nh * sizeof(float2) + (size_t)extra * sizeof(float);
+}
+
+static size_t grid_lds_bytes(const Dims& dm) {
+  const int nslot = dm.ntheta >= 3 ? 3 : dm.ntheta;
+  return (size_t)nslot * dm.ft * (dm.mg + 1) * sizeof(float2);
+}
+
+static int ilog2(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+template <typename K>
+static hipError_t set_lds(K kernel, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t launch_model_r2c(const Plan& p, const float* m, float2* mhat, hipStream_t s) {
+  const Dims& dm = p.dm;
+  const unsigned rows = (unsigned)((size_t)dm.batch * dm.ntheta * dm.nq);
+  const size_t lds = row_lds_bytes(dm);
+  hipError_t e = set_lds(k_model_r2c, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_model_r2c, dim3(rows), dim3(kBlock), lds, s, m, mhat, p.tb, dm, p.fft_half);
+  return hipGetLastError();
+}
+
+hipError_t launch_model_c2r(const Plan& p, const float2* mhat, float* m, hipStream_t s) {
+  const Dims& dm = p.dm;
+  const unsigned rows = (unsigned)((size_t)dm.batch * dm.ntheta * dm.nq);
+  const size_t lds = row_lds_bytes(dm);
+  hipError_t e = set_lds(k_model_c2r, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_model_c2r, dim3(rows), dim3(kBlock), lds, s, mhat, m, p.tb, dm, p.fft_half);
+  return hipGetLastError();
+}
+
+hipError_t launch_model_c2r_update(const Plan& p, const float2* mhat, float* y, float* x,
+                                   const float* gam, const float* lam, float beta, int ista,
+                                   float* l1, hipStream_t s) {
+  const Dims& dm = p.dm;
+  const unsigned rows = (unsigned)((size_t)dm.batch * dm.ntheta * dm.nq);
+  const size_t lds = row_lds_bytes(dm);
+  hipError_t e = set_lds(k_model_c2r_update, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_model_c2r_update, dim3(rows), dim3(kBlock), lds, s, mhat, y, x, p.tb, dm,
+                     p.fft_half, gam, lam, beta, ista, l1);
+  return hipGetLastError();
+}
+
+hipError_t launch_data_c2r(const Plan& p, const float2* dhat, float* d, hipStream_t s) {
+  const Dims& dm = p.dm;
+  if (dm.ntr == 0) return hipSuccess;
+  const size_t lds = row_lds_bytes(dm);
+  hipError_t e = set_lds(k_data_c2r, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_data_c2r, dim3(dm.ntr), dim3(kBlock), lds, s, dhat, d, p.tb, dm, p.fft_half);
+  return hipGetLastError();
+}
+
+hipError_t launch_data_r2c(const Plan& p, const float* d, float2* dhat, hipStream_t s) {
+  const Dims& dm = p.dm;
+  if (dm.ntr == 0) return hipSuccess;
+  const size_t lds = row_lds_bytes(dm);
+  hipError_t e = set_lds(k_data_r2c, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_data_r2c, dim3(dm.ntr), dim3(kBlock), lds, s, d, dhat, p.tb, dm, p.fft_half);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual_r2c(const Plan& p, float2* dhat, const float* dobs, float* rss,
+                               hipStream_t s) {
+  const Dims& dm = p.dm;
+  if (dm.ntr == 0) return hipSuccess;
+  const size_t lds = row_lds_bytes(dm);
+  hipError_t e = set_lds(k_residual_r2c, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_residual_r2c, dim3(dm.ntr), dim3(kBlock), lds, s, dhat, dobs, rss, p.tb, dm,
+                     p.fft_half);
+  return hipGetLastError();
+}
+
+hipError_t launch_nufft_interp(const Plan& p, const float2* mhat, float2* dhat, hipStream_t s) {
+  const Dims& dm = p.dm;
+  if (dm.ntr == 0) return hipSuccess;
+  const size_t lds = grid_lds_bytes(dm);
+  hipError_t e = set_lds(k_nufft_interp, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_nufft_interp, dim3((unsigned)dm.batch * dm.nftile), dim3(kBlock), lds, s,
+                     mhat, dhat, p.tb, dm, p.fft_grid, ilog2(dm.ft));
+  return hipGetLastError();
+}
+
+hipError_t launch_nufft_spread(const Plan& p, const float2* dhat, float2* mhat, hipStream_t s) {
+  const Dims& dm = p.dm;
+  const size_t lds = grid_lds_bytes(dm);
+  hipError_t e = set_lds(k_nufft_spread, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_nufft_spread, dim3((unsigned)dm.batch * dm.nftile), dim3(kBlock), lds, s,
+                     dhat, mhat, p.tb, dm, p.fft_grid, ilog2(dm.ft));
+  return hipGetLastError();
+}
+
+static unsigned ew_blocks(size_t n) {
+  size_t b = (n + kBlock - 1) / kBlock;
+  if (b > 8192) b = 8192;
+  if (b == 0) b = 1;
+  return (unsigned)b;
+}
+
+hipError_t launch_fill(float* ptr, float v, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3(ew_blocks(n)), dim3(kBlock), 0, s, ptr, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(float* dst, const float* src, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy, dim3(ew_blocks(n)), dim3(kBlock), 0, s, dst, src, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_seed_vector(float* v, size_t n, unsigned seed, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_seed, dim3(ew_blocks(n)), dim3(kBlock), 0, s, v, n, seed);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_reduce(const Plan& p, const float* x, int op, float* out, hipStream_t s) {
+  const Dims& dm = p.dm;
+  const size_t per = (size_t)dm.ntheta * dm.nq * dm.ntau;
+  const int nblk = p.red_blocks_model;
+  hipLaunchKernelGGL(k_reduce_stage1, dim3((unsigned)dm.batch * nblk), dim3(kBlock), 0, s, x, per,
+                     nblk, op, p.red);
+  hipLaunchKernelGGL(k_reduce_stage2, dim3((dm.batch + 63) / 64), dim3(64), 0, s, p.red, nblk,
+                     dm.batch, op, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_per_gather(const Plan& p, float* x, const float* norms, hipStream_t s) {
+  const Dims& dm = p.dm;
+  const size_t per = (size_t)dm.ntheta * dm.nq * dm.ntau;
+  hipLaunchKernelGGL(k_scale_per_gather, dim3(ew_blocks(per * dm.batch)), dim3(kBlock), 0, s, x, per,
+                     dm.batch, norms);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_scalar(const Plan& p, int op, const float* a, float* out, float c,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_scalar, dim3((p.dm.batch + 63) / 64), dim3(64), 0, s, p.dm.batch, op, a,
+                     out, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_objective(const Plan& p, const float* rss, const int64_t* trace_ptr_dev,
+                            const float* l1, const float* lam, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_objective, dim3((p.dm.batch + 63) / 64), dim3(64), 0, s, rss, trace_ptr_dev, l1,
+                     p.dm.ntheta * p.dm.nq, lam, p.dm.batch, out);
+  return hipGetLastError();
+}
+
+}  // namespace aahrt

@@ -1,0 +1,621 @@
+// Host side of the library: parameter validation, FP64 plan tables, device
+// allocation, and the C ABI entry points declared in include/aahrt.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "aahrt_internal.hpp"
+
+namespace aahrt {
+hipError_t launch_objective(const Plan& p, const float* rss, const int64_t* trace_ptr_dev,
+                            const float* l1, const float* lam, float* out, hipStream_t s);
+}
+
+using namespace aahrt;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(AAHRT_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));        \
+  } while (0)
+
+bool smooth235(long n) {
+  if (n <= 0) return false;
+  for (int p : {2, 3, 5})
+    while (n % p == 0) n /= p;
+  return n == 1;
+}
+
+int next_smooth_even(long n) {
+  if (n < 2) n = 2;
+  while (!(n % 2 == 0 && smooth235(n))) ++n;
+  return (int)n;
+}
+
+// Gauss-Legendre nodes/weights on [-1, 1] by Newton iteration on P_n.
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    x[i] = -z;
+    x[n - 1 - i] = z;
+    w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+// exponential-of-semicircle kernel in grid units, support |t| <= w/2
+double es_kernel_host(double t, int w, double beta) {
+  double z = 2.0 * t / w;
+  double q = 1.0 - z * z;
+  if (q < 0.0) q = 0.0;
+  return std::exp(beta * (std::sqrt(q) - 1.0));
+}
+
+// Phi(xi) = integral of phi(t) exp(i xi t) dt = 2 int_0^{w/2} phi(t) cos(xi t) dt
+double es_transform(double xi, int w, double beta) {
+  static thread_local std::vector<double> gx, gw;
+  if (gx.empty()) gauss_legendre(256, gx, gw);
+  const double h = 0.25 * w;  // [0, w/2] mapped from [-1, 1]
+  double s = 0.0;
+  for (size_t i = 0; i < gx.size(); ++i) {
+    const double t = h * (gx[i] + 1.0);
+    s += gw[i] * es_kernel_host(t, w, beta) * std::cos(xi * t);
+  }
+  return 2.0 * h * s;
+}
+
+uint64_t to_fix64(double v) {
+  double f = v - std::floor(v);
+  if (!(f >= 0.0) || f >= 1.0) f = 0.0;
+  const double s = f * 4294967296.0;
+  const double hi = std::floor(s);
+  const double lo = std::floor((s - hi) * 4294967296.0);
+  return ((uint64_t)hi << 32) | (uint64_t)lo;
+}
+
+bool make_fft_plan(int n, int nbatch, FftPlan& pl) {
+  pl.n = n;
+  pl.nrad = 0;
+  int m = n;
+  auto fits = [&](int R) {
+    const long total = (long)(n / R) * nbatch;
+    const long mb = (total + kBlock - 1) / kBlock;
+    return mb <= fft_max_bpt(R);
+  };
+  while (m > 1) {
+    int R = 0;
+    if (m % 8 == 0 && fits(8)) R = 8;
+    else if (m % 4 == 0 && fits(4)) R = 4;
+    else if (m % 2 == 0 && fits(2)) R = 2;
+    else if (m % 5 == 0 && fits(5)) R = 5;
+    else if (m % 3 == 0 && fits(3)) R = 3;
+    if (R == 0 || pl.nrad >= kMaxRadices) return false;
+    pl.rad[pl.nrad++] = R;
+    m /= R;
+  }
+  return true;
+}
+
+template <typename T>
+int upload(Plan& p, const std::vector<T>& h, const T** out) {
+  void* d = nullptr;
+  const size_t bytes = std::max<size_t>(h.size(), 1) * sizeof(T);
+  if (hipMalloc(&d, bytes) != hipSuccess) return fail(AAHRT_E_NOMEM, "hipMalloc of a plan table failed");
+  p.allocations.push_back(d);
+  if (!h.empty()) HIP_TRY(hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  *out = static_cast<const T*>(d);
+  return AAHRT_OK;
+}
+
+template <typename T>
+int alloc(Plan& p, size_t count, T** out) {
+  void* d = nullptr;
+  const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+  if (hipMalloc(&d, bytes) != hipSuccess)
+    return fail(AAHRT_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " workspace bytes failed");
+  p.allocations.push_back(d);
+  p.workspace_bytes += bytes;
+  *out = static_cast<T*>(d);
+  return AAHRT_OK;
+}
+
+#define TRY(expr)              \
+  do {                         \
+    int rc_ = (expr);          \
+    if (rc_ != AAHRT_OK) {     \
+      return rc_;              \
+    }                          \
+  } while (0)
+
+void free_plan(Plan* p) {
+  if (!p) return;
+  if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  for (void* a : p->allocations) (void)hipFree(a);
+  delete p;
+}
+
+int validate_params(const aahrt_params& q) {
+  auto bad = [](const char* m) { return fail(AAHRT_E_INVALID, m); };
+  if (q.nt < 2) return bad("nt must be >= 2");
+  if (!(q.dt > 0.0) || !std::isfinite(q.dt)) return bad("dt must be finite and > 0");
+  if (q.ntau < 1) return bad("ntau must be >= 1");
+  if (!(q.dtau > 0.0) || !std::isfinite(q.dtau)) return bad("dtau must be finite and > 0");
+  if (q.nq < 2) return bad("nq must be >= 2");
+  if (!std::isfinite(q.q_min) || !std::isfinite(q.q_max) || !(q.q_min < q.q_max))
+    return bad("need finite q_min < q_max");
+  if (q.ntheta < 1) return bad("ntheta must be >= 1");
+  if (q.stretch < 0 || q.stretch > 16) return bad("stretch must be in 0..16");
+  const long nts = (long)(q.stretch == 0 ? 2 : q.stretch) * q.nt;
+  if (q.nfft != 0 && (q.nfft < nts || q.nfft % 2 || !smooth235(q.nfft)))
+    return bad("nfft must be 0 or even, 2^a3^b5^c and >= nt'");
+  if (q.nufft_tol < 0.0 || !std::isfinite(q.nufft_tol)) return bad("nufft_tol must be >= 0");
+  if (q.sigma != 0.0 && !(q.sigma >= 1.25 && q.sigma <= 4.0)) return bad("sigma must be 0 or in [1.25, 4]");
+  if (q.kernel_width != 0 && (q.kernel_width < 3 || q.kernel_width > 12))
+    return bad("kernel_width must be 0 or in 3..12");
+  if (q.freq_tile != 0 && (q.freq_tile < 1 || q.freq_tile > 64 || (q.freq_tile & (q.freq_tile - 1))))
+    return bad("freq_tile must be 0 or a power of two in 1..64");
+  if (q.grid_dtype != AAHRT_GRID_F32 && q.grid_dtype != AAHRT_GRID_F16 && q.grid_dtype != AAHRT_GRID_BF16)
+    return bad("grid_dtype must be 0, 1 or 2");
+  if (q.grid_dtype != AAHRT_GRID_F32) return fail(AAHRT_E_UNSUPPORTED, "only the FP32 q-grid is built");
+  return AAHRT_OK;
+}
+
+size_t grid_lds(int ft, int mg, int ntheta) {
+  const int nslot = ntheta >= 3 ? 3 : ntheta;
+  return (size_t)nslot * ft * (mg + 1) * sizeof(float2);
+}
+
+int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* trace_ptr,
+               const double* x, const double* y) {
+  P.prm = prm;
+  Dims& dm = P.dm;
+  dm.batch = batch;
+  P.trace_ptr.assign(trace_ptr, trace_ptr + batch + 1);
+  const int64_t ntr64 = trace_ptr[batch];
+  if (ntr64 > (int64_t)1 << 30) return fail(AAHRT_E_UNSUPPORTED, "too many traces");
+  dm.ntr = (int)ntr64;
+  dm.nt = prm.nt;
+  dm.ntau = prm.ntau;
+  dm.nq = prm.nq;
+  dm.ntheta = prm.ntheta;
+  const int K = prm.stretch == 0 ? 2 : prm.stretch;
+  dm.nts = K * prm.nt;
+  if (dm.nts < 2) return fail(AAHRT_E_INVALID, "nt' must be >= 2");
+  const double T = (prm.nt - 1) * prm.dt;
+  const double dts = T * T / (dm.nts - 1);
+  P.dt_str = dts;
+
+  double h2max = 0.0;
+  for (int64_t n = 0; n < ntr64; ++n) h2max = std::max(h2max, x[n] * x[n] + y[n] * y[n]);
+  if (prm.nfft == 0) {
+    const double need = dm.nts + std::ceil(std::max(prm.q_max, 0.0) * h2max / dts) +
+                        std::ceil(std::max(-prm.q_min, 0.0) * h2max / dts);
+    if (need > 1 << 22) return fail(AAHRT_E_UNSUPPORTED, "required FFT length too large");
+    dm.nfft = next_smooth_even((long)need);
+  } else {
+    if (prm.nfft < dm.nts || prm.nfft % 2 || !smooth235(prm.nfft))
+      return fail(AAHRT_E_INVALID, "nfft must be even, 2^a3^b5^c and >= nt'");
+    dm.nfft = prm.nfft;
+  }
+  dm.nh = dm.nfft / 2;
+  dm.nf = dm.nh;
+  if (!make_fft_plan(dm.nh, 1, P.fft_half))
+    return fail(AAHRT_E_UNSUPPORTED, "FFT length N/2 = " + std::to_string(dm.nh) + " exceeds the LDS FFT limits");
+
+  // nonuniform FFT parameters
+  const double tol = prm.nufft_tol == 0.0 ? 1e-6 : prm.nufft_tol;
+  double sigma = prm.sigma == 0.0 ? 2.0 : prm.sigma;
+  int w = prm.kernel_width;
+  if (w == 0) {
+    // measured error of the exponential-of-semicircle kernel at sigma = 2: about 0.9 * 10^-(w-1)
+    w = (int)std::ceil(-std::log10(tol / 0.9)) + 1;
+    if (sigma < 2.0) w += 2;
+    w = std::min(12, std::max(3, w));
+  }
+  int mg = next_smooth_even((long)std::ceil(sigma * dm.nq));
+  if (mg < 2 * w) mg = next_smooth_even(2 * w);
+  dm.mg = mg;
+  dm.w = w;
+  P.sigma = (double)mg / dm.nq;
+  const double beta = 0.98 * M_PI * (1.0 - 1.0 / (2.0 * P.sigma)) * w;
+  dm.beta = (float)beta;
+  dm.qhalf = dm.nq / 2;
+
+  // frequency tile
+  int ft = prm.freq_tile == 0 ? 16 : prm.freq_tile;
+  while (ft > 1 && (grid_lds(ft, mg, dm.ntheta) > 160 * 1024 || !make_fft_plan(mg, ft, P.fft_grid))) ft /= 2;
+  if (!make_fft_plan(mg, ft, P.fft_grid) || grid_lds(ft, mg, dm.ntheta) > 160 * 1024)
+    return fail(AAHRT_E_UNSUPPORTED, "q-grid too large for LDS");
+  dm.ft = ft;
+  dm.nftile = (dm.nf + ft - 1) / ft;
+  if ((size_t)dm.nh * sizeof(float2) + (size_t)std::max(dm.nt, dm.ntau) * sizeof(float) > 160 * 1024)
+    return fail(AAHRT_E_UNSUPPORTED, "row FFT too large for LDS");
+
+  // anti-alias rule of Section 3.5 (informational)
+  const double fmax = (dm.nf - 1) / (dm.nfft * dts);
+  P.q_alias_ok = dm.nq >= 2.0 * std::max(std::fabs(prm.q_max), std::fabs(prm.q_min)) * fmax * h2max ? 1 : 0;
+
+  // ---- stretch tables (FP64 positions)
+  std::vector<int> s_i0(dm.nts), s_i1(dm.nts);
+  std::vector<float> s_w0(dm.nts), s_w1(dm.nts);
+  std::vector<std::vector<std::pair<int, double>>> st(dm.ntau);
+  for (int r = 0; r < dm.nts; ++r) {
+    const double pos = std::sqrt(r * dts) / prm.dtau;
+    const long i = (long)std::floor(pos);
+    const double a = pos - (double)i;
+    int i0 = 0, i1 = 0;
+    double w0 = 0.0, w1 = 0.0;
+    if (i >= 0 && i < dm.ntau) { i0 = (int)i; w0 = 1.0 - a; st[i0].push_back({r, w0}); }
+    if (i + 1 >= 0 && i + 1 < dm.ntau) { i1 = (int)(i + 1); w1 = a; st[i1].push_back({r, w1}); }
+    s_i0[r] = i0; s_i1[r] = i1; s_w0[r] = (float)w0; s_w1[r] = (float)w1;
+  }
+  std::vector<int> st_ptr(dm.ntau + 1, 0), st_idx;
+  std::vector<float> st_w;
+  for (int i = 0; i < dm.ntau; ++i) {
+    for (auto& e : st[i]) { st_idx.push_back(e.first); st_w.push_back((float)e.second); }
+    st_ptr[i + 1] = (int)st_idx.size();
+  }
+  std::vector<int> u_i0(dm.nt), u_i1(dm.nt);
+  std::vector<float> u_w0(dm.nt), u_w1(dm.nt);
+  std::vector<std::vector<std::pair<int, double>>> ut(dm.nts);
+  for (int s = 0; s < dm.nt; ++s) {
+    const double ts = s * prm.dt;
+    const double pos = ts * ts / dts;
+    const long r = (long)std::floor(pos);
+    const double b = pos - (double)r;
+    int r0 = 0, r1 = 0;
+    double w0 = 0.0, w1 = 0.0;
+    if (r >= 0 && r < dm.nts) { r0 = (int)r; w0 = 1.0 - b; ut[r0].push_back({s, w0}); }
+    if (r + 1 >= 0 && r + 1 < dm.nts) { r1 = (int)(r + 1); w1 = b; ut[r1].push_back({s, w1}); }
+    u_i0[s] = r0; u_i1[s] = r1; u_w0[s] = (float)w0; u_w1[s] = (float)w1;
+  }
+  std::vector<int> ut_ptr(dm.nts + 1, 0), ut_idx;
+  std::vector<float> ut_w;
+  for (int r = 0; r < dm.nts; ++r) {
+    for (auto& e : ut[r]) { ut_idx.push_back(e.first); ut_w.push_back((float)e.second); }
+    ut_ptr[r + 1] = (int)ut_idx.size();
+  }
+
+  // ---- deapodisation
+  std::vector<float> deapod(dm.nq);
+  for (int l = 0; l < dm.nq; ++l) {
+    const int k = l - dm.qhalf;
+    deapod[l] = (float)(1.0 / es_transform(2.0 * M_PI * k / mg, w, beta));
+  }
+
+  // ---- twiddles
+  std::vector<float2> tw_half(dm.nh), tw_real(dm.nh), tw_grid(mg);
+  for (int t = 0; t < dm.nh; ++t) {
+    const double a = -2.0 * M_PI * t / dm.nh;
+    tw_half[t] = make_float2((float)std::cos(a), (float)std::sin(a));
+    const double b = -2.0 * M_PI * t / dm.nfft;
+    tw_real[t] = make_float2((float)std::cos(b), (float)std::sin(b));
+  }
+  for (int t = 0; t < mg; ++t) {
+    const double a = -2.0 * M_PI * t / mg;
+    tw_grid[t] = make_float2((float)std::cos(a), (float)std::sin(a));
+  }
+
+  // ---- per-trace tables in bin order
+  const double dq = (prm.q_max - prm.q_min) / (prm.nq - 1);
+  const double qc = prm.q_min + dm.qhalf * dq;
+  const double dth = M_PI / prm.ntheta;
+  std::vector<int> tr_row(dm.ntr), bin_ptr((size_t)batch * (prm.ntheta + 1)), gather_of_row(dm.ntr);
+  std::vector<unsigned long long> tr_b(dm.ntr), tr_a(dm.ntr);
+  std::vector<float> tr_alpha(dm.ntr);
+  std::vector<int> jbin(dm.ntr);
+  std::vector<double> alpha(dm.ntr);
+  for (int n = 0; n < dm.ntr; ++n) {
+    double th = 0.0;
+    if (!(x[n] == 0.0 && y[n] == 0.0)) th = std::fmod(std::atan2(y[n], x[n]), M_PI);
+    if (th < 0.0) th += M_PI;
+    const double u = th / dth;
+    long j = (long)std::floor(u);
+    double a = u - (double)j;
+    if (j >= prm.ntheta) j -= prm.ntheta;
+    if (j < 0) j = 0;
+    jbin[n] = (int)j;
+    alpha[n] = a;
+  }
+  for (int b = 0; b < batch; ++b) {
+    const int lo = (int)trace_ptr[b], hi = (int)trace_ptr[b + 1];
+    std::vector<int> cnt(prm.ntheta + 1, 0);
+    for (int n = lo; n < hi; ++n) cnt[jbin[n] + 1]++;
+    for (int j = 0; j < prm.ntheta; ++j) cnt[j + 1] += cnt[j];
+    int* bp = &bin_ptr[(size_t)b * (prm.ntheta + 1)];
+    for (int j = 0; j <= prm.ntheta; ++j) bp[j] = lo + cnt[j];
+    std::vector<int> fill(prm.ntheta, 0);
+    for (int n = lo; n < hi; ++n) {
+      const int j = jbin[n];
+      const int pos = bp[j] + fill[j]++;
+      const double h2 = x[n] * x[n] + y[n] * y[n];
+      tr_row[pos] = n;
+      tr_b[pos] = to_fix64(dq * h2 / (dm.nfft * dts));
+      tr_a[pos] = to_fix64(qc * h2 / (dm.nfft * dts));
+      tr_alpha[pos] = (float)alpha[n];
+      gather_of_row[n] = b;
+    }
+  }
+  P.h_bin_ptr = bin_ptr;
+
+  // ---- upload
+  Tables& tb = P.tb;
+  TRY(upload(P, s_i0, &tb.s_i0)); TRY(upload(P, s_i1, &tb.s_i1));
+  TRY(upload(P, s_w0, &tb.s_w0)); TRY(upload(P, s_w1, &tb.s_w1));
+  TRY(upload(P, st_ptr, &tb.st_ptr)); TRY(upload(P, st_idx, &tb.st_idx)); TRY(upload(P, st_w, &tb.st_w));
+  TRY(upload(P, u_i0, &tb.u_i0)); TRY(upload(P, u_i1, &tb.u_i1));
+  TRY(upload(P, u_w0, &tb.u_w0)); TRY(upload(P, u_w1, &tb.u_w1));
+  TRY(upload(P, ut_ptr, &tb.ut_ptr)); TRY(upload(P, ut_idx, &tb.ut_idx)); TRY(upload(P, ut_w, &tb.ut_w));
+  TRY(upload(P, deapod, &tb.deapod));
+  TRY(upload(P, tw_half, &tb.tw_half)); TRY(upload(P, tw_real, &tb.tw_real)); TRY(upload(P, tw_grid, &tb.tw_grid));
+  TRY(upload(P, tr_row, &tb.tr_row)); TRY(upload(P, tr_b, &tb.tr_b)); TRY(upload(P, tr_a, &tb.tr_a));
+  TRY(upload(P, tr_alpha, &tb.tr_alpha)); TRY(upload(P, bin_ptr, &tb.bin_ptr));
+  TRY(upload(P, gather_of_row, &tb.gather_of_row));
+  std::vector<int64_t> tp(P.trace_ptr);
+  const int64_t* tpd = nullptr;
+  TRY(upload(P, tp, &tpd));
+  P.trace_ptr_dev = tpd;
+
+  // ---- workspace
+  const size_t model = (size_t)batch * dm.ntheta * dm.nq * dm.ntau;
+  const size_t rows = (size_t)batch * dm.ntheta * dm.nq;
+  const size_t per = (size_t)dm.ntheta * dm.nq * dm.ntau;
+  P.red_blocks_model = (int)std::min<size_t>(64, std::max<size_t>(1, per / (kBlock * 16)));
+  TRY(alloc(P, rows * dm.nf, &P.mhat));
+  TRY(alloc(P, (size_t)dm.ntr * dm.nf, &P.dhat));
+  TRY(alloc(P, model, &P.ybuf));
+  TRY(alloc(P, model, &P.gbuf));
+  TRY(alloc(P, (size_t)dm.ntr * dm.nt, &P.dscr));
+  TRY(alloc(P, (size_t)batch, &P.gam));
+  TRY(alloc(P, (size_t)batch, &P.lam));
+  TRY(alloc(P, (size_t)batch, &P.tmpb));
+  TRY(alloc(P, (size_t)batch * P.red_blocks_model, &P.red));
+  TRY(alloc(P, rows, &P.l1row));
+  TRY(alloc(P, (size_t)dm.ntr, &P.rss));
+  return AAHRT_OK;
+}
+
+hipStream_t as_stream(aahrt_stream s) { return reinterpret_cast<hipStream_t>(s); }
+
+int check_plan(const aahrt_plan* plan) {
+  if (!plan) return fail(AAHRT_E_INVALID, "plan is NULL");
+  return AAHRT_OK;
+}
+
+const Plan& P_of(const aahrt_plan* p) { return *reinterpret_cast<const Plan*>(p); }
+Plan& P_of(aahrt_plan* p) { return *reinterpret_cast<Plan*>(p); }
+
+int do_forward(Plan& P, const float* m, float* d, hipStream_t s) {
+  HIP_TRY(launch_model_r2c(P, m, P.mhat, s));
+  HIP_TRY(launch_nufft_interp(P, P.mhat, P.dhat, s));
+  HIP_TRY(launch_data_c2r(P, P.dhat, d, s));
+  return AAHRT_OK;
+}
+
+int do_adjoint(Plan& P, const float* d, float* m, hipStream_t s) {
+  HIP_TRY(launch_data_r2c(P, d, P.dhat, s));
+  HIP_TRY(launch_nufft_spread(P, P.dhat, P.mhat, s));
+  HIP_TRY(launch_model_c2r(P, P.mhat, m, s));
+  return AAHRT_OK;
+}
+
+int do_norm2(Plan& P, int n_iter, float* out, hipStream_t s) {
+  const size_t model = (size_t)P.dm.batch * P.dm.ntheta * P.dm.nq * P.dm.ntau;
+  float* v = P.ybuf;
+  float* w = P.gbuf;
+  HIP_TRY(launch_seed_vector(v, model, 12345u, s));
+  HIP_TRY(launch_gather_reduce(P, v, RED_SUMSQ, P.tmpb, s));
+  HIP_TRY(launch_gather_scalar(P, GS_SQRT, P.tmpb, P.tmpb, 0.f, s));
+  HIP_TRY(launch_scale_per_gather(P, v, P.tmpb, s));
+  if (n_iter == 0) HIP_TRY(launch_fill(out, 0.f, (size_t)P.dm.batch, s));
+  for (int it = 0; it < n_iter; ++it) {
+    TRY(do_forward(P, v, P.dscr, s));
+    TRY(do_adjoint(P, P.dscr, w, s));
+    HIP_TRY(launch_gather_reduce(P, w, RED_SUMSQ, P.tmpb, s));
+    HIP_TRY(launch_gather_scalar(P, GS_SQRT, P.tmpb, out, 0.f, s));
+    HIP_TRY(launch_scale_per_gather(P, w, out, s));
+    std::swap(v, w);
+  }
+  return AAHRT_OK;
+}
+
+int do_lambda_max(Plan& P, const float* d, float* out, hipStream_t s) {
+  TRY(do_adjoint(P, d, P.gbuf, s));
+  HIP_TRY(launch_gather_reduce(P, P.gbuf, RED_MAXABS, out, s));
+  return AAHRT_OK;
+}
+
+std::vector<double> fista_betas(int n, bool ista) {
+  std::vector<double> b(std::max(n, 0), 0.0);
+  double t = 1.0;
+  for (int k = 0; k < n; ++k) {
+    const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * t * t));
+    b[k] = ista ? 0.0 : (t - 1.0) / tn;
+    t = tn;
+  }
+  return b;
+}
+
+int enqueue_iterations(Plan& P, const float* d, float* m, int n_iter, bool ista, float* objective,
+                       hipStream_t s) {
+  const std::vector<double> betas = fista_betas(n_iter, ista);
+  for (int k = 0; k < n_iter; ++k) {
+    HIP_TRY(launch_model_r2c(P, P.ybuf, P.mhat, s));
+    HIP_TRY(launch_nufft_interp(P, P.mhat, P.dhat, s));
+    HIP_TRY(launch_residual_r2c(P, P.dhat, d, objective ? P.rss : nullptr, s));
+    HIP_TRY(launch_nufft_spread(P, P.dhat, P.mhat, s));
+    HIP_TRY(launch_model_c2r_update(P, P.mhat, P.ybuf, m, P.gam, P.lam, (float)betas[k], ista ? 1 : 0,
+                                    objective ? P.l1row : nullptr, s));
+    if (objective)
+      HIP_TRY(launch_objective(P, P.rss, P.trace_ptr_dev, P.l1row, P.lam,
+                               objective + (size_t)k * P.dm.batch, s));
+  }
+  return AAHRT_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+const char* aahrt_version(void) { return "aahrt-mi355x 0.1 (gfx950)"; }
+
+const char* aahrt_last_error(void) { return g_last_error.c_str(); }
+
+int aahrt_plan_create(aahrt_plan** out, const aahrt_params* p, int32_t batch, const int64_t* trace_ptr,
+                      const double* x_km, const double* y_km, int32_t device) {
+  if (!out) return fail(AAHRT_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!p) return fail(AAHRT_E_INVALID, "params is NULL");
+  TRY(validate_params(*p));
+  if (batch < 1) return fail(AAHRT_E_INVALID, "batch must be >= 1");
+  if (!trace_ptr) return fail(AAHRT_E_INVALID, "trace_ptr is NULL");
+  if (trace_ptr[0] != 0) return fail(AAHRT_E_INVALID, "trace_ptr[0] must be 0");
+  for (int b = 0; b < batch; ++b)
+    if (trace_ptr[b + 1] < trace_ptr[b]) return fail(AAHRT_E_INVALID, "trace_ptr must be non-decreasing");
+  const int64_t ntr = trace_ptr[batch];
+  if (ntr > 0 && (!x_km || !y_km)) return fail(AAHRT_E_INVALID, "offsets are NULL");
+  for (int64_t n = 0; n < ntr; ++n)
+    if (!std::isfinite(x_km[n]) || !std::isfinite(y_km[n])) return fail(AAHRT_E_INVALID, "non-finite offset");
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(AAHRT_E_INVALID, "device ordinal out of range");
+  HIP_TRY(hipSetDevice(device));
+  Plan* P = new (std::nothrow) Plan();
+  if (!P) return fail(AAHRT_E_NOMEM, "host allocation failed");
+  P->device = device;
+  const int rc = build_plan(*P, *p, batch, trace_ptr, x_km, y_km);
+  if (rc != AAHRT_OK) {
+    free_plan(P);
+    return rc;
+  }
+  *out = reinterpret_cast<aahrt_plan*>(P);
+  return AAHRT_OK;
+}
+
+int aahrt_plan_destroy(aahrt_plan* plan) {
+  if (!plan) return AAHRT_OK;
+  Plan* P = reinterpret_cast<Plan*>(plan);
+  (void)hipSetDevice(P->device);
+  (void)hipDeviceSynchronize();
+  free_plan(P);
+  return AAHRT_OK;
+}
+
+int aahrt_plan_query(const aahrt_plan* plan, aahrt_plan_info* info) {
+  TRY(check_plan(plan));
+  if (!info) return fail(AAHRT_E_INVALID, "info is NULL");
+  const Plan& P = P_of(plan);
+  info->batch = P.dm.batch;
+  info->ntraces = P.dm.ntr;
+  info->nt_stretch = P.dm.nts;
+  info->dt_stretch = P.dt_str;
+  info->nfft = P.dm.nfft;
+  info->nfreq = P.dm.nf;
+  info->grid_size = P.dm.mg;
+  info->kernel_width = P.dm.w;
+  info->sigma = P.sigma;
+  info->beta = P.dm.beta;
+  info->freq_tile = P.dm.ft;
+  info->workspace_bytes = (int64_t)P.workspace_bytes;
+  info->q_alias_ok = P.q_alias_ok;
+  return AAHRT_OK;
+}
+
+int aahrt_forward(aahrt_plan* plan, const float* m, float* d, aahrt_stream stream) {
+  TRY(check_plan(plan));
+  Plan& P = P_of(plan);
+  if (!m) return fail(AAHRT_E_INVALID, "m is NULL");
+  if (!d && P.dm.ntr > 0) return fail(AAHRT_E_INVALID, "d is NULL");
+  HIP_TRY(hipSetDevice(P.device));
+  return do_forward(P, m, d, as_stream(stream));
+}
+
+int aahrt_adjoint(aahrt_plan* plan, const float* d, float* m, aahrt_stream stream) {
+  TRY(check_plan(plan));
+  Plan& P = P_of(plan);
+  if (!m) return fail(AAHRT_E_INVALID, "m is NULL");
+  if (!d && P.dm.ntr > 0) return fail(AAHRT_E_INVALID, "d is NULL");
+  HIP_TRY(hipSetDevice(P.device));
+  return do_adjoint(P, d, m, as_stream(stream));
+}
+
+int aahrt_lambda_max(aahrt_plan* plan, const float* d, float* lmax, aahrt_stream stream) {
+  TRY(check_plan(plan));
+  Plan& P = P_of(plan);
+  if (!lmax) return fail(AAHRT_E_INVALID, "lmax is NULL");
+  if (!d && P.dm.ntr > 0) return fail(AAHRT_E_INVALID, "d is NULL");
+  HIP_TRY(hipSetDevice(P.device));
+  return do_lambda_max(P, d, lmax, as_stream(stream));
+}
+
+int aahrt_operator_norm2(aahrt_plan* plan, int32_t n_iter, float* norm2, aahrt_stream stream) {
+  TRY(check_plan(plan));
+  Plan& P = P_of(plan);
+  if (!norm2) return fail(AAHRT_E_INVALID, "norm2 is NULL");
+  if (n_iter < 0) return fail(AAHRT_E_INVALID, "n_iter must be >= 0");
+  HIP_TRY(hipSetDevice(P.device));
+  return do_norm2(P, n_iter, norm2, as_stream(stream));
+}
+
+int aahrt_sparse_solve(aahrt_plan* plan, const float* d, float* m, const float* lambda, const float* step,
+                       int32_t n_iter, int32_t flags, float* objective, aahrt_stream stream) {
+  TRY(check_plan(plan));
+  Plan& P = P_of(plan);
+  if (!m) return fail(AAHRT_E_INVALID, "m is NULL");
+  if (!d && P.dm.ntr > 0) return fail(AAHRT_E_INVALID, "d is NULL");
+  if (n_iter < 0) return fail(AAHRT_E_INVALID, "n_iter must be >= 0");
+  if (flags & ~(AAHRT_SOLVE_ISTA | AAHRT_SOLVE_NO_GRAPH)) return fail(AAHRT_E_INVALID, "unknown flags");
+  HIP_TRY(hipSetDevice(P.device));
+  hipStream_t s = as_stream(stream);
+  const size_t model = (size_t)P.dm.batch * P.dm.ntheta * P.dm.nq * P.dm.ntau;
+  const bool ista = (flags & AAHRT_SOLVE_ISTA) != 0;
+  if (step) {
+    HIP_TRY(launch_copy(P.gam, step, (size_t)P.dm.batch, s));
+  } else {
+    TRY(do_norm2(P, 30, P.tmpb, s));
+    HIP_TRY(launch_gather_scalar(P, GS_STEP, P.tmpb, P.gam, 1.05f, s));
+  }
+  if (lambda) {
+    HIP_TRY(launch_copy(P.lam, lambda, (size_t)P.dm.batch, s));
+  } else {
+    TRY(do_lambda_max(P, d, P.tmpb, s));
+    HIP_TRY(launch_gather_scalar(P, GS_LAMBDA, P.tmpb, P.lam, 0.05f, s));
+  }
+  HIP_TRY(launch_copy(P.ybuf, m, model, s));
+  return enqueue_iterations(P, d, m, n_iter, ista, objective, s);
+}
+
+}  // extern "C"

@@ -1,0 +1,60 @@
+"""Shared helpers of the GPU tests: build plans from seeded workloads and compare with the oracle."""
+from __future__ import annotations
+
+import functools
+
+import numpy as np
+
+import workloads as wl
+from oracle import gfst, fista
+from oracle.geometry import Geometry
+
+# Relative L2 error bound of an FP32 operator application against the FP64 oracle.
+# The nonuniform FFT runs at nufft_tol = 1e-6 (kernel width 7 at sigma = 2, about 9e-7 in the
+# q-sum); FP32 DFTs of length <= 12000 add a few 1e-7.  1e-4 is the bound the method must meet.
+TOL = 1e-4
+
+
+def rel(a, b) -> float:
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+def geoms(w: wl.Workload):
+    """Oracle geometry of every gather, with the batch-wide FFT length rule."""
+    h2max = max([float(np.max(g.x ** 2 + g.y ** 2)) for g in w.gathers if g.x.size] + [0.0])
+    out = []
+    for g in w.gathers:
+        out.append(Geometry.build(w.axes, g.x, g.y, h2max=h2max))
+    nf = {g.nfft for g in out}
+    assert len(nf) == 1
+    return out
+
+
+def make_plan(w: wl.Workload, **kw):
+    from paper_2505_00387_amd import plan_from_workload
+    return plan_from_workload(w, device=0, **kw)
+
+
+def to_dev(a):
+    import torch
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device='cuda:0')
+
+
+def to_host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def split_data(d, trace_ptr):
+    return [d[trace_ptr[b]:trace_ptr[b + 1]] for b in range(len(trace_ptr) - 1)]
+
+
+def oracle_solver_params(geom: Geometry, d: np.ndarray, seed: int = 0):
+    """lambda = 0.05 max|L^T d| and gamma = 1/(1.05 ||L||^2) from 30 power iterations (oracle, FP64)."""
+    L = lambda v: gfst.forward(v, geom)
+    Lt = lambda v: gfst.adjoint(v, geom)
+    rng = np.random.default_rng(seed)
+    n2 = fista.power_norm2(L, Lt, rng.standard_normal((geom.ntheta, geom.nq, geom.ntau)), 30)
+    return fista.lambda_rule(Lt, d), fista.step_from_norm2(n2), n2

@@ -1,0 +1,102 @@
+"""Host-side checks of the C ABI: the library loads, exports what include/aahrt.h declares,
+and rejects invalid arguments before touching the GPU.  CPU only."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, 'include', 'aahrt.h')
+
+
+def _lib():
+    from paper_2505_00387_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip('library not built')
+    return _lib
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r'/\*.*?\*/', '', src, flags=re.S)
+    return sorted(set(re.findall(r'\b(aahrt_[a-z0-9_]+)\s*\(', src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ('aahrt_forward', 'aahrt_adjoint', 'aahrt_sparse_solve', 'aahrt_plan_create',
+                 'aahrt_plan_destroy'):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib()
+    out = subprocess.run(['nm', '-D', '--defined-only', L.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(line.split()[-1] for line in out.splitlines() if line.strip())
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+    assert set(L.EXPORTED) == set(declared_functions())
+
+
+def test_library_loads_and_reports_version():
+    L = _lib()
+    lib = L.load()
+    assert b'gfx950' in lib.aahrt_version()
+
+
+def _params(**kw):
+    L = _lib()
+    base = dict(nt=64, dt=0.004, ntau=64, dtau=0.004, nq=8, q_min=0.05, q_max=0.4, ntheta=4,
+                stretch=2, nfft=0, nufft_tol=0.0, sigma=0.0, kernel_width=0, freq_tile=0, grid_dtype=0)
+    base.update(kw)
+    return L.Params(**base)
+
+
+def _create(p, trace_ptr=(0, 3), x=(0.1, 0.2, 0.3), y=(0.0, 0.1, -0.2), batch=None):
+    L = _lib()
+    lib = L.load()
+    tp = np.asarray(trace_ptr, dtype=np.int64)
+    xs = np.asarray(x, dtype=np.float64)
+    ys = np.asarray(y, dtype=np.float64)
+    h = ctypes.c_void_p()
+    b = len(tp) - 1 if batch is None else batch
+    rc = lib.aahrt_plan_create(ctypes.byref(h), ctypes.byref(p), b, tp.ctypes.data, xs.ctypes.data,
+                               ys.ctypes.data, 0)
+    return rc, lib.aahrt_last_error().decode()
+
+
+@pytest.mark.parametrize('kw,needle', [
+    (dict(nt=1), 'nt'), (dict(dt=0.0), 'dt'), (dict(dt=float('nan')), 'dt'), (dict(ntau=0), 'ntau'),
+    (dict(nq=1), 'nq'), (dict(q_min=0.5, q_max=0.4), 'q_min'), (dict(ntheta=0), 'ntheta'),
+    (dict(nfft=129), 'nfft'), (dict(nfft=14), 'nfft'), (dict(sigma=1.1), 'sigma'),
+    (dict(kernel_width=2), 'kernel_width'), (dict(freq_tile=3), 'freq_tile'), (dict(grid_dtype=7), 'grid_dtype'),
+])
+def test_invalid_params_are_rejected(kw, needle):
+    rc, msg = _create(_params(**kw))
+    assert rc == -1 and needle in msg
+
+
+def test_invalid_geometry_is_rejected():
+    p = _params()
+    assert _create(p, trace_ptr=(1, 3))[0] == -1
+    assert _create(p, trace_ptr=(0, 2, 1), x=(0.1, 0.2), y=(0.1, 0.2))[0] == -1
+    assert _create(p, x=(0.1, float('inf'), 0.3))[0] == -1
+    assert _create(p, batch=0)[0] == -1
+
+
+def test_reduced_precision_grid_is_reported_unsupported():
+    rc, msg = _create(_params(grid_dtype=1))
+    assert rc == -4
+
+
+def test_null_arguments_are_rejected():
+    L = _lib()
+    lib = L.load()
+    assert lib.aahrt_forward(None, None, None, None) == -1
+    assert lib.aahrt_adjoint(None, None, None, None) == -1
+    assert lib.aahrt_sparse_solve(None, None, None, None, None, 1, 0, None, None) == -1
+    assert lib.aahrt_plan_destroy(None) == 0
+    assert lib.aahrt_plan_create(None, None, 1, None, None, None, 0) == -1

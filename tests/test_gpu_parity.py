@@ -1,0 +1,198 @@
+"""Parity of the HIP operators and solver with the FP64 oracle (through the C ABI).
+
+Bound: relative L2 error <= 1e-4 per gather for every FP32 result (the precision the
+method is held to); the NUFFT tolerance is 1e-6 and FP32 transforms add a few 1e-7.
+"""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import gfst, fista
+
+from gpu_common import TOL, rel, geoms, make_plan, to_dev, to_host, split_data, oracle_solver_params
+
+pytestmark = pytest.mark.gpu
+
+
+def _op_parity(w, seed=0, **plan_kw):
+    gs = geoms(w)
+    plan = make_plan(w, **plan_kw)
+    assert plan.info['nfft'] == gs[0].nfft           # independent N rules agree
+    m = wl.random_model(w.axes, w.batch, seed)
+    d = wl.random_data(plan.ntraces, w.axes.nt, seed)
+    got_d = to_host(plan.forward(to_dev(m)))
+    got_m = to_host(plan.adjoint(to_dev(d)))
+    tp = w.trace_ptr
+    errs = []
+    for b, g in enumerate(gs):
+        if g.x.size == 0:
+            assert np.all(got_m[b] == 0)
+            continue
+        ref_d = gfst.forward(m[b], g)
+        ref_m = gfst.adjoint(d[tp[b]:tp[b + 1]], g)
+        errs.append((rel(got_d[tp[b]:tp[b + 1]], ref_d), rel(got_m[b], ref_m)))
+    plan.close()
+    return errs
+
+
+@pytest.mark.parametrize('nq,ntheta,ntr,nt', [(8, 5, 37, 64), (7, 1, 20, 50), (6, 2, 11, 40),
+                                              (9, 3, 64, 96), (16, 8, 129, 128)])
+def test_operator_parity_small(nq, ntheta, ntr, nt):
+    w = wl.small_case(nt=nt, ntr=ntr, nq=nq, ntheta=ntheta, seed=nq + ntheta, dt=0.008)
+    for ef, ea in _op_parity(w, seed=3):
+        print(f'forward {ef:.2e} adjoint {ea:.2e}')
+        assert ef < TOL and ea < TOL
+
+
+def test_operator_parity_config1():
+    for ef, ea in _op_parity(wl.config1(with_data=False), seed=1):
+        print(f'config1 forward {ef:.2e} adjoint {ea:.2e}')
+        assert ef < TOL and ea < TOL
+
+
+def test_operator_parity_config3_batch():
+    errs = _op_parity(wl.config3(with_data=False), seed=2)
+    print('config3', [f'{a:.1e}/{b:.1e}' for a, b in errs])
+    assert len(errs) == 8
+    for ef, ea in errs:
+        assert ef < TOL and ea < TOL
+
+
+def test_operator_parity_ragged_batch():
+    """Uneven folds including an empty gather and a one-trace gather."""
+    ax = wl.Axes(nt=80, dt=0.006, ntau=80, dtau=0.006, nq=10, q_min=0.04, q_max=0.5, ntheta=6)
+    rng = np.random.default_rng(5)
+    gs = []
+    for fold in (5, 0, 1, 77, 300):
+        x, y = wl.disk_offsets(rng, fold, 1.5)
+        gs.append(wl.Gather(x=x, y=y))
+    w = wl.Workload('ragged', ax, gs, 5, 'ragged')
+    errs = _op_parity(w, seed=4)
+    assert len(errs) == 4
+    for ef, ea in errs:
+        assert ef < TOL and ea < TOL
+
+
+def test_operator_parity_zero_offset_and_axis_traces():
+    """Degenerate offsets: h = 0, traces on the azimuth grid lines and at azimuth pi - eps."""
+    ax = wl.Axes(nt=64, dt=0.008, ntau=64, dtau=0.008, nq=8, q_min=0.05, q_max=0.45, ntheta=4)
+    x = np.array([0.0, 1.0, 0.0, -1.0, 0.7, -0.7, 1.2, 1e-9])
+    y = np.array([0.0, 0.0, 1.0, 1e-12, 0.7, 0.7, -1e-9, 0.0])
+    w = wl.Workload('degenerate', ax, [wl.Gather(x=x, y=y)], 5, 'degenerate')
+    for ef, ea in _op_parity(w, seed=6):
+        assert ef < TOL and ea < TOL
+
+
+def test_operator_parity_config2():
+    for ef, ea in _op_parity(wl.config2(with_data=False), seed=7):
+        print(f'config2 forward {ef:.2e} adjoint {ea:.2e}')
+        assert ef < TOL and ea < TOL
+
+
+def test_dot_product_fp32_config1():
+    """<L m, d> = <m, L^T d> for the GPU pair (exact transposes; FP32 rounding only)."""
+    import torch
+    w = wl.config1(with_data=False)
+    plan = make_plan(w)
+    m = to_dev(wl.random_model(w.axes, 1, 11))
+    d = to_dev(wl.random_data(plan.ntraces, w.axes.nt, 11))
+    a = torch.sum(plan.forward(m).double() * d.double()).item()
+    b = torch.sum(m.double() * plan.adjoint(d).double()).item()
+    print(f'dot test {abs(a - b) / abs(a):.2e}')
+    assert abs(a - b) / abs(a) < 1e-5
+    plan.close()
+
+
+def test_operator_parity_config4_full_size_sampled():
+    """All 256 uneven gathers on the GPU; sampled traces and model rows checked by the oracle."""
+    w = wl.config4(with_data=False)
+    plan = make_plan(w)
+    gsall = geoms(w)
+    assert plan.info['nfft'] == gsall[0].nfft == 4320
+    m = wl.random_model(w.axes, w.batch, 21)
+    d = wl.random_data(plan.ntraces, w.axes.nt, 21)
+    got_d = to_host(plan.forward(to_dev(m)))
+    got_m = to_host(plan.adjoint(to_dev(d)))
+    tp = w.trace_ptr
+    folds = np.diff(tp)
+    rng = np.random.default_rng(0)
+    picks = sorted({int(np.argmin(folds)), int(np.argmax(folds)), int(rng.integers(w.batch)), 255})
+    for b in picks:
+        g = gsall[b]
+        idx = sorted(rng.choice(g.x.size, 4, replace=False))
+        ref = gfst.forward_traces(m[b], g, idx)
+        ef = rel(got_d[tp[b] + np.array(idx)], ref)
+        rows = [(int(rng.integers(g.ntheta)), int(rng.integers(g.nq))) for _ in range(3)]
+        refm = gfst.adjoint(d[tp[b]:tp[b + 1]], g, rows=rows)
+        ea = rel(np.stack([got_m[b, j, l] for j, l in rows]), refm)
+        print(f'gather {b} fold {folds[b]}: forward {ef:.2e} adjoint {ea:.2e}')
+        assert ef < TOL and ea < TOL
+    plan.close()
+
+
+# ------------------------------------------------------------------ solver
+def test_lambda_and_norm_match_oracle_config1():
+    w = wl.config1(with_data=True)
+    g = geoms(w)[0]
+    d = w.gathers[0].data
+    lam, gam, n2 = oracle_solver_params(g, d)
+    plan = make_plan(w)
+    lmax = to_host(plan.lambda_max(to_dev(d)))[0]
+    assert abs(0.05 * lmax - lam) / lam < 1e-4
+    gn2 = to_host(plan.operator_norm2(60))[0]
+    print(f'norm2 gpu {gn2:.6e} oracle {n2:.6e}')
+    assert abs(gn2 - n2) / n2 < 2e-3
+    plan.close()
+
+
+def _fista_parity(w, n_iter, ista=False, check_objective=False):
+    import torch
+    gs = geoms(w)
+    plan = make_plan(w)
+    ds = [g.data for g in w.gathers]
+    lams, gams = [], []
+    for g, d in zip(gs, ds):
+        lam, gam, _ = oracle_solver_params(g, d)
+        lams.append(lam)
+        gams.append(gam)
+    dall = np.concatenate(ds, axis=0)
+    x, obj = plan.sparse_solve(to_dev(dall), n_iter, lam=to_dev(np.array(lams)), step=to_dev(np.array(gams)),
+                               ista=ista, objective=check_objective)
+    x = to_host(x)
+    errs = []
+    for b, (g, d) in enumerate(zip(gs, ds)):
+        L = lambda v, g=g: gfst.forward(v, g)
+        Lt = lambda v, g=g: gfst.adjoint(v, g)
+        ref = fista.solve(L, Lt, d, lams[b], gams[b], n_iter, momentum=not ista)
+        errs.append(rel(x[b], ref))
+    plan.close()
+    return errs, (to_host(obj) if obj is not None else None)
+
+
+def test_fista_parity_config1_20_iterations():
+    errs, _ = _fista_parity(wl.config1(), 20)
+    print('fista config1', errs)
+    assert errs[0] < TOL
+
+
+def test_ista_parity_config1():
+    errs, _ = _fista_parity(wl.config1(), 8, ista=True)
+    assert errs[0] < TOL
+
+
+def test_fista_parity_config3_batch():
+    errs, _ = _fista_parity(wl.config3(), 10)
+    print('fista config3', [f'{e:.1e}' for e in errs])
+    assert max(errs) < TOL
+
+
+def test_solver_defaults_zero_lambda_rule():
+    """lambda >= max|L^T d| gives m = 0 (exact) with the library's own step."""
+    import torch
+    w = wl.config1()
+    plan = make_plan(w)
+    d = to_dev(w.gathers[0].data)
+    lm = plan.lambda_max(d) * 1.001
+    x, _ = plan.sparse_solve(d, 5, lam=lm)
+    assert torch.count_nonzero(x).item() == 0
+    plan.close()
