@@ -1,0 +1,231 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched sparse AAHRT on one MI355X.
+
+A step is one 100-iteration FISTA solve of the whole batch: the lambda rule
+(one L^T pass and a per-gather max) plus 100 iterations of {L, residual, L^T,
+shrinkage + momentum}.  The workload is 256 CMP gathers of uneven fold (200 to
+1200 traces in a 3 km disk), nt = 1024 at 2 ms, nq = 64, ntheta = 16, seeded
+synthetic data (elliptical-moveout Ricker events plus noise).  The step length
+gamma_b = 1/(1.05 ||L_b||^2) depends only on the geometry, so it is computed
+once per plan (30 power iterations) and reported as setup, like the plan.
+
+Prints one JSON line: metric, value (gathers/s), ms per step, the roofline of
+the dominant kernel (algorithmic bytes per launch / its mean HIP-event time),
+fwd+adj gather-pairs/s, per-kernel times, and the FP64 oracle timed on host
+cores on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_bytes(plan, name: str) -> float:
+    """Algorithmic HBM bytes of one launch of a kernel over the plan's batch."""
+    a = plan.axes
+    B, ntr, nf = plan.batch, plan.ntraces, plan.info['nfreq']
+    rows = B * a.ntheta * a.nq
+    return {
+        'model_r2c': rows * (4 * a.ntau + 8 * nf),
+        'nufft_interp': rows * 8 * nf + ntr * 8 * nf,
+        'data_c2r': ntr * (8 * nf + 4 * a.nt),
+        'data_r2c': ntr * (4 * a.nt + 8 * nf),
+        'nufft_spread': ntr * 8 * nf + rows * 8 * nf,
+        'model_c2r': rows * (8 * nf + 4 * a.ntau),
+        'residual_r2c': ntr * (16 * nf + 4 * a.nt),
+        'model_c2r_update': rows * (8 * nf + 16 * a.ntau),
+    }[name]
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ('kernels.hip', 'fft_lds.hpp', 'aahrt_internal.hpp'):
+        with open(os.path.join(ROOT, 'paper_2505_00387_amd', 'csrc', f), 'rb') as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if taken on this kernel source."""
+    path = os.path.join(ROOT, 'profiles', 'hbm_counters.json')
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except Exception:
+        return None
+    if rec.get('source_hash') != source_hash() or rec.get('workload') != workload:
+        return None
+    k = rec.get('kernels', {}).get(kernel)
+    return None if k is None else k.get('bytes_per_launch')
+
+
+def cpu_baseline(w, sample_gather: int):
+    """FP64 oracle, one FISTA iteration on one gather, scaled to a 100-iteration solve."""
+    import numpy as np
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:  # pragma: no cover
+        threadpool_limits = None
+    from oracle import gfst, fista
+    from oracle.geometry import Geometry
+    h2max = max(float(np.max(g.x ** 2 + g.y ** 2)) for g in w.gathers)
+    g0 = w.gathers[sample_gather]
+    geom = Geometry.build(w.axes, g0.x, g0.y, h2max=h2max)
+    d = g0.data
+    L = lambda v: gfst.forward(v, geom)
+    Lt = lambda v: gfst.adjoint(v, geom)
+    ctx = threadpool_limits(1) if threadpool_limits else None
+    try:
+        if ctx:
+            ctx.__enter__()
+        t0 = time.perf_counter()
+        fista.solve(L, Lt, d, 1.0, 1e-3, 1)        # L, L^T and the update of one iteration
+        t_iter = time.perf_counter() - t0
+    finally:
+        if ctx:
+            ctx.__exit__(None, None, None)
+    t_solve = w.n_iter * t_iter + 0.5 * t_iter       # + lambda rule (one L^T pass)
+    return {'value': 1.0 / t_solve, 'unit': 'gathers/s', 'cores': 1, 'kind': 'oracle',
+            'sample': f'one FISTA iteration (L + L^T + shrinkage, FP64 NumPy, 1 thread) on gather '
+                      f'{sample_gather} (fold {g0.x.size}, the median) took {t_iter:.2f} s; '
+                      f'scaled to {w.n_iter} iterations + lambda rule per gather'}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument('--gpus', type=int, default=1)
+    ap.add_argument('--steps', type=int, default=3)
+    ap.add_argument('--warmup', type=int, default=1)
+    ap.add_argument('--iters', type=int, default=0, help='FISTA iterations per solve (0: workload default, 100)')
+    ap.add_argument('--no-cpu', action='store_true', help='skip the oracle CPU-baseline leg')
+    ap.add_argument('--pairs', type=int, default=5, help='timed fwd+adj pairs')
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print('bench.py runs on one GPU only: the batched solve shards by gather, and this build '
+              'measures one GPU\'s share (use --gpus 1).', file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import workloads as wl
+    from paper_2505_00387_amd import plan_from_workload
+
+    assert torch.cuda.is_available(), 'bench.py needs a GPU'
+    dev = torch.device('cuda:0')
+    t0 = time.perf_counter()
+    w = wl.config4(with_data=True)
+    t_gen = time.perf_counter() - t0
+    n_iter = args.iters or w.n_iter
+    print(f'# workload {w.name}: {w.batch} gathers, {int(w.trace_ptr[-1])} traces, generated in {t_gen:.1f} s',
+          file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    plan = plan_from_workload(w, device=0)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    d = torch.tensor(w.data_all(), dtype=torch.float32, device=dev)
+    m = torch.zeros(plan.model_shape, dtype=torch.float32, device=dev)
+
+    t0 = time.perf_counter()
+    n2 = plan.operator_norm2(30)
+    gam = (1.0 / (1.05 * n2)).contiguous()
+    torch.cuda.synchronize()
+    t_power = time.perf_counter() - t0
+    print(f'# plan {t_plan:.2f} s, power iteration {t_power:.2f} s, info {plan.info}', file=sys.stderr, flush=True)
+
+    def step():
+        m.zero_()
+        plan.sparse_solve(d, n_iter, m=m, step=gam, graph=False)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+        torch.cuda.synchronize()
+        print(f'# step {i + 1}/{args.steps} done at {time.perf_counter() - t0:.2f} s', file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = plan.profile_read()
+    plan.profile(False)
+    ms_step = 1000.0 * elapsed / args.steps
+    gathers_per_s = w.batch / (elapsed / args.steps)
+
+    # forward + adjoint pairs over the batch
+    mr = torch.randn(plan.model_shape, dtype=torch.float32, device=dev)
+    dd = torch.empty(plan.data_shape, dtype=torch.float32, device=dev)
+    ma = torch.empty(plan.model_shape, dtype=torch.float32, device=dev)
+    plan.forward(mr, dd)
+    plan.adjoint(dd, ma)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.pairs):
+        plan.forward(mr, dd)
+        plan.adjoint(dd, ma)
+    torch.cuda.synchronize()
+    t_pair = (time.perf_counter() - t0) / args.pairs
+    pairs_per_s = w.batch / t_pair
+    a = w.axes
+    nf = plan.info['nfreq']
+    rows = w.batch * a.ntheta * a.nq
+    bop = 4 * rows * a.ntau + 16 * rows * nf + 16 * plan.ntraces * nf + 4 * plan.ntraces * a.nt
+    pair_gbs = 2 * bop / t_pair / 1e9
+
+    kernels = {}
+    for name, (ms, n) in prof.items():
+        if n == 0:
+            continue
+        avg = ms / n
+        byt = kernel_bytes(plan, name)
+        kernels[name] = {'launches': n, 'avg_ms': round(avg, 4), 'total_ms': round(ms, 2),
+                         'alg_GBs': round(byt / (avg * 1e-3) / 1e9, 1)}
+    dom = max(kernels, key=lambda k: kernels[k]['total_ms'])
+    avg = kernels[dom]['avg_ms']
+    ach = kernel_bytes(plan, dom) / (avg * 1e-3) / 1e9
+    traffic = load_traffic(dom, w.name)
+    roofline = {'bound': 'hbm', 'achieved': round(ach, 1), 'peak': HBM_PEAK_GBS, 'unit': 'GB/s',
+                'frac': round(ach / HBM_PEAK_GBS, 4), 'traffic': traffic, 'kernel': dom,
+                'alg_bytes_per_launch': int(kernel_bytes(plan, dom)), 'avg_ms': avg}
+
+    cpu = None
+    if not args.no_cpu:
+        folds = np.diff(w.trace_ptr)
+        med = int(np.argsort(folds)[len(folds) // 2])
+        print('# timing the FP64 oracle on one gather (about 20-30 s)', file=sys.stderr, flush=True)
+        cpu = cpu_baseline(w, med)
+
+    out = {
+        'metric': 'CMP gathers/s, 100-iter sparse AAHRT at <=1e-4 rel err',
+        'value': round(gathers_per_s, 2), 'unit': 'gathers/s', 'n_gpus': 1, 'steps': args.steps,
+        'warmup': args.warmup, 'ms_per_step': round(ms_step, 2), 'higher_is_better': True,
+        'scaling': 'weak', 'vs_baseline': None, 'dtype': 'f32', 'data': 'synthetic',
+        'config': {'workload': w.name, 'gathers': w.batch, 'traces': plan.ntraces, 'nt': a.nt,
+                   'nq': a.nq, 'ntheta': a.ntheta, 'fista_iters': n_iter, 'nfft': plan.info['nfft'],
+                   'kernel_width': plan.info['kernel_width'], 'grid': plan.info['grid_size'],
+                   'freq_tile': plan.info['freq_tile']},
+        'roofline': roofline,
+        'cpu_baseline': cpu,
+        'secondary': {'fwd_adj_pairs_per_s': round(pairs_per_s, 1), 'fwd_adj_pair_ms': round(1e3 * t_pair, 3),
+                      'fwd_adj_alg_GBs': round(pair_gbs, 1), 'setup_plan_s': round(t_plan, 3),
+                      'setup_power_iteration_s': round(t_power, 3)},
+        'kernels': kernels,
+    }
+    print(json.dumps(out), flush=True)
+    plan.close()
+
+
+if __name__ == '__main__':
+    main()

@@ -184,6 +184,35 @@ int aahrt_sparse_solve(aahrt_plan* plan, const float* d, float* m, const float* 
                        const float* step, int32_t n_iter, int32_t flags, float* objective,
                        aahrt_stream stream);
 
+/* Kernels of the library, for per-kernel timing. */
+typedef enum {
+  AAHRT_K_MODEL_R2C = 0,        /* model rows: stretch S, deapodise, real DFT along tau' (L steps 1-2) */
+  AAHRT_K_NUFFT_INTERP = 1,     /* GFST map: q-grid FFT + kernel interpolation + azimuth weights (L step 3) */
+  AAHRT_K_DATA_C2R = 2,         /* traces: inverse real DFT, unstretch (L steps 4-5) */
+  AAHRT_K_DATA_R2C = 3,         /* traces: unstretch transpose, real DFT (L^T) */
+  AAHRT_K_NUFFT_SPREAD = 4,     /* transpose of the GFST map: spreading + inverse q-grid FFT (L^T) */
+  AAHRT_K_MODEL_C2R = 5,        /* model rows: inverse real DFT, stretch transpose (L^T) */
+  AAHRT_K_RESIDUAL_R2C = 6,     /* solver: residual d - L y fused with the data side of L^T */
+  AAHRT_K_MODEL_C2R_UPDATE = 7, /* solver: model side of L^T fused with shrinkage + momentum */
+  AAHRT_K_COUNT = 8
+} aahrt_kernel_id;
+
+/*
+ * Per-kernel timing (Section 5 reports wall-clock cost; this splits it per kernel).
+ * enable = 1 records a HIP event pair on the launch stream around every kernel of the
+ * kinds above (up to 8192 launches between reads) and clears the totals; 0 stops recording.
+ * Recording is for eager calls (AAHRT_SOLVE_NO_GRAPH for the solver).
+ */
+int aahrt_profile_enable(aahrt_plan* plan, int32_t enable);
+
+/*
+ * Accumulated time of one kernel kind since the last enable: waits for the recorded
+ * events, adds their durations, then reports the totals.
+ *   total_ms : host double, milliseconds summed over launches
+ *   launches : host int64, number of timed launches
+ */
+int aahrt_profile_read(aahrt_plan* plan, int32_t kernel, double* total_ms, int64_t* launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -131,6 +131,19 @@ class Plan:
         check(self._lib.aahrt_operator_norm2(self._h, int(n_iter), out.data_ptr(), _stream(stream)))
         return out
 
+    def profile(self, enable: bool = True):
+        check(self._lib.aahrt_profile_enable(self._h, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        """{kernel name: (total ms, launches)} since the last profile(True)."""
+        out = {}
+        for k, name in enumerate(_lib.KERNELS):
+            ms = ctypes.c_double()
+            n = ctypes.c_int64()
+            check(self._lib.aahrt_profile_read(self._h, k, ctypes.byref(ms), ctypes.byref(n)))
+            out[name] = (ms.value, n.value)
+        return out
+
     def sparse_solve(self, d, n_iter, m=None, lam=None, step=None, ista=False, graph=True,
                      objective=False, stream=None):
         """FISTA (or ISTA) sparse AAHRT; returns (m, objective or None)."""

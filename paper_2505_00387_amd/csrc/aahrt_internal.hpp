@@ -104,6 +104,13 @@ struct Plan {
   // host copies
   std::vector<int64_t> trace_ptr;
   std::vector<int> h_bin_ptr;
+  // per-kernel timing
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<int> ev_kind;      // kernel id of each recorded pair
+  double prof_ms[AAHRT_K_COUNT] = {0};
+  int64_t prof_n[AAHRT_K_COUNT] = {0};
   // cached graph of the solver
   hipGraphExec_t graph_exec = nullptr;
   hipGraph_t graph = nullptr;

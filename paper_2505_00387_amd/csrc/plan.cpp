@@ -160,6 +160,7 @@ int alloc(Plan& p, size_t count, T** out) {
 
 void free_plan(Plan* p) {
   if (!p) return;
+  for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
   if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   for (void* a : p->allocations) (void)hipFree(a);
@@ -417,17 +418,54 @@ int check_plan(const aahrt_plan* plan) {
 const Plan& P_of(const aahrt_plan* p) { return *reinterpret_cast<const Plan*>(p); }
 Plan& P_of(aahrt_plan* p) { return *reinterpret_cast<Plan*>(p); }
 
+constexpr size_t kEventPairs = 8192;
+
+// Event pair around one kernel launch when timing is on.
+struct ProfScope {
+  Plan& P;
+  hipStream_t s;
+  int pair = -1;
+  ProfScope(Plan& p, int kind, hipStream_t st) : P(p), s(st) {
+    if (P.prof && P.ev_used < kEventPairs) {
+      pair = (int)P.ev_used++;
+      P.ev_kind[pair] = kind;
+      (void)hipEventRecord(P.ev_pool[2 * pair], s);
+    }
+  }
+  ~ProfScope() {
+    if (pair >= 0) (void)hipEventRecord(P.ev_pool[2 * pair + 1], s);
+  }
+};
+
+int drain_profile(Plan& P) {
+  for (size_t i = 0; i < P.ev_used; ++i) {
+    HIP_TRY(hipEventSynchronize(P.ev_pool[2 * i + 1]));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, P.ev_pool[2 * i], P.ev_pool[2 * i + 1]));
+    P.prof_ms[P.ev_kind[i]] += ms;
+    P.prof_n[P.ev_kind[i]] += 1;
+  }
+  P.ev_used = 0;
+  return AAHRT_OK;
+}
+
+#define KCALL(KIND, expr)                  \
+  do {                                     \
+    ProfScope ps_(P, KIND, s);             \
+    HIP_TRY(expr);                         \
+  } while (0)
+
 int do_forward(Plan& P, const float* m, float* d, hipStream_t s) {
-  HIP_TRY(launch_model_r2c(P, m, P.mhat, s));
-  HIP_TRY(launch_nufft_interp(P, P.mhat, P.dhat, s));
-  HIP_TRY(launch_data_c2r(P, P.dhat, d, s));
+  KCALL(AAHRT_K_MODEL_R2C, launch_model_r2c(P, m, P.mhat, s));
+  KCALL(AAHRT_K_NUFFT_INTERP, launch_nufft_interp(P, P.mhat, P.dhat, s));
+  KCALL(AAHRT_K_DATA_C2R, launch_data_c2r(P, P.dhat, d, s));
   return AAHRT_OK;
 }
 
 int do_adjoint(Plan& P, const float* d, float* m, hipStream_t s) {
-  HIP_TRY(launch_data_r2c(P, d, P.dhat, s));
-  HIP_TRY(launch_nufft_spread(P, P.dhat, P.mhat, s));
-  HIP_TRY(launch_model_c2r(P, P.mhat, m, s));
+  KCALL(AAHRT_K_DATA_R2C, launch_data_r2c(P, d, P.dhat, s));
+  KCALL(AAHRT_K_NUFFT_SPREAD, launch_nufft_spread(P, P.dhat, P.mhat, s));
+  KCALL(AAHRT_K_MODEL_C2R, launch_model_c2r(P, P.mhat, m, s));
   return AAHRT_OK;
 }
 
@@ -472,12 +510,13 @@ int enqueue_iterations(Plan& P, const float* d, float* m, int n_iter, bool ista,
                        hipStream_t s) {
   const std::vector<double> betas = fista_betas(n_iter, ista);
   for (int k = 0; k < n_iter; ++k) {
-    HIP_TRY(launch_model_r2c(P, P.ybuf, P.mhat, s));
-    HIP_TRY(launch_nufft_interp(P, P.mhat, P.dhat, s));
-    HIP_TRY(launch_residual_r2c(P, P.dhat, d, objective ? P.rss : nullptr, s));
-    HIP_TRY(launch_nufft_spread(P, P.dhat, P.mhat, s));
-    HIP_TRY(launch_model_c2r_update(P, P.mhat, P.ybuf, m, P.gam, P.lam, (float)betas[k], ista ? 1 : 0,
-                                    objective ? P.l1row : nullptr, s));
+    KCALL(AAHRT_K_MODEL_R2C, launch_model_r2c(P, P.ybuf, P.mhat, s));
+    KCALL(AAHRT_K_NUFFT_INTERP, launch_nufft_interp(P, P.mhat, P.dhat, s));
+    KCALL(AAHRT_K_RESIDUAL_R2C, launch_residual_r2c(P, P.dhat, d, objective ? P.rss : nullptr, s));
+    KCALL(AAHRT_K_NUFFT_SPREAD, launch_nufft_spread(P, P.dhat, P.mhat, s));
+    KCALL(AAHRT_K_MODEL_C2R_UPDATE,
+          launch_model_c2r_update(P, P.mhat, P.ybuf, m, P.gam, P.lam, (float)betas[k], ista ? 1 : 0,
+                                  objective ? P.l1row : nullptr, s));
     if (objective)
       HIP_TRY(launch_objective(P, P.rss, P.trace_ptr_dev, P.l1row, P.lam,
                                objective + (size_t)k * P.dm.batch, s));
@@ -616,6 +655,33 @@ int aahrt_sparse_solve(aahrt_plan* plan, const float* d, float* m, const float* 
   }
   HIP_TRY(launch_copy(P.ybuf, m, model, s));
   return enqueue_iterations(P, d, m, n_iter, ista, objective, s);
+}
+
+int aahrt_profile_enable(aahrt_plan* plan, int32_t enable) {
+  TRY(check_plan(plan));
+  Plan& P = P_of(plan);
+  HIP_TRY(hipSetDevice(P.device));
+  if (enable && P.ev_pool.empty()) {
+    P.ev_pool.resize(2 * kEventPairs);
+    P.ev_kind.assign(kEventPairs, 0);
+    for (auto& e : P.ev_pool) HIP_TRY(hipEventCreate(&e));
+  }
+  if (P.ev_used) TRY(drain_profile(P));
+  for (int k = 0; k < AAHRT_K_COUNT; ++k) { P.prof_ms[k] = 0.0; P.prof_n[k] = 0; }
+  P.prof = enable != 0;
+  return AAHRT_OK;
+}
+
+int aahrt_profile_read(aahrt_plan* plan, int32_t kernel, double* total_ms, int64_t* launches) {
+  TRY(check_plan(plan));
+  if (kernel < 0 || kernel >= AAHRT_K_COUNT) return fail(AAHRT_E_INVALID, "kernel id out of range");
+  if (!total_ms || !launches) return fail(AAHRT_E_INVALID, "output pointer is NULL");
+  Plan& P = P_of(plan);
+  HIP_TRY(hipSetDevice(P.device));
+  TRY(drain_profile(P));
+  *total_ms = P.prof_ms[kernel];
+  *launches = P.prof_n[kernel];
+  return AAHRT_OK;
 }
 
 }  // extern "C"

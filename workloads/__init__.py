@@ -105,14 +105,23 @@ def _event_matrix(rng, p_lo, p_hi):
 
 
 def synth_data(axes: Axes, x, y, events, snr: Optional[float], rng) -> np.ndarray:
-    """Sum of Ricker events on t^2 = tau0^2 + h^T W h, plus noise at the given SNR."""
-    t = np.arange(axes.nt) * axes.dt
+    """Sum of Ricker events on t^2 = tau0^2 + h^T W h, plus noise at the given SNR.
+
+    Each wavelet is evaluated on the samples within 1.6/f0 of its arrival time (its
+    amplitude there is below 1e-11 of the peak) and is zero elsewhere.
+    """
     d = np.zeros((x.size, axes.nt))
     h = np.stack([x, y], axis=1)
+    rows = np.arange(x.size)[:, None]
     for ev in events:
         hw = np.einsum('ni,ij,nj->n', h, ev['W'], h)
         tev = np.sqrt(ev['tau0'] ** 2 + hw)
-        d += ev['amp'] * ricker(t[None, :] - tev[:, None], ev['f0'])
+        half = int(np.ceil(1.6 / (ev['f0'] * axes.dt)))
+        idx = np.rint(tev / axes.dt).astype(np.int64)[:, None] + np.arange(-half, half + 1)[None, :]
+        ok = (idx >= 0) & (idx < axes.nt)
+        vals = ev['amp'] * ricker(idx * axes.dt - tev[:, None], ev['f0'])
+        rr = np.broadcast_to(rows, idx.shape)
+        d[rr[ok], idx[ok]] += vals[ok]
     if snr is not None and d.size:
         rms = np.sqrt(np.mean(d * d))
         d += rng.standard_normal(d.shape) * (rms / snr)
