@@ -11,18 +11,27 @@
 
 namespace aahrt {
 
-constexpr int kMaxRadices = 24;
-constexpr int kBlock = 256;  // threads per workgroup for every kernel
+constexpr int kMaxPasses = 12;
+constexpr int kBlock = 256;     // threads per workgroup of the row kernels and small kernels
+constexpr int kBlockG = 512;    // threads per workgroup of the GFST (nonuniform FFT) kernels
+constexpr int kStageTraces = 64;  // traces staged in LDS per chunk in the GFST kernels
 
-// Largest butterflies-per-thread count instantiated for each radix (keeps the
-// register array of one pass at <= 40 complex values).
-__host__ __device__ constexpr int fft_max_bpt(int R) { return R == 2 ? 16 : (R == 8 ? 4 : 8); }
+// x / d = (umulhi(x, m) + x) >> s for 0 <= x < 2^31 (d = 1: x).
+struct FastDiv {
+  unsigned d, m, s;
+};
 
-// Radix schedule of an LDS Stockham FFT (radices 2, 3, 4, 5, 8).
+// One Stockham pass: radix r, nb = n/r butterflies per sequence, ns = product of
+// the earlier radices, stride = n/(ns*r) into the twiddle table.
+struct FftPass {
+  int r, nb, ns, stride;
+  FastDiv dnb, dns;
+};
+
 struct FftPlan {
   int n;
-  int nrad;
-  int rad[kMaxRadices];
+  int npass;
+  FftPass pass[kMaxPasses];
 };
 
 // Device tables of one plan.  Per-trace arrays are stored in "bin order":

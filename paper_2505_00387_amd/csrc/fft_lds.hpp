@@ -1,11 +1,11 @@
-// Batched complex FFTs held in LDS, Stockham autosort, radices 2/3/4/5/8.
+// Batched complex FFTs in LDS: Stockham autosort, radices 2/3/4/5/8/16.
 //
-// One workgroup of kBlock threads transforms `nbatch` sequences of length n
-// stored at buf + b*bstride.  Each pass loads every butterfly's R inputs into
-// registers, synchronises, then writes the R outputs in autosort order, so a
-// single LDS buffer is transformed in place.  Twiddles come from a table
-// tw[t] = exp(-2 pi i t/n) built in FP64 on the host.  INV selects the sign
-// +i (unnormalised inverse).
+// A workgroup of NT threads transforms `nbatch` sequences of length n stored at
+// buf + b*bstride.  Passes alternate between two LDS buffers (ping-pong), so a
+// butterfly is loaded, transformed and stored without holding other
+// butterflies in registers.  Twiddles come from a table tw[t] = exp(-2 pi i t/n)
+// built in FP64 on the host; INV selects the +i sign (unnormalised inverse).
+// Index arithmetic uses host-built multiply-shift division constants.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -24,6 +24,21 @@ __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2
 template <bool INV>
 __device__ __forceinline__ float2 mul_i(float2 a) {
   return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+// multiply by exp(-+ i pi/4) and exp(-+ 3 i pi/4)
+template <bool INV>
+__device__ __forceinline__ float2 mul_w8(float2 a) {
+  const float r = 0.70710678118654752440f;
+  return INV ? make_float2(r * (a.x - a.y), r * (a.x + a.y)) : make_float2(r * (a.x + a.y), r * (a.y - a.x));
+}
+template <bool INV>
+__device__ __forceinline__ float2 mul_w8_3(float2 a) {
+  const float r = 0.70710678118654752440f;
+  return INV ? make_float2(-r * (a.x + a.y), r * (a.x - a.y)) : make_float2(r * (a.y - a.x), -r * (a.x + a.y));
+}
+
+__device__ __forceinline__ unsigned fdiv(unsigned x, const FastDiv& d) {
+  return d.d == 1 ? x : (__umulhi(x, d.m) + x) >> d.s;
 }
 
 template <int R, bool INV>
@@ -93,18 +108,9 @@ struct Dft<8, INV> {
     float2 o[4] = {v[1], v[3], v[5], v[7]};
     Dft<4, INV>::run(e);
     Dft<4, INV>::run(o);
-    const float r = 0.70710678118654752440f;
-    float2 o1 = o[1], o2 = o[2], o3 = o[3];
-    float2 w1, w2, w3;
-    if (!INV) {
-      w1 = make_float2(r * (o1.x + o1.y), r * (o1.y - o1.x));
-      w2 = make_float2(o2.y, -o2.x);
-      w3 = make_float2(r * (o3.y - o3.x), -r * (o3.x + o3.y));
-    } else {
-      w1 = make_float2(r * (o1.x - o1.y), r * (o1.x + o1.y));
-      w2 = make_float2(-o2.y, o2.x);
-      w3 = make_float2(-r * (o3.x + o3.y), r * (o3.x - o3.y));
-    }
+    const float2 w1 = mul_w8<INV>(o[1]);
+    const float2 w2 = mul_i<INV>(o[2]);
+    const float2 w3 = mul_w8_3<INV>(o[3]);
     v[0] = cadd(e[0], o[0]);
     v[4] = csub(e[0], o[0]);
     v[1] = cadd(e[1], w1);
@@ -116,83 +122,95 @@ struct Dft<8, INV> {
   }
 };
 
-// One Stockham pass of radix R; MAXB butterflies per thread at most.
-template <int R, int MAXB, bool INV>
-__device__ __forceinline__ void fft_pass(float2* buf, int n, int nbatch, int bstride, int Ns,
-                                         const float2* __restrict__ tw) {
-  const int nb = n / R;
-  const int total = nb * nbatch;
-  const int stride = n / (Ns * R);
-  float2 v[MAXB][R];
-  int jj[MAXB], bb[MAXB];
-#pragma unroll
-  for (int t = 0; t < MAXB; ++t) {
-    const int b = threadIdx.x + t * kBlock;
-    jj[t] = -1;
-    bb[t] = 0;
-    if (b < total) {
-      const int fb = b / nb;
-      const int j = b - fb * nb;
-      jj[t] = j;
-      bb[t] = fb;
-      const float2* x = buf + fb * bstride + j;
-#pragma unroll
-      for (int r = 0; r < R; ++r) v[t][r] = x[r * nb];
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int t = 0; t < MAXB; ++t) {
-    const int j = jj[t];
-    if (j >= 0) {
-      const int k = j % Ns;
-      if (Ns > 1) {
-#pragma unroll
-        for (int r = 1; r < R; ++r) {
-          float2 w = tw[r * k * stride];
-          if (INV) w.y = -w.y;
-          v[t][r] = cmul(v[t][r], w);
-        }
-      }
-      Dft<R, INV>::run(v[t]);
-      float2* y = buf + bb[t] * bstride + (j - k) * R + k;
-#pragma unroll
-      for (int r = 0; r < R; ++r) y[r * Ns] = v[t][r];
-    }
-  }
-  __syncthreads();
-}
-
-template <int R, bool INV>
-__device__ __forceinline__ void fft_pass_dispatch(float2* buf, int n, int nbatch, int bstride,
-                                                  int Ns, const float2* tw) {
-  const int total = (n / R) * nbatch;
-  const int mb = (total + kBlock - 1) / kBlock;
-  if (mb <= 1) fft_pass<R, 1, INV>(buf, n, nbatch, bstride, Ns, tw);
-  else if (mb <= 2) fft_pass<R, 2, INV>(buf, n, nbatch, bstride, Ns, tw);
-  else if (mb <= 4) fft_pass<R, 4, INV>(buf, n, nbatch, bstride, Ns, tw);
-  else if constexpr (fft_max_bpt(R) >= 8) {
-    if (mb <= 8) fft_pass<R, 8, INV>(buf, n, nbatch, bstride, Ns, tw);
-    else if constexpr (fft_max_bpt(R) >= 16) fft_pass<R, 16, INV>(buf, n, nbatch, bstride, Ns, tw);
-  }
-}
-
-// Full transform; the caller synchronises before the first pass.
+// 16 = 4 x 4: DFT-4 over stride-4 inputs, twiddles W16^(a k1), DFT-4 across.
 template <bool INV>
-__device__ void fft_lds(float2* buf, const FftPlan& pl, int nbatch, int bstride,
-                        const float2* __restrict__ tw) {
-  int Ns = 1;
-  for (int s = 0; s < pl.nrad; ++s) {
-    const int R = pl.rad[s];
-    switch (R) {
-      case 2: fft_pass_dispatch<2, INV>(buf, pl.n, nbatch, bstride, Ns, tw); break;
-      case 3: fft_pass_dispatch<3, INV>(buf, pl.n, nbatch, bstride, Ns, tw); break;
-      case 4: fft_pass_dispatch<4, INV>(buf, pl.n, nbatch, bstride, Ns, tw); break;
-      case 5: fft_pass_dispatch<5, INV>(buf, pl.n, nbatch, bstride, Ns, tw); break;
-      default: fft_pass_dispatch<8, INV>(buf, pl.n, nbatch, bstride, Ns, tw); break;
+struct Dft<16, INV> {
+  __device__ __forceinline__ static void run(float2* v) {
+    const float c = 0.92387953251128675613f, s = 0.38268343236508977173f;
+    float2 sub[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b) sub[a][b] = v[a + 4 * b];
+      Dft<4, INV>::run(sub[a]);
     }
-    Ns *= R;
+    // twiddle W16^(a*k1): a = 1: k1 = 1,2,3 -> W^1, W^2, W^3; a = 2: W^2, W^4, W^6; a = 3: W^3, W^6, W^9
+    const float sg = INV ? 1.f : -1.f;
+    const float2 w1 = make_float2(c, sg * s), w3 = make_float2(s, sg * c);
+    sub[1][1] = cmul(sub[1][1], w1);
+    sub[1][2] = mul_w8<INV>(sub[1][2]);
+    sub[1][3] = cmul(sub[1][3], w3);
+    sub[2][1] = mul_w8<INV>(sub[2][1]);
+    sub[2][2] = mul_i<INV>(sub[2][2]);
+    sub[2][3] = mul_w8_3<INV>(sub[2][3]);
+    sub[3][1] = cmul(sub[3][1], w3);
+    sub[3][2] = mul_w8_3<INV>(sub[3][2]);
+    sub[3][3] = cmul(sub[3][3], make_float2(-c, -sg * s));  // W^9 = -W^1
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      float2 t[4] = {sub[0][k1], sub[1][k1], sub[2][k1], sub[3][k1]};
+      Dft<4, INV>::run(t);
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[k2];
+    }
   }
+};
+
+// One out-of-place Stockham pass of radix R.
+template <int R, bool INV, int NT>
+__device__ __forceinline__ void fft_pass(const float2* __restrict__ src, float2* __restrict__ dst,
+                                         const FftPass& ps, int nbatch, int bstride,
+                                         const float2* __restrict__ tw) {
+  const int nb = ps.nb;
+  const int total = nb * nbatch;
+  for (int b = threadIdx.x; b < total; b += NT) {
+    const int fb = (int)fdiv((unsigned)b, ps.dnb);
+    const int j = b - fb * nb;
+    const int jq = (int)fdiv((unsigned)j, ps.dns);
+    const int k = j - jq * ps.ns;
+    float2 v[R];
+    const float2* x = src + fb * bstride + j;
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = x[r * nb];
+    if (ps.ns > 1) {
+      const int step = k * ps.stride;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        float2 w = tw[r * step];
+        if (INV) w.y = -w.y;
+        v[r] = cmul(v[r], w);
+      }
+    }
+    Dft<R, INV>::run(v);
+    float2* y = dst + fb * bstride + jq * ps.ns * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) y[r * ps.ns] = v[r];
+  }
+  __syncthreads();
+}
+
+// Full transform of the data in `a` (the caller synchronises before calling).
+// Returns the buffer (a or b) holding the result.
+template <bool INV, int NT>
+__device__ float2* fft_lds(float2* a, float2* b, const FftPlan& pl, int nbatch, int bstride,
+                           const float2* __restrict__ tw) {
+  float2* src = a;
+  float2* dst = b;
+  for (int s = 0; s < pl.npass; ++s) {
+    const FftPass& ps = pl.pass[s];
+    switch (ps.r) {
+      case 2: fft_pass<2, INV, NT>(src, dst, ps, nbatch, bstride, tw); break;
+      case 3: fft_pass<3, INV, NT>(src, dst, ps, nbatch, bstride, tw); break;
+      case 4: fft_pass<4, INV, NT>(src, dst, ps, nbatch, bstride, tw); break;
+      case 5: fft_pass<5, INV, NT>(src, dst, ps, nbatch, bstride, tw); break;
+      case 8: fft_pass<8, INV, NT>(src, dst, ps, nbatch, bstride, tw); break;
+      default: fft_pass<16, INV, NT>(src, dst, ps, nbatch, bstride, tw); break;
+    }
+    float2* t = src;
+    src = dst;
+    dst = t;
+  }
+  return src;
 }
 
 }  // namespace aahrt

@@ -16,6 +16,7 @@
 namespace aahrt {
 
 // ------------------------------------------------------------------ helpers
+template <int NT>
 __device__ __forceinline__ float block_sum(float v, float* red) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
@@ -25,11 +26,12 @@ __device__ __forceinline__ float block_sum(float v, float* red) {
   __syncthreads();
   float s = 0.f;
   if (threadIdx.x == 0) {
-    for (int i = 0; i < kBlock / 64; ++i) s += red[i];
+    for (int i = 0; i < NT / 64; ++i) s += red[i];
   }
   return s;  // valid on thread 0
 }
 
+template <int NT>
 __device__ __forceinline__ float block_max(float v, float* red) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_down(v, o, 64));
@@ -39,7 +41,7 @@ __device__ __forceinline__ float block_max(float v, float* red) {
   __syncthreads();
   float s = 0.f;
   if (threadIdx.x == 0) {
-    for (int i = 0; i < kBlock / 64; ++i) s = fmaxf(s, red[i]);
+    for (int i = 0; i < NT / 64; ++i) s = fmaxf(s, red[i]);
   }
   return s;
 }
@@ -77,7 +79,7 @@ __device__ __forceinline__ void load_packed_c2r(float2* buf, const float2* __res
   }
 }
 
-// Pack x[r] = scale * sum_{e in CSR row r} w[e] g[idx[e]] (r < nts, zero beyond) as z[p] = x[2p] + i x[2p+1].
+// Pack x[r] = sum_{e in CSR row r} w[e] g[idx[e]] (r < nts, zero beyond) as z[p] = x[2p] + i x[2p+1].
 __device__ __forceinline__ void pack_from_csr(float2* buf, const float* g, const int* __restrict__ ptr,
                                               const int* __restrict__ idx, const float* __restrict__ w,
                                               int nts, int nh) {
@@ -97,14 +99,18 @@ __device__ __forceinline__ void pack_from_csr(float2* buf, const float* g, const
 }
 
 // ------------------------------------------------------------------ model side
+// Row kernels use two LDS buffers of N/2 complex values (FFT ping-pong); the
+// staged input row aliases the second buffer before the first pass.
+
 // Steps 1-2 of L: M'(tau') = S M, times the deapodisation of its curvature
 // index, real DFT of length N, bins 0..N/2-1 stored as mhat[row][f].
 __global__ __launch_bounds__(kBlock) void k_model_r2c(const float* __restrict__ m,
                                                       float2* __restrict__ mhat, Tables tb, Dims dm,
                                                       FftPlan fp) {
   extern __shared__ float2 lds[];
-  float2* buf = lds;
-  float* row = reinterpret_cast<float*>(lds + dm.nh);
+  float2* A = lds;
+  float2* B = lds + dm.nh;
+  float* row = reinterpret_cast<float*>(B);
   const size_t rid = blockIdx.x;
   const int l = (int)(rid % dm.nq);
   const float* src = m + rid * dm.ntau;
@@ -116,32 +122,30 @@ __global__ __launch_bounds__(kBlock) void k_model_r2c(const float* __restrict__ 
     float a = 0.f, b = 0.f;
     if (r0 < dm.nts) a = sc * (tb.s_w0[r0] * row[tb.s_i0[r0]] + tb.s_w1[r0] * row[tb.s_i1[r0]]);
     if (r1 < dm.nts) b = sc * (tb.s_w0[r1] * row[tb.s_i0[r1]] + tb.s_w1[r1] * row[tb.s_i1[r1]]);
-    buf[p] = make_float2(a, b);
+    A[p] = make_float2(a, b);
   }
   __syncthreads();
-  fft_lds<false>(buf, fp, 1, dm.nh, tb.tw_half);
-  store_real_spectrum(buf, mhat + rid * dm.nf, tb, dm);
+  const float2* X = fft_lds<false, kBlock>(A, B, fp, 1, dm.nh, tb.tw_half);
+  store_real_spectrum(X, mhat + rid * dm.nf, tb, dm);
 }
 
 // Transpose of steps 1-2: inverse real DFT (1/N, doubled positive bins), first
 // nt' samples, times the deapodisation, then S^T.
-__device__ __forceinline__ void model_c2r_core(const float2* __restrict__ mhat, float2* buf,
-                                               const Tables& tb, const Dims& dm, const FftPlan& fp,
-                                               size_t rid) {
-  load_packed_c2r(buf, mhat + rid * dm.nf, tb, dm);
+__device__ __forceinline__ const float* model_c2r_core(const float2* __restrict__ mhat, float2* A,
+                                                       float2* B, const Tables& tb, const Dims& dm,
+                                                       const FftPlan& fp, size_t rid) {
+  load_packed_c2r(A, mhat + rid * dm.nf, tb, dm);
   __syncthreads();
-  fft_lds<true>(buf, fp, 1, dm.nh, tb.tw_half);
+  return reinterpret_cast<const float*>(fft_lds<true, kBlock>(A, B, fp, 1, dm.nh, tb.tw_half));
 }
 
 __global__ __launch_bounds__(kBlock) void k_model_c2r(const float2* __restrict__ mhat,
                                                       float* __restrict__ m, Tables tb, Dims dm,
                                                       FftPlan fp) {
   extern __shared__ float2 lds[];
-  float2* buf = lds;
   const size_t rid = blockIdx.x;
   const int l = (int)(rid % dm.nq);
-  model_c2r_core(mhat, buf, tb, dm, fp, rid);
-  const float* xs = reinterpret_cast<const float*>(buf);
+  const float* xs = model_c2r_core(mhat, lds, lds + dm.nh, tb, dm, fp, rid);
   const float sc = tb.deapod[l] / (float)dm.nfft;
   float* dst = m + rid * dm.ntau;
   for (int i = threadIdx.x; i < dm.ntau; i += kBlock) {
@@ -164,12 +168,10 @@ __global__ __launch_bounds__(kBlock) void k_model_c2r_update(const float2* __res
                                                              float* __restrict__ l1) {
   extern __shared__ float2 lds[];
   __shared__ float red[kBlock / 64];
-  float2* buf = lds;
   const size_t rid = blockIdx.x;
   const int l = (int)(rid % dm.nq);
   const int b = (int)(rid / ((size_t)dm.nq * dm.ntheta));
-  model_c2r_core(mhat, buf, tb, dm, fp, rid);
-  const float* xs = reinterpret_cast<const float*>(buf);
+  const float* xs = model_c2r_core(mhat, lds, lds + dm.nh, tb, dm, fp, rid);
   const float sc = tb.deapod[l] / (float)dm.nfft;
   const float g = gam[b];
   const float thr = g * lam[b];
@@ -188,7 +190,7 @@ __global__ __launch_bounds__(kBlock) void k_model_c2r_update(const float2* __res
     s1 += fabsf(xn);
   }
   if (l1) {
-    const float t = block_sum(s1, red);
+    const float t = block_sum<kBlock>(s1, red);
     if (threadIdx.x == 0) l1[rid] = t;
   }
 }
@@ -199,12 +201,12 @@ __global__ __launch_bounds__(kBlock) void k_data_c2r(const float2* __restrict__ 
                                                      float* __restrict__ d, Tables tb, Dims dm,
                                                      FftPlan fp) {
   extern __shared__ float2 lds[];
-  float2* buf = lds;
+  float2* A = lds;
+  float2* B = lds + dm.nh;
   const size_t n = blockIdx.x;
-  load_packed_c2r(buf, dhat + n * dm.nf, tb, dm);
+  load_packed_c2r(A, dhat + n * dm.nf, tb, dm);
   __syncthreads();
-  fft_lds<true>(buf, fp, 1, dm.nh, tb.tw_half);
-  const float* xs = reinterpret_cast<const float*>(buf);
+  const float* xs = reinterpret_cast<const float*>(fft_lds<true, kBlock>(A, B, fp, 1, dm.nh, tb.tw_half));
   const float invN = 1.0f / (float)dm.nfft;
   float* dst = d + n * dm.nt;
   for (int s = threadIdx.x; s < dm.nt; s += kBlock)
@@ -216,16 +218,17 @@ __global__ __launch_bounds__(kBlock) void k_data_r2c(const float* __restrict__ d
                                                      float2* __restrict__ dhat, Tables tb, Dims dm,
                                                      FftPlan fp) {
   extern __shared__ float2 lds[];
-  float2* buf = lds;
-  float* g = reinterpret_cast<float*>(lds + dm.nh);
+  float2* A = lds;
+  float2* B = lds + dm.nh;
+  float* g = reinterpret_cast<float*>(B);
   const size_t n = blockIdx.x;
   const float* src = d + n * dm.nt;
   for (int s = threadIdx.x; s < dm.nt; s += kBlock) g[s] = src[s];
   __syncthreads();
-  pack_from_csr(buf, g, tb.ut_ptr, tb.ut_idx, tb.ut_w, dm.nts, dm.nh);
+  pack_from_csr(A, g, tb.ut_ptr, tb.ut_idx, tb.ut_w, dm.nts, dm.nh);
   __syncthreads();
-  fft_lds<false>(buf, fp, 1, dm.nh, tb.tw_half);
-  store_real_spectrum(buf, dhat + n * dm.nf, tb, dm);
+  const float2* X = fft_lds<false, kBlock>(A, B, fp, 1, dm.nh, tb.tw_half);
+  store_real_spectrum(X, dhat + n * dm.nf, tb, dm);
 }
 
 // Solver data side, in place on dhat[n]: r = d_obs - S^-1 F1^-1 Dh (steps 4-5),
@@ -236,13 +239,15 @@ __global__ __launch_bounds__(kBlock) void k_residual_r2c(float2* __restrict__ dh
                                                          Dims dm, FftPlan fp) {
   extern __shared__ float2 lds[];
   __shared__ float red[kBlock / 64];
-  float2* buf = lds;
-  float* g = reinterpret_cast<float*>(lds + dm.nh);
+  float2* A = lds;
+  float2* B = lds + dm.nh;
   const size_t n = blockIdx.x;
-  load_packed_c2r(buf, dhat + n * dm.nf, tb, dm);
+  load_packed_c2r(A, dhat + n * dm.nf, tb, dm);
   __syncthreads();
-  fft_lds<true>(buf, fp, 1, dm.nh, tb.tw_half);
-  const float* xs = reinterpret_cast<const float*>(buf);
+  float2* X = fft_lds<true, kBlock>(A, B, fp, 1, dm.nh, tb.tw_half);
+  float2* Y = (X == A) ? B : A;
+  const float* xs = reinterpret_cast<const float*>(X);
+  float* g = reinterpret_cast<float*>(Y);
   const float invN = 1.0f / (float)dm.nfft;
   const float* ob = dobs + n * dm.nt;
   float ss = 0.f;
@@ -253,12 +258,12 @@ __global__ __launch_bounds__(kBlock) void k_residual_r2c(float2* __restrict__ dh
     ss += r * r;
   }
   __syncthreads();
-  pack_from_csr(buf, g, tb.ut_ptr, tb.ut_idx, tb.ut_w, dm.nts, dm.nh);
+  pack_from_csr(X, g, tb.ut_ptr, tb.ut_idx, tb.ut_w, dm.nts, dm.nh);
   __syncthreads();
-  fft_lds<false>(buf, fp, 1, dm.nh, tb.tw_half);
-  store_real_spectrum(buf, dhat + n * dm.nf, tb, dm);
+  const float2* Z = fft_lds<false, kBlock>(X, Y, fp, 1, dm.nh, tb.tw_half);
+  store_real_spectrum(Z, dhat + n * dm.nf, tb, dm);
   if (rss) {
-    const float t = block_sum(ss, red);
+    const float t = block_sum<kBlock>(ss, red);
     if (threadIdx.x == 0) rss[n] = t;
   }
 }
@@ -268,8 +273,10 @@ __global__ __launch_bounds__(kBlock) void k_residual_r2c(float2* __restrict__ dh
 // The oversampled q-grid of one azimuth slice for all ft frequencies lives in
 // LDS as [ft][mg+1] (one pad element against bank conflicts).  Slices are
 // visited in azimuth order; traces are grouped by their lower azimuth bin j_n,
-// so bin j needs slices j and j+1 (mod ntheta).  Three slots: slice 0 stays in
-// slot 0 (the last bin wraps onto it); slice s >= 1 uses slot 1 + ((s-1) & 1).
+// so bin j needs slices j and j+1 (mod ntheta).  Slot use: slice 0 stays in
+// slot 0 (the last bin wraps onto it); slice s >= 1 uses slot 1 + ((s-1) & 1);
+// one more slot is the FFT ping-pong scratch.  Per-trace tables of a bin are
+// staged in LDS in chunks of kStageTraces traces.
 
 __device__ __forceinline__ int slot_of(int s) { return s == 0 ? 0 : 1 + ((s - 1) & 1); }
 
@@ -305,17 +312,43 @@ __device__ __forceinline__ float2 pre_phase(unsigned long long f, unsigned long 
 __device__ __forceinline__ float es_kernel(float dist, float inv_half_w, float beta) {
   const float z = dist * inv_half_w;
   const float q = fmaxf(1.0f - z * z, 0.0f);
-  return __expf(beta * (__fsqrt_rn(q) - 1.0f));
+  return __expf(beta * (__builtin_amdgcn_sqrtf(q) - 1.0f));
+}
+
+// Logical tile index with consecutive tiles (same gather) on one XCD: the
+// hardware deals workgroup i to XCD i mod 8.
+__device__ __forceinline__ int xcd_tile(int id, int n) {
+  const int q = n >> 3, r = n & 7;
+  const int x = id & 7, loc = id >> 3;
+  return x < r ? x * (q + 1) + loc : r * (q + 1) + (x - r) * q + loc;
+}
+
+struct Stage {
+  unsigned long long* b;
+  unsigned long long* a;
+  float* alpha;
+  int* row;
+  float2* dv;  // spread only: [kStageTraces][ft]
+};
+
+__device__ __forceinline__ Stage stage_at(float2* base, int ft) {
+  Stage st;
+  st.b = reinterpret_cast<unsigned long long*>(base);
+  st.a = st.b + kStageTraces;
+  st.alpha = reinterpret_cast<float*>(st.a + kStageTraces);
+  st.row = reinterpret_cast<int*>(st.alpha + kStageTraces);
+  st.dv = reinterpret_cast<float2*>(st.row + kStageTraces);
+  return st;
 }
 
 // Forward q-grid of slice s: g[f][m] = sum_k c_k exp(-2 pi i k m/mg), c_k = Mh[b][s][k + nq/2][f0+f].
-__device__ void build_grid(float2* G, const float2* __restrict__ mhat_slice, int f0,
+__device__ void build_grid(float2* G, float2* scratch, const float2* __restrict__ mhat_slice, int f0,
                            const Tables& tb, const Dims& dm, const FftPlan& fpg, int ftl) {
   const int ld = dm.mg + 1;
   const int ft = dm.ft;
-  for (int i = threadIdx.x; i < ft * ld; i += kBlock) G[i] = make_float2(0.f, 0.f);
+  for (int i = threadIdx.x; i < ft * ld; i += kBlockG) G[i] = make_float2(0.f, 0.f);
   __syncthreads();
-  for (int it = threadIdx.x; it < dm.nq * ft; it += kBlock) {
+  for (int it = threadIdx.x; it < dm.nq * ft; it += kBlockG) {
     const int l = it >> ftl;
     const int fl = it & (ft - 1);
     const int f = f0 + fl;
@@ -326,135 +359,169 @@ __device__ void build_grid(float2* G, const float2* __restrict__ mhat_slice, int
     G[fl * ld + m] = c;
   }
   __syncthreads();
-  fft_lds<false>(G, fpg, ft, ld, tb.tw_grid);
+  const float2* R = fft_lds<false, kBlockG>(G, scratch, fpg, ft, ld, tb.tw_grid);
+  if (R != G) {
+    for (int i = threadIdx.x; i < ft * ld; i += kBlockG) G[i] = R[i];
+    __syncthreads();
+  }
 }
 
-__global__ __launch_bounds__(kBlock) void k_nufft_interp(const float2* __restrict__ mhat,
-                                                         float2* __restrict__ dhat, Tables tb,
-                                                         Dims dm, FftPlan fpg, int ftl) {
+__global__ __launch_bounds__(kBlockG) void k_nufft_interp(const float2* __restrict__ mhat,
+                                                          float2* __restrict__ dhat, Tables tb,
+                                                          Dims dm, FftPlan fpg, int ftl) {
   extern __shared__ float2 lds[];
   const int ld = dm.mg + 1;
   const int ft = dm.ft;
   const int slot_sz = ft * ld;
-  const int b = blockIdx.x / dm.nftile;
-  const int f0 = (blockIdx.x - b * dm.nftile) * ft;
+  const int nslot = dm.ntheta >= 3 ? 3 : dm.ntheta;
+  float2* scratch = lds + nslot * slot_sz;
+  const Stage st = stage_at(scratch + slot_sz, ft);
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int b = tile / dm.nftile;
+  const int f0 = (tile - b * dm.nftile) * ft;
   const int* bp = tb.bin_ptr + (size_t)b * (dm.ntheta + 1);
   const size_t slice_stride = (size_t)dm.nq * dm.nf;
   const float2* mb = mhat + (size_t)b * dm.ntheta * slice_stride;
   if (bp[dm.ntheta] == bp[0]) return;  // empty gather: nothing to write
   const float ihw = 2.0f / (float)dm.w;
 
-  build_grid(lds, mb, f0, tb, dm, fpg, ftl);
-  if (dm.ntheta > 1) build_grid(lds + slot_sz, mb + slice_stride, f0, tb, dm, fpg, ftl);
+  build_grid(lds, scratch, mb, f0, tb, dm, fpg, ftl);
+  if (dm.ntheta > 1) build_grid(lds + slot_sz, scratch, mb + slice_stride, f0, tb, dm, fpg, ftl);
   for (int j = 0; j < dm.ntheta; ++j) {
     const int j1 = (j + 1 == dm.ntheta) ? 0 : j + 1;
     const float2* G0 = lds + slot_of(j) * slot_sz;
     const float2* G1 = lds + slot_of(j1) * slot_sz;
-    const int p0 = bp[j], cnt = bp[j + 1] - bp[j];
-    for (int it = threadIdx.x; it < cnt * ft; it += kBlock) {
-      const int ti = it >> ftl;
-      const int fl = it & (ft - 1);
-      const int f = f0 + fl;
-      if (f >= dm.nf) continue;
-      const int pos = p0 + ti;
-      const KernelPoint kp = kernel_point((unsigned long long)f, tb.tr_b[pos], dm.mg, dm.w);
-      const float alpha = tb.tr_alpha[pos];
-      float2 a0 = make_float2(0.f, 0.f), a1 = make_float2(0.f, 0.f);
-      int m = kp.base;
-      if (m < 0) m += dm.mg;
-      const float2* g0 = G0 + fl * ld;
-      const float2* g1 = G1 + fl * ld;
-      for (int t = 0; t < dm.w; ++t) {
-        const float ph = es_kernel(kp.d0 - (float)t, ihw, dm.beta);
-        const float2 v0 = g0[m], v1 = g1[m];
-        a0.x += ph * v0.x;
-        a0.y += ph * v0.y;
-        a1.x += ph * v1.x;
-        a1.y += ph * v1.y;
-        m = (m + 1 == dm.mg) ? 0 : m + 1;
+    for (int c0 = bp[j]; c0 < bp[j + 1]; c0 += kStageTraces) {
+      const int cnt = min(kStageTraces, bp[j + 1] - c0);
+      for (int t = threadIdx.x; t < cnt; t += kBlockG) {
+        st.b[t] = tb.tr_b[c0 + t];
+        st.a[t] = tb.tr_a[c0 + t];
+        st.alpha[t] = tb.tr_alpha[c0 + t];
+        st.row[t] = tb.tr_row[c0 + t];
       }
-      const float2 v = make_float2((1.f - alpha) * a0.x + alpha * a1.x,
-                                   (1.f - alpha) * a0.y + alpha * a1.y);
-      const float2 e = pre_phase((unsigned long long)f, tb.tr_a[pos], -1.0f);
-      dhat[(size_t)tb.tr_row[pos] * dm.nf + f] = cmul(v, e);
+      __syncthreads();
+      for (int it = threadIdx.x; it < cnt * ft; it += kBlockG) {
+        const int ti = it >> ftl;
+        const int fl = it & (ft - 1);
+        const int f = f0 + fl;
+        if (f >= dm.nf) continue;
+        const KernelPoint kp = kernel_point((unsigned long long)f, st.b[ti], dm.mg, dm.w);
+        const float alpha = st.alpha[ti];
+        float2 a0 = make_float2(0.f, 0.f), a1 = make_float2(0.f, 0.f);
+        int m = kp.base;
+        if (m < 0) m += dm.mg;
+        const float2* g0 = G0 + fl * ld;
+        const float2* g1 = G1 + fl * ld;
+        for (int t = 0; t < dm.w; ++t) {
+          const float ph = es_kernel(kp.d0 - (float)t, ihw, dm.beta);
+          const float2 v0 = g0[m], v1 = g1[m];
+          a0.x += ph * v0.x;
+          a0.y += ph * v0.y;
+          a1.x += ph * v1.x;
+          a1.y += ph * v1.y;
+          m = (m + 1 == dm.mg) ? 0 : m + 1;
+        }
+        const float2 v = make_float2((1.f - alpha) * a0.x + alpha * a1.x,
+                                     (1.f - alpha) * a0.y + alpha * a1.y);
+        const float2 e = pre_phase((unsigned long long)f, st.a[ti], -1.0f);
+        dhat[(size_t)st.row[ti] * dm.nf + f] = cmul(v, e);
+      }
+      __syncthreads();
     }
-    __syncthreads();
     if (j + 2 < dm.ntheta)
-      build_grid(lds + slot_of(j + 2) * slot_sz, mb + (size_t)(j + 2) * slice_stride, f0, tb, dm,
-                 fpg, ftl);
+      build_grid(lds + slot_of(j + 2) * slot_sz, scratch, mb + (size_t)(j + 2) * slice_stride, f0, tb,
+                 dm, fpg, ftl);
   }
 }
 
 // Inverse q-grid of slice s: H[k] = sum_m G[m] exp(+2 pi i k m/mg) for the nq
 // modes, written to Mh[b][s][k + nq/2][f0 + f]; the slot is cleared afterwards.
-__device__ void finish_grid(float2* G, float2* __restrict__ out_slice, int f0, const Tables& tb,
-                            const Dims& dm, const FftPlan& fpg, int ftl) {
+__device__ void finish_grid(float2* G, float2* scratch, float2* __restrict__ out_slice, int f0,
+                            const Tables& tb, const Dims& dm, const FftPlan& fpg, int ftl) {
   const int ld = dm.mg + 1;
   const int ft = dm.ft;
-  fft_lds<true>(G, fpg, ft, ld, tb.tw_grid);
-  for (int it = threadIdx.x; it < dm.nq * ft; it += kBlock) {
+  const float2* R = fft_lds<true, kBlockG>(G, scratch, fpg, ft, ld, tb.tw_grid);
+  for (int it = threadIdx.x; it < dm.nq * ft; it += kBlockG) {
     const int l = it >> ftl;
     const int fl = it & (ft - 1);
     const int f = f0 + fl;
     int m = l - dm.qhalf;
     if (m < 0) m += dm.mg;
-    if (f < dm.nf) out_slice[(size_t)l * dm.nf + f] = G[fl * ld + m];
+    if (f < dm.nf) out_slice[(size_t)l * dm.nf + f] = R[fl * ld + m];
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < ft * ld; i += kBlock) G[i] = make_float2(0.f, 0.f);
+  for (int i = threadIdx.x; i < ft * ld; i += kBlockG) G[i] = make_float2(0.f, 0.f);
   __syncthreads();
 }
 
-__global__ __launch_bounds__(kBlock) void k_nufft_spread(const float2* __restrict__ dhat,
-                                                         float2* __restrict__ mhat, Tables tb,
-                                                         Dims dm, FftPlan fpg, int ftl) {
+__global__ __launch_bounds__(kBlockG) void k_nufft_spread(const float2* __restrict__ dhat,
+                                                          float2* __restrict__ mhat, Tables tb,
+                                                          Dims dm, FftPlan fpg, int ftl) {
   extern __shared__ float2 lds[];
   const int ld = dm.mg + 1;
   const int ft = dm.ft;
   const int slot_sz = ft * ld;
-  const int b = blockIdx.x / dm.nftile;
-  const int f0 = (blockIdx.x - b * dm.nftile) * ft;
+  const int nslot = dm.ntheta >= 3 ? 3 : dm.ntheta;
+  float2* scratch = lds + nslot * slot_sz;
+  const Stage st = stage_at(scratch + slot_sz, ft);
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int b = tile / dm.nftile;
+  const int f0 = (tile - b * dm.nftile) * ft;
   const int* bp = tb.bin_ptr + (size_t)b * (dm.ntheta + 1);
   const size_t slice_stride = (size_t)dm.nq * dm.nf;
   float2* mb = mhat + (size_t)b * dm.ntheta * slice_stride;
   const float ihw = 2.0f / (float)dm.w;
-  const int nslot = dm.ntheta >= 3 ? 3 : dm.ntheta;
-  for (int i = threadIdx.x; i < nslot * slot_sz; i += kBlock) lds[i] = make_float2(0.f, 0.f);
+  for (int i = threadIdx.x; i < nslot * slot_sz; i += kBlockG) lds[i] = make_float2(0.f, 0.f);
   __syncthreads();
   for (int j = 0; j < dm.ntheta; ++j) {
     const int j1 = (j + 1 == dm.ntheta) ? 0 : j + 1;
     float* G0 = reinterpret_cast<float*>(lds + slot_of(j) * slot_sz);
     float* G1 = reinterpret_cast<float*>(lds + slot_of(j1) * slot_sz);
-    const int p0 = bp[j], cnt = bp[j + 1] - bp[j];
-    for (int it = threadIdx.x; it < cnt * ft; it += kBlock) {
-      const int ti = it >> ftl;
-      const int fl = it & (ft - 1);
-      const int f = f0 + fl;
-      if (f >= dm.nf) continue;
-      const int pos = p0 + ti;
-      const float2 dv = dhat[(size_t)tb.tr_row[pos] * dm.nf + f];
-      const float2 s = cmul(dv, pre_phase((unsigned long long)f, tb.tr_a[pos], 1.0f));
-      const KernelPoint kp = kernel_point((unsigned long long)f, tb.tr_b[pos], dm.mg, dm.w);
-      const float alpha = tb.tr_alpha[pos];
-      const float2 s0 = cscale(s, 1.f - alpha), s1 = cscale(s, alpha);
-      int m = kp.base;
-      if (m < 0) m += dm.mg;
-      float* g0 = G0 + 2 * fl * ld;
-      float* g1 = G1 + 2 * fl * ld;
-      for (int t = 0; t < dm.w; ++t) {
-        const float ph = es_kernel(kp.d0 - (float)t, ihw, dm.beta);
-        atomicAdd(g0 + 2 * m, ph * s0.x);
-        atomicAdd(g0 + 2 * m + 1, ph * s0.y);
-        atomicAdd(g1 + 2 * m, ph * s1.x);
-        atomicAdd(g1 + 2 * m + 1, ph * s1.y);
-        m = (m + 1 == dm.mg) ? 0 : m + 1;
+    for (int c0 = bp[j]; c0 < bp[j + 1]; c0 += kStageTraces) {
+      const int cnt = min(kStageTraces, bp[j + 1] - c0);
+      for (int t = threadIdx.x; t < cnt; t += kBlockG) {
+        st.b[t] = tb.tr_b[c0 + t];
+        st.a[t] = tb.tr_a[c0 + t];
+        st.alpha[t] = tb.tr_alpha[c0 + t];
+        st.row[t] = tb.tr_row[c0 + t];
       }
+      __syncthreads();
+      for (int it = threadIdx.x; it < cnt * ft; it += kBlockG) {
+        const int ti = it >> ftl;
+        const int fl = it & (ft - 1);
+        const int f = f0 + fl;
+        st.dv[it] = f < dm.nf ? dhat[(size_t)st.row[ti] * dm.nf + f] : make_float2(0.f, 0.f);
+      }
+      __syncthreads();
+      for (int it = threadIdx.x; it < cnt * ft; it += kBlockG) {
+        const int ti = it >> ftl;
+        const int fl = it & (ft - 1);
+        const int f = f0 + fl;
+        if (f >= dm.nf) continue;
+        const float2 s = cmul(st.dv[it], pre_phase((unsigned long long)f, st.a[ti], 1.0f));
+        const KernelPoint kp = kernel_point((unsigned long long)f, st.b[ti], dm.mg, dm.w);
+        const float alpha = st.alpha[ti];
+        const float2 s0 = cscale(s, 1.f - alpha), s1 = cscale(s, alpha);
+        int m = kp.base;
+        if (m < 0) m += dm.mg;
+        float* g0 = G0 + 2 * fl * ld;
+        float* g1 = G1 + 2 * fl * ld;
+        for (int t = 0; t < dm.w; ++t) {
+          const float ph = es_kernel(kp.d0 - (float)t, ihw, dm.beta);
+          atomicAdd(g0 + 2 * m, ph * s0.x);
+          atomicAdd(g0 + 2 * m + 1, ph * s0.y);
+          atomicAdd(g1 + 2 * m, ph * s1.x);
+          atomicAdd(g1 + 2 * m + 1, ph * s1.y);
+          m = (m + 1 == dm.mg) ? 0 : m + 1;
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
     if (j >= 1)
-      finish_grid(lds + slot_of(j) * slot_sz, mb + (size_t)j * slice_stride, f0, tb, dm, fpg, ftl);
+      finish_grid(lds + slot_of(j) * slot_sz, scratch, mb + (size_t)j * slice_stride, f0, tb, dm, fpg,
+                  ftl);
   }
-  finish_grid(lds, mb, f0, tb, dm, fpg, ftl);
+  finish_grid(lds, scratch, mb, f0, tb, dm, fpg, ftl);
 }
 
 // ------------------------------------------------------------------ small kernels
@@ -497,7 +564,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_stage1(const float* __restric
     else if (op == RED_MAXABS) acc = fmaxf(acc, fabsf(v));
     else acc += fabsf(v);
   }
-  const float r = (op == RED_MAXABS) ? block_max(acc, red) : block_sum(acc, red);
+  const float r = (op == RED_MAXABS) ? block_max<kBlock>(acc, red) : block_sum<kBlock>(acc, red);
   if (threadIdx.x == 0) part[blockIdx.x] = r;
 }
 
@@ -515,11 +582,12 @@ __global__ void k_reduce_stage2(const float* __restrict__ part, int nblk, int ns
 
 __global__ void k_scale_per_gather(float* __restrict__ x, size_t per, int batch,
                                    const float* __restrict__ norms) {
-  const size_t n = per * (size_t)batch;
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-    const float nv = norms[i / per];
-    x[i] = nv > 0.f ? x[i] / nv : 0.f;
-  }
+  const int b = blockIdx.y;
+  const float nv = norms[b];
+  const float s = nv > 0.f ? 1.0f / nv : 0.f;
+  float* xb = x + (size_t)b * per;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < per; i += (size_t)gridDim.x * blockDim.x)
+    xb[i] *= s;
 }
 
 __global__ void k_gather_scalar(int batch, int op, const float* __restrict__ a, float* __restrict__ out,
@@ -546,14 +614,12 @@ __global__ void k_objective(const float* __restrict__ rss, const int64_t* __rest
 }
 
 // ------------------------------------------------------------------ launchers
-static size_t row_lds_bytes(const Dims& dm) {
-  const int extra = dm.nt > dm.ntau ? dm.nt : dm.ntau;
-  return (size_t)dm.nh * sizeof(float2) + (size_t)extra * sizeof(float);
-}
+static size_t row_lds_bytes(const Dims& dm) { return 2 * (size_t)dm.nh * sizeof(float2); }
 
 static size_t grid_lds_bytes(const Dims& dm) {
-  const int nslot = dm.ntheta >= 3 ? 3 : dm.ntheta;
-  return (size_t)nslot * dm.ft * (dm.mg + 1) * sizeof(float2);
+  const int nslot = (dm.ntheta >= 3 ? 3 : dm.ntheta) + 1;
+  return (size_t)nslot * dm.ft * (dm.mg + 1) * sizeof(float2) +
+         (size_t)kStageTraces * (24 + dm.ft * sizeof(float2));
 }
 
 static int ilog2(int v) {
@@ -639,7 +705,7 @@ hipError_t launch_nufft_interp(const Plan& p, const float2* mhat, float2* dhat, 
   const size_t lds = grid_lds_bytes(dm);
   hipError_t e = set_lds(k_nufft_interp, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_nufft_interp, dim3((unsigned)dm.batch * dm.nftile), dim3(kBlock), lds, s,
+  hipLaunchKernelGGL(k_nufft_interp, dim3((unsigned)dm.batch * dm.nftile), dim3(kBlockG), lds, s,
                      mhat, dhat, p.tb, dm, p.fft_grid, ilog2(dm.ft));
   return hipGetLastError();
 }
@@ -649,7 +715,7 @@ hipError_t launch_nufft_spread(const Plan& p, const float2* dhat, float2* mhat, 
   const size_t lds = grid_lds_bytes(dm);
   hipError_t e = set_lds(k_nufft_spread, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_nufft_spread, dim3((unsigned)dm.batch * dm.nftile), dim3(kBlock), lds, s,
+  hipLaunchKernelGGL(k_nufft_spread, dim3((unsigned)dm.batch * dm.nftile), dim3(kBlockG), lds, s,
                      dhat, mhat, p.tb, dm, p.fft_grid, ilog2(dm.ft));
   return hipGetLastError();
 }
@@ -693,7 +759,9 @@ hipError_t launch_gather_reduce(const Plan& p, const float* x, int op, float* ou
 hipError_t launch_scale_per_gather(const Plan& p, float* x, const float* norms, hipStream_t s) {
   const Dims& dm = p.dm;
   const size_t per = (size_t)dm.ntheta * dm.nq * dm.ntau;
-  hipLaunchKernelGGL(k_scale_per_gather, dim3(ew_blocks(per * dm.batch)), dim3(kBlock), 0, s, x, per,
+  size_t bx = (per + kBlock - 1) / kBlock;
+  if (bx > 256) bx = 256;
+  hipLaunchKernelGGL(k_scale_per_gather, dim3((unsigned)bx, dm.batch), dim3(kBlock), 0, s, x, per,
                      dm.batch, norms);
   return hipGetLastError();
 }

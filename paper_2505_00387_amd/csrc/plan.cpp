@@ -104,24 +104,40 @@ uint64_t to_fix64(double v) {
   return ((uint64_t)hi << 32) | (uint64_t)lo;
 }
 
-bool make_fft_plan(int n, int nbatch, FftPlan& pl) {
+FastDiv make_fastdiv(unsigned d) {
+  FastDiv f{1u, 0u, 0u};
+  if (d <= 1) return f;
+  unsigned s = 0;
+  while ((1u << s) < d) ++s;
+  f.d = d;
+  f.s = s;
+  f.m = (unsigned)(((1ull << 32) * ((1ull << s) - d)) / d + 1);
+  return f;
+}
+
+// Radix schedule for a length-n Stockham FFT: 16s, then 8/4/2, then 5s and 3s.
+bool make_fft_plan(int n, FftPlan& pl) {
   pl.n = n;
-  pl.nrad = 0;
+  pl.npass = 0;
   int m = n;
-  auto fits = [&](int R) {
-    const long total = (long)(n / R) * nbatch;
-    const long mb = (total + kBlock - 1) / kBlock;
-    return mb <= fft_max_bpt(R);
-  };
+  int ns = 1;
   while (m > 1) {
     int R = 0;
-    if (m % 8 == 0 && fits(8)) R = 8;
-    else if (m % 4 == 0 && fits(4)) R = 4;
-    else if (m % 2 == 0 && fits(2)) R = 2;
-    else if (m % 5 == 0 && fits(5)) R = 5;
-    else if (m % 3 == 0 && fits(3)) R = 3;
-    if (R == 0 || pl.nrad >= kMaxRadices) return false;
-    pl.rad[pl.nrad++] = R;
+    if (m % 16 == 0) R = 16;
+    else if (m % 8 == 0) R = 8;
+    else if (m % 4 == 0) R = 4;
+    else if (m % 2 == 0) R = 2;
+    else if (m % 5 == 0) R = 5;
+    else if (m % 3 == 0) R = 3;
+    if (R == 0 || pl.npass >= kMaxPasses) return false;
+    FftPass& ps = pl.pass[pl.npass++];
+    ps.r = R;
+    ps.nb = n / R;
+    ps.ns = ns;
+    ps.stride = n / (ns * R);
+    ps.dnb = make_fastdiv((unsigned)ps.nb);
+    ps.dns = make_fastdiv((unsigned)ps.ns);
+    ns *= R;
     m /= R;
   }
   return true;
@@ -193,9 +209,11 @@ int validate_params(const aahrt_params& q) {
   return AAHRT_OK;
 }
 
+// LDS of a GFST workgroup: azimuth-slice slots + one FFT scratch slot + staged trace tables.
 size_t grid_lds(int ft, int mg, int ntheta) {
-  const int nslot = ntheta >= 3 ? 3 : ntheta;
-  return (size_t)nslot * ft * (mg + 1) * sizeof(float2);
+  const int nslot = (ntheta >= 3 ? 3 : ntheta) + 1;
+  return (size_t)nslot * ft * (mg + 1) * sizeof(float2) +
+         (size_t)kStageTraces * (24 + ft * sizeof(float2));
 }
 
 int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* trace_ptr,
@@ -232,7 +250,7 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
   }
   dm.nh = dm.nfft / 2;
   dm.nf = dm.nh;
-  if (!make_fft_plan(dm.nh, 1, P.fft_half))
+  if (!make_fft_plan(dm.nh, P.fft_half))
     return fail(AAHRT_E_UNSUPPORTED, "FFT length N/2 = " + std::to_string(dm.nh) + " exceeds the LDS FFT limits");
 
   // nonuniform FFT parameters
@@ -255,13 +273,13 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
   dm.qhalf = dm.nq / 2;
 
   // frequency tile
+  if (!make_fft_plan(mg, P.fft_grid)) return fail(AAHRT_E_UNSUPPORTED, "q-grid length not 5-smooth");
   int ft = prm.freq_tile == 0 ? 16 : prm.freq_tile;
-  while (ft > 1 && (grid_lds(ft, mg, dm.ntheta) > 160 * 1024 || !make_fft_plan(mg, ft, P.fft_grid))) ft /= 2;
-  if (!make_fft_plan(mg, ft, P.fft_grid) || grid_lds(ft, mg, dm.ntheta) > 160 * 1024)
-    return fail(AAHRT_E_UNSUPPORTED, "q-grid too large for LDS");
+  while (ft > 1 && grid_lds(ft, mg, dm.ntheta) > 160 * 1024) ft /= 2;
+  if (grid_lds(ft, mg, dm.ntheta) > 160 * 1024) return fail(AAHRT_E_UNSUPPORTED, "q-grid too large for LDS");
   dm.ft = ft;
   dm.nftile = (dm.nf + ft - 1) / ft;
-  if ((size_t)dm.nh * sizeof(float2) + (size_t)std::max(dm.nt, dm.ntau) * sizeof(float) > 160 * 1024)
+  if (2 * (size_t)dm.nh * sizeof(float2) > 160 * 1024 || std::max(dm.nt, dm.ntau) > 2 * dm.nh)
     return fail(AAHRT_E_UNSUPPORTED, "row FFT too large for LDS");
 
   // anti-alias rule of Section 3.5 (informational)
