@@ -80,9 +80,11 @@ __device__ __forceinline__ void load_packed_c2r(float2* buf, const float2* __res
 }
 
 // Pack x[r] = sum_{e in CSR row r} w[e] g[idx[e]] (r < nts, zero beyond) as z[p] = x[2p] + i x[2p+1].
-__device__ __forceinline__ void pack_from_csr(float2* buf, const float* g, const int* __restrict__ ptr,
+// Returns this thread's share of sum |x[r]|.
+__device__ __forceinline__ float pack_from_csr(float2* buf, const float* g, const int* __restrict__ ptr,
                                               const int* __restrict__ idx, const float* __restrict__ w,
                                               int nts, int nh) {
+  float l1 = 0.f;
   for (int p = threadIdx.x; p < nh; p += kBlock) {
     float v[2] = {0.f, 0.f};
 #pragma unroll
@@ -95,7 +97,9 @@ __device__ __forceinline__ void pack_from_csr(float2* buf, const float* g, const
       }
     }
     buf[p] = make_float2(v[0], v[1]);
+    l1 += fabsf(v[0]) + fabsf(v[1]);
   }
+  return l1;
 }
 
 // ------------------------------------------------------------------ model side
@@ -214,10 +218,13 @@ __global__ __launch_bounds__(kBlock) void k_data_c2r(const float2* __restrict__ 
 }
 
 // Transpose of step 5 then the forward real DFT (the data side of L^T).
+// tr_l1[n] = sum |x| of the stretched trace (bounds |Dh[n,f]| for the spreading scale).
 __global__ __launch_bounds__(kBlock) void k_data_r2c(const float* __restrict__ d,
-                                                     float2* __restrict__ dhat, Tables tb, Dims dm,
+                                                     float2* __restrict__ dhat,
+                                                     float* __restrict__ tr_l1, Tables tb, Dims dm,
                                                      FftPlan fp) {
   extern __shared__ float2 lds[];
+  __shared__ float red[kBlock / 64];
   float2* A = lds;
   float2* B = lds + dm.nh;
   float* g = reinterpret_cast<float*>(B);
@@ -225,7 +232,9 @@ __global__ __launch_bounds__(kBlock) void k_data_r2c(const float* __restrict__ d
   const float* src = d + n * dm.nt;
   for (int s = threadIdx.x; s < dm.nt; s += kBlock) g[s] = src[s];
   __syncthreads();
-  pack_from_csr(A, g, tb.ut_ptr, tb.ut_idx, tb.ut_w, dm.nts, dm.nh);
+  const float l1 = pack_from_csr(A, g, tb.ut_ptr, tb.ut_idx, tb.ut_w, dm.nts, dm.nh);
+  const float l1s = block_sum<kBlock>(l1, red);
+  if (threadIdx.x == 0) tr_l1[n] = l1s;
   __syncthreads();
   const float2* X = fft_lds<false, kBlock>(A, B, fp, 1, dm.nh, tb.tw_half);
   store_real_spectrum(X, dhat + n * dm.nf, tb, dm);
@@ -235,7 +244,8 @@ __global__ __launch_bounds__(kBlock) void k_data_r2c(const float* __restrict__ d
 // then the data side of L^T applied to r.  rss[n] = sum r^2 when not null.
 __global__ __launch_bounds__(kBlock) void k_residual_r2c(float2* __restrict__ dhat,
                                                          const float* __restrict__ dobs,
-                                                         float* __restrict__ rss, Tables tb,
+                                                         float* __restrict__ rss,
+                                                         float* __restrict__ tr_l1, Tables tb,
                                                          Dims dm, FftPlan fp) {
   extern __shared__ float2 lds[];
   __shared__ float red[kBlock / 64];
@@ -258,7 +268,9 @@ __global__ __launch_bounds__(kBlock) void k_residual_r2c(float2* __restrict__ dh
     ss += r * r;
   }
   __syncthreads();
-  pack_from_csr(X, g, tb.ut_ptr, tb.ut_idx, tb.ut_w, dm.nts, dm.nh);
+  const float l1 = pack_from_csr(X, g, tb.ut_ptr, tb.ut_idx, tb.ut_w, dm.nts, dm.nh);
+  const float l1s = block_sum<kBlock>(l1, red);
+  if (threadIdx.x == 0) tr_l1[n] = l1s;
   __syncthreads();
   const float2* Z = fft_lds<false, kBlock>(X, Y, fp, 1, dm.nh, tb.tw_half);
   store_real_spectrum(Z, dhat + n * dm.nf, tb, dm);
@@ -434,13 +446,98 @@ __global__ __launch_bounds__(kBlockG) void k_nufft_interp(const float2* __restri
   }
 }
 
-// Inverse q-grid of slice s: H[k] = sum_m G[m] exp(+2 pi i k m/mg) for the nq
-// modes, written to Mh[b][s][k + nq/2][f0 + f]; the slot is cleared afterwards.
-__device__ void finish_grid(float2* G, float2* scratch, float2* __restrict__ out_slice, int f0,
+// Type-1 spreading accumulates in LDS as 64-bit fixed point: every contribution
+// c is added as round(c * S) with S = 2^50 / B_b, where B_b = sum over the
+// gather's traces of the L1 norm of the stretched trace bounds every |Dh[n,f]|
+// and therefore every grid cell (the kernel and the azimuth weights are <= 1).
+// Integer adds are exact and order independent, so the result is deterministic
+// and the rounding error is below 2^-50 B_b per contribution.
+__device__ __forceinline__ long long to_fix(double scaled_c) {
+  // round-to-nearest integer of a double with |x| < 2^51: add 1.5*2^52 and read the low bits
+  const double t = scaled_c + 6755399441055744.0;
+  return __double_as_longlong(t) - 0x4338000000000000LL;
+}
+
+// One azimuth bin into the fixed-point slots lo (weight 1 - alpha, slice j) and
+// hi (weight alpha, slice j+1); a null slot is skipped.
+__device__ void spread_bin(long long* lo, long long* hi, int c_begin, int c_end,
+                           const float2* __restrict__ dhat, const Stage& st, int f0, double S,
+                           const Tables& tb, const Dims& dm, int ftl) {
+  const int ld = dm.mg + 1;
+  const int ft = dm.ft;
+  const float ihw = 2.0f / (float)dm.w;
+  for (int c0 = c_begin; c0 < c_end; c0 += kStageTraces) {
+    const int cnt = min(kStageTraces, c_end - c0);
+    for (int t = threadIdx.x; t < cnt; t += kBlockG) {
+      st.b[t] = tb.tr_b[c0 + t];
+      st.a[t] = tb.tr_a[c0 + t];
+      st.alpha[t] = tb.tr_alpha[c0 + t];
+      st.row[t] = tb.tr_row[c0 + t];
+    }
+    __syncthreads();
+    for (int it = threadIdx.x; it < cnt * ft; it += kBlockG) {
+      const int ti = it >> ftl;
+      const int f = f0 + (it & (ft - 1));
+      st.dv[it] = f < dm.nf ? dhat[(size_t)st.row[ti] * dm.nf + f] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    for (int it = threadIdx.x; it < cnt * ft; it += kBlockG) {
+      const int ti = it >> ftl;
+      const int fl = it & (ft - 1);
+      const int f = f0 + fl;
+      if (f >= dm.nf) continue;
+      const float2 s = cmul(st.dv[it], pre_phase((unsigned long long)f, st.a[ti], 1.0f));
+      const KernelPoint kp = kernel_point((unsigned long long)f, st.b[ti], dm.mg, dm.w);
+      const double alpha = st.alpha[ti];
+      const double s0x = (1.0 - alpha) * S * s.x, s0y = (1.0 - alpha) * S * s.y;
+      const double s1x = alpha * S * s.x, s1y = alpha * S * s.y;
+      int m = kp.base;
+      if (m < 0) m += dm.mg;
+      unsigned long long* g0 = reinterpret_cast<unsigned long long*>(lo ? lo + 2 * fl * ld : nullptr);
+      unsigned long long* g1 = reinterpret_cast<unsigned long long*>(hi ? hi + 2 * fl * ld : nullptr);
+      for (int t = 0; t < dm.w; ++t) {
+        const double ph = (double)es_kernel(kp.d0 - (float)t, ihw, dm.beta);
+        if (g0) {
+          atomicAdd(g0 + 2 * m, (unsigned long long)to_fix(ph * s0x));
+          atomicAdd(g0 + 2 * m + 1, (unsigned long long)to_fix(ph * s0y));
+        }
+        if (g1) {
+          atomicAdd(g1 + 2 * m, (unsigned long long)to_fix(ph * s1x));
+          atomicAdd(g1 + 2 * m + 1, (unsigned long long)to_fix(ph * s1y));
+        }
+        m = (m + 1 == dm.mg) ? 0 : m + 1;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Decode a fixed-point slot to FP32 (in place: the first half of the slot
+// becomes [ft][mg+1] complex), inverse q-grid FFT (the second half is the
+// ping-pong buffer): H[k] = sum_m G[m] exp(+2 pi i k m/mg) for the nq modes,
+// written to Mh[b][s][k + nq/2][f0 + f]; the slot is cleared afterwards.
+__device__ void finish_slot(long long* slot, float2* __restrict__ out_slice, int f0, double inv_s,
                             const Tables& tb, const Dims& dm, const FftPlan& fpg, int ftl) {
   const int ld = dm.mg + 1;
   const int ft = dm.ft;
-  const float2* R = fft_lds<true, kBlockG>(G, scratch, fpg, ft, ld, tb.tw_grid);
+  const int cells = ft * ld;
+  constexpr int kPer = kDecodePer;  // cells per thread held in registers during the decode
+  float2 v[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int i = threadIdx.x + k * kBlockG;
+    if (i < cells) v[k] = make_float2((float)((double)slot[2 * i] * inv_s), (float)((double)slot[2 * i + 1] * inv_s));
+  }
+  __syncthreads();
+  float2* P = reinterpret_cast<float2*>(slot);
+  float2* Q = P + cells;
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int i = threadIdx.x + k * kBlockG;
+    if (i < cells) P[i] = v[k];
+  }
+  __syncthreads();
+  const float2* R = fft_lds<true, kBlockG>(P, Q, fpg, ft, ld, tb.tw_grid);
   for (int it = threadIdx.x; it < dm.nq * ft; it += kBlockG) {
     const int l = it >> ftl;
     const int fl = it & (ft - 1);
@@ -450,78 +547,56 @@ __device__ void finish_grid(float2* G, float2* scratch, float2* __restrict__ out
     if (f < dm.nf) out_slice[(size_t)l * dm.nf + f] = R[fl * ld + m];
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < ft * ld; i += kBlockG) G[i] = make_float2(0.f, 0.f);
+  for (int i = threadIdx.x; i < 2 * cells; i += kBlockG) slot[i] = 0;
   __syncthreads();
 }
 
+// Transpose of k_nufft_interp.  Two fixed-point slots: slice s lives in slot
+// s & 1.  The wrap bin ntheta-1 is spread twice, its upper part into slice 0
+// before the sweep and its lower part into slice ntheta-1 at the end, so no
+// slice has to stay resident across the whole sweep.
 __global__ __launch_bounds__(kBlockG) void k_nufft_spread(const float2* __restrict__ dhat,
+                                                          const float* __restrict__ tr_l1,
+                                                          const int64_t* __restrict__ trace_ptr,
                                                           float2* __restrict__ mhat, Tables tb,
                                                           Dims dm, FftPlan fpg, int ftl) {
   extern __shared__ float2 lds[];
+  __shared__ float red[kBlockG / 64];
+  __shared__ double scale_sh;
   const int ld = dm.mg + 1;
   const int ft = dm.ft;
-  const int slot_sz = ft * ld;
-  const int nslot = dm.ntheta >= 3 ? 3 : dm.ntheta;
-  float2* scratch = lds + nslot * slot_sz;
-  const Stage st = stage_at(scratch + slot_sz, ft);
+  const int cells = ft * ld;
+  long long* slots = reinterpret_cast<long long*>(lds);  // 2 slots x cells x (re, im)
+  const Stage st = stage_at(lds + 4 * cells, ft);
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int b = tile / dm.nftile;
   const int f0 = (tile - b * dm.nftile) * ft;
   const int* bp = tb.bin_ptr + (size_t)b * (dm.ntheta + 1);
   const size_t slice_stride = (size_t)dm.nq * dm.nf;
   float2* mb = mhat + (size_t)b * dm.ntheta * slice_stride;
-  const float ihw = 2.0f / (float)dm.w;
-  for (int i = threadIdx.x; i < nslot * slot_sz; i += kBlockG) lds[i] = make_float2(0.f, 0.f);
+
+  float part = 0.f;
+  for (int64_t n = trace_ptr[b] + threadIdx.x; n < trace_ptr[b + 1]; n += kBlockG) part += tr_l1[n];
+  const float bsum = block_sum<kBlockG>(part, red);
+  if (threadIdx.x == 0) scale_sh = bsum > 0.f ? 1125899906842624.0 / (double)bsum : 1.0;  // 2^50 / B
+  for (int i = threadIdx.x; i < 4 * cells; i += kBlockG) slots[i] = 0;
   __syncthreads();
-  for (int j = 0; j < dm.ntheta; ++j) {
-    const int j1 = (j + 1 == dm.ntheta) ? 0 : j + 1;
-    float* G0 = reinterpret_cast<float*>(lds + slot_of(j) * slot_sz);
-    float* G1 = reinterpret_cast<float*>(lds + slot_of(j1) * slot_sz);
-    for (int c0 = bp[j]; c0 < bp[j + 1]; c0 += kStageTraces) {
-      const int cnt = min(kStageTraces, bp[j + 1] - c0);
-      for (int t = threadIdx.x; t < cnt; t += kBlockG) {
-        st.b[t] = tb.tr_b[c0 + t];
-        st.a[t] = tb.tr_a[c0 + t];
-        st.alpha[t] = tb.tr_alpha[c0 + t];
-        st.row[t] = tb.tr_row[c0 + t];
-      }
-      __syncthreads();
-      for (int it = threadIdx.x; it < cnt * ft; it += kBlockG) {
-        const int ti = it >> ftl;
-        const int fl = it & (ft - 1);
-        const int f = f0 + fl;
-        st.dv[it] = f < dm.nf ? dhat[(size_t)st.row[ti] * dm.nf + f] : make_float2(0.f, 0.f);
-      }
-      __syncthreads();
-      for (int it = threadIdx.x; it < cnt * ft; it += kBlockG) {
-        const int ti = it >> ftl;
-        const int fl = it & (ft - 1);
-        const int f = f0 + fl;
-        if (f >= dm.nf) continue;
-        const float2 s = cmul(st.dv[it], pre_phase((unsigned long long)f, st.a[ti], 1.0f));
-        const KernelPoint kp = kernel_point((unsigned long long)f, st.b[ti], dm.mg, dm.w);
-        const float alpha = st.alpha[ti];
-        const float2 s0 = cscale(s, 1.f - alpha), s1 = cscale(s, alpha);
-        int m = kp.base;
-        if (m < 0) m += dm.mg;
-        float* g0 = G0 + 2 * fl * ld;
-        float* g1 = G1 + 2 * fl * ld;
-        for (int t = 0; t < dm.w; ++t) {
-          const float ph = es_kernel(kp.d0 - (float)t, ihw, dm.beta);
-          atomicAdd(g0 + 2 * m, ph * s0.x);
-          atomicAdd(g0 + 2 * m + 1, ph * s0.y);
-          atomicAdd(g1 + 2 * m, ph * s1.x);
-          atomicAdd(g1 + 2 * m + 1, ph * s1.y);
-          m = (m + 1 == dm.mg) ? 0 : m + 1;
-        }
-      }
-      __syncthreads();
-    }
-    if (j >= 1)
-      finish_grid(lds + slot_of(j) * slot_sz, scratch, mb + (size_t)j * slice_stride, f0, tb, dm, fpg,
-                  ftl);
+  const double S = scale_sh;
+  const double inv_s = 1.0 / S;
+  long long* slot0 = slots;
+  long long* slot1 = slots + 2 * cells;
+  const int last = dm.ntheta - 1;
+
+  spread_bin(nullptr, slot0, bp[last], bp[last + 1], dhat, st, f0, S, tb, dm, ftl);
+  for (int j = 0; j < last; ++j) {
+    long long* sj = (j & 1) ? slot1 : slot0;
+    long long* sn = (j & 1) ? slot0 : slot1;
+    spread_bin(sj, sn, bp[j], bp[j + 1], dhat, st, f0, S, tb, dm, ftl);
+    finish_slot(sj, mb + (size_t)j * slice_stride, f0, inv_s, tb, dm, fpg, ftl);
   }
-  finish_grid(lds, scratch, mb, f0, tb, dm, fpg, ftl);
+  long long* sl = (last & 1) ? slot1 : slot0;
+  spread_bin(sl, nullptr, bp[last], bp[last + 1], dhat, st, f0, S, tb, dm, ftl);
+  finish_slot(sl, mb + (size_t)last * slice_stride, f0, inv_s, tb, dm, fpg, ftl);
 }
 
 // ------------------------------------------------------------------ small kernels
@@ -622,6 +697,11 @@ static size_t grid_lds_bytes(const Dims& dm) {
          (size_t)kStageTraces * (24 + dm.ft * sizeof(float2));
 }
 
+static size_t spread_lds_bytes(const Dims& dm) {
+  return 2 * (size_t)dm.ft * (dm.mg + 1) * 2 * sizeof(long long) +
+         (size_t)kStageTraces * (24 + dm.ft * sizeof(float2));
+}
+
 static int ilog2(int v) {
   int l = 0;
   while ((1 << l) < v) ++l;
@@ -683,7 +763,8 @@ hipError_t launch_data_r2c(const Plan& p, const float* d, float2* dhat, hipStrea
   const size_t lds = row_lds_bytes(dm);
   hipError_t e = set_lds(k_data_r2c, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_data_r2c, dim3(dm.ntr), dim3(kBlock), lds, s, d, dhat, p.tb, dm, p.fft_half);
+  hipLaunchKernelGGL(k_data_r2c, dim3(dm.ntr), dim3(kBlock), lds, s, d, dhat, p.tr_l1, p.tb, dm,
+                     p.fft_half);
   return hipGetLastError();
 }
 
@@ -694,8 +775,8 @@ hipError_t launch_residual_r2c(const Plan& p, float2* dhat, const float* dobs, f
   const size_t lds = row_lds_bytes(dm);
   hipError_t e = set_lds(k_residual_r2c, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_residual_r2c, dim3(dm.ntr), dim3(kBlock), lds, s, dhat, dobs, rss, p.tb, dm,
-                     p.fft_half);
+  hipLaunchKernelGGL(k_residual_r2c, dim3(dm.ntr), dim3(kBlock), lds, s, dhat, dobs, rss, p.tr_l1,
+                     p.tb, dm, p.fft_half);
   return hipGetLastError();
 }
 
@@ -712,11 +793,11 @@ hipError_t launch_nufft_interp(const Plan& p, const float2* mhat, float2* dhat, 
 
 hipError_t launch_nufft_spread(const Plan& p, const float2* dhat, float2* mhat, hipStream_t s) {
   const Dims& dm = p.dm;
-  const size_t lds = grid_lds_bytes(dm);
+  const size_t lds = spread_lds_bytes(dm);
   hipError_t e = set_lds(k_nufft_spread, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_nufft_spread, dim3((unsigned)dm.batch * dm.nftile), dim3(kBlockG), lds, s,
-                     dhat, mhat, p.tb, dm, p.fft_grid, ilog2(dm.ft));
+                     dhat, p.tr_l1, p.trace_ptr_dev, mhat, p.tb, dm, p.fft_grid, ilog2(dm.ft));
   return hipGetLastError();
 }
 

@@ -209,11 +209,14 @@ int validate_params(const aahrt_params& q) {
   return AAHRT_OK;
 }
 
-// LDS of a GFST workgroup: azimuth-slice slots + one FFT scratch slot + staged trace tables.
+// LDS of a GFST workgroup: azimuth-slice slots + one FFT scratch slot + staged trace tables
+// (interpolation), or two fixed-point slots of twice the size (spreading); the larger one.
 size_t grid_lds(int ft, int mg, int ntheta) {
   const int nslot = (ntheta >= 3 ? 3 : ntheta) + 1;
-  return (size_t)nslot * ft * (mg + 1) * sizeof(float2) +
-         (size_t)kStageTraces * (24 + ft * sizeof(float2));
+  const size_t stage = (size_t)kStageTraces * (24 + ft * sizeof(float2));
+  const size_t interp = (size_t)nslot * ft * (mg + 1) * sizeof(float2) + stage;
+  const size_t spread = 4 * (size_t)ft * (mg + 1) * sizeof(float2) + stage;
+  return interp > spread ? interp : spread;
 }
 
 int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* trace_ptr,
@@ -275,7 +278,7 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
   // frequency tile
   if (!make_fft_plan(mg, P.fft_grid)) return fail(AAHRT_E_UNSUPPORTED, "q-grid length not 5-smooth");
   int ft = prm.freq_tile == 0 ? 16 : prm.freq_tile;
-  while (ft > 1 && grid_lds(ft, mg, dm.ntheta) > 160 * 1024) ft /= 2;
+  while (ft > 1 && (grid_lds(ft, mg, dm.ntheta) > 160 * 1024 || ft * (mg + 1) > kDecodePer * kBlockG)) ft /= 2;
   if (grid_lds(ft, mg, dm.ntheta) > 160 * 1024) return fail(AAHRT_E_UNSUPPORTED, "q-grid too large for LDS");
   dm.ft = ft;
   dm.nftile = (dm.nf + ft - 1) / ft;
@@ -423,6 +426,7 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
   TRY(alloc(P, (size_t)batch * P.red_blocks_model, &P.red));
   TRY(alloc(P, rows, &P.l1row));
   TRY(alloc(P, (size_t)dm.ntr, &P.rss));
+  TRY(alloc(P, (size_t)dm.ntr, &P.tr_l1));
   return AAHRT_OK;
 }
 

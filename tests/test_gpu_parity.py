@@ -212,3 +212,19 @@ def test_solver_defaults_zero_lambda_rule():
     x, _ = plan.sparse_solve(d, 5, lam=lm)
     assert torch.count_nonzero(x).item() == 0
     plan.close()
+
+
+def test_operators_are_bitwise_deterministic():
+    """Fixed-point spreading makes every kernel order independent: repeated calls agree bit for bit."""
+    import torch
+    w = wl.config3(with_data=True)
+    plan = make_plan(w)
+    d = to_dev(w.data_all())
+    m1 = plan.adjoint(d).clone()
+    m2 = plan.adjoint(d).clone()
+    assert torch.equal(m1, m2)
+    x1, _ = plan.sparse_solve(d, 5)
+    x1 = x1.clone()
+    x2, _ = plan.sparse_solve(d, 5)
+    assert torch.equal(x1, x2)
+    plan.close()
