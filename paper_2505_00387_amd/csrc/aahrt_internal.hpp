@@ -35,23 +35,23 @@ struct FftPlan {
   FftPass pass[kMaxPasses];
 };
 
+// Two-tap linear interpolation entry: value = w0 * x[i0] + w1 * x[i1] (dropped taps have weight 0).
+struct __attribute__((aligned(16))) Tap {
+  int i0, i1;
+  float w0, w1;
+};
+
 // Device tables of one plan.  Per-trace arrays are stored in "bin order":
 // within a gather, traces are grouped by their lower azimuth bin j_n.
 struct Tables {
-  // stretch S (model side): for r < nt', M'(r) = s_w0[r] M[s_i0[r]] + s_w1[r] M[s_i1[r]]
-  const int* s_i0;
-  const int* s_i1;
-  const float* s_w0;
-  const float* s_w1;
+  // stretch S (model side): for r < nt', M'(r) = interpolation s_tap[r] of M
+  const Tap* s_tap;
   // S^T as CSR over tau samples
   const int* st_ptr;
   const int* st_idx;
   const float* st_w;
-  // unstretch U (data side): d(s) = u_w0[s] D'[u_i0[s]] + u_w1[s] D'[u_i1[s]]
-  const int* u_i0;
-  const int* u_i1;
-  const float* u_w0;
-  const float* u_w1;
+  // unstretch U (data side): d(s) = interpolation u_tap[s] of D'
+  const Tap* u_tap;
   // U^T as CSR over stretched samples
   const int* ut_ptr;
   const int* ut_idx;

@@ -1,4 +1,4 @@
-// Batched complex FFTs in LDS: Stockham autosort, radices 2/3/4/5/8/16.
+// Batched complex FFTs in LDS: Stockham autosort, radices 2/3/4/5/8/9/15/16.
 //
 // A workgroup of NT threads transforms `nbatch` sequences of length n stored at
 // buf + b*bstride.  Passes alternate between two LDS buffers (ping-pong), so a
@@ -14,25 +14,25 @@
 
 namespace aahrt {
 
-__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+__host__ __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__host__ __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__host__ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
-__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__host__ __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 // multiply by -i (forward sign) or +i (inverse sign)
 template <bool INV>
-__device__ __forceinline__ float2 mul_i(float2 a) {
+__host__ __device__ __forceinline__ float2 mul_i(float2 a) {
   return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
 }
 // multiply by exp(-+ i pi/4) and exp(-+ 3 i pi/4)
 template <bool INV>
-__device__ __forceinline__ float2 mul_w8(float2 a) {
+__host__ __device__ __forceinline__ float2 mul_w8(float2 a) {
   const float r = 0.70710678118654752440f;
   return INV ? make_float2(r * (a.x - a.y), r * (a.x + a.y)) : make_float2(r * (a.x + a.y), r * (a.y - a.x));
 }
 template <bool INV>
-__device__ __forceinline__ float2 mul_w8_3(float2 a) {
+__host__ __device__ __forceinline__ float2 mul_w8_3(float2 a) {
   const float r = 0.70710678118654752440f;
   return INV ? make_float2(-r * (a.x + a.y), r * (a.x - a.y)) : make_float2(r * (a.y - a.x), -r * (a.x + a.y));
 }
@@ -46,7 +46,7 @@ struct Dft;
 
 template <bool INV>
 struct Dft<2, INV> {
-  __device__ __forceinline__ static void run(float2* v) {
+  __host__ __device__ __forceinline__ static void run(float2* v) {
     float2 a = v[0], b = v[1];
     v[0] = cadd(a, b);
     v[1] = csub(a, b);
@@ -55,7 +55,7 @@ struct Dft<2, INV> {
 
 template <bool INV>
 struct Dft<3, INV> {
-  __device__ __forceinline__ static void run(float2* v) {
+  __host__ __device__ __forceinline__ static void run(float2* v) {
     const float s = 0.86602540378443864676f;
     float2 a = v[0];
     float2 s1 = cadd(v[1], v[2]);
@@ -70,7 +70,7 @@ struct Dft<3, INV> {
 
 template <bool INV>
 struct Dft<4, INV> {
-  __device__ __forceinline__ static void run(float2* v) {
+  __host__ __device__ __forceinline__ static void run(float2* v) {
     float2 s0 = cadd(v[0], v[2]), s1 = csub(v[0], v[2]);
     float2 s2 = cadd(v[1], v[3]), s3 = mul_i<INV>(csub(v[1], v[3]));
     v[0] = cadd(s0, s2);
@@ -82,7 +82,7 @@ struct Dft<4, INV> {
 
 template <bool INV>
 struct Dft<5, INV> {
-  __device__ __forceinline__ static void run(float2* v) {
+  __host__ __device__ __forceinline__ static void run(float2* v) {
     const float c1 = 0.30901699437494742410f, c2 = -0.80901699437494742410f;
     const float s1 = 0.95105651629515357212f, s2 = 0.58778525229247312917f;
     float2 x0 = v[0];
@@ -103,7 +103,7 @@ struct Dft<5, INV> {
 
 template <bool INV>
 struct Dft<8, INV> {
-  __device__ __forceinline__ static void run(float2* v) {
+  __host__ __device__ __forceinline__ static void run(float2* v) {
     float2 e[4] = {v[0], v[2], v[4], v[6]};
     float2 o[4] = {v[1], v[3], v[5], v[7]};
     Dft<4, INV>::run(e);
@@ -125,7 +125,7 @@ struct Dft<8, INV> {
 // 16 = 4 x 4: DFT-4 over stride-4 inputs, twiddles W16^(a k1), DFT-4 across.
 template <bool INV>
 struct Dft<16, INV> {
-  __device__ __forceinline__ static void run(float2* v) {
+  __host__ __device__ __forceinline__ static void run(float2* v) {
     const float c = 0.92387953251128675613f, s = 0.38268343236508977173f;
     float2 sub[4][4];
 #pragma unroll
@@ -156,6 +156,85 @@ struct Dft<16, INV> {
   }
 };
 
+// 9 = 3 x 3: DFT-3 over stride-3 inputs, twiddles W9^(a k1), DFT-3 across.
+template <bool INV>
+struct Dft<9, INV> {
+  __host__ __device__ __forceinline__ static void run(float2* v) {
+    const float c1 = 0.766044443118978f, s1 = 0.6427876096865393f;   // W9^1
+    const float c2 = 0.17364817766693041f, s2 = 0.984807753012208f;  // W9^2
+    const float c4 = -0.9396926207859083f, s4 = 0.3420201433256689f; // W9^4
+    const float sg = INV ? 1.f : -1.f;
+    float2 sub[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+      for (int b = 0; b < 3; ++b) sub[a][b] = v[a + 3 * b];
+      Dft<3, INV>::run(sub[a]);
+    }
+    sub[1][1] = cmul(sub[1][1], make_float2(c1, sg * s1));
+    sub[1][2] = cmul(sub[1][2], make_float2(c2, sg * s2));
+    sub[2][1] = cmul(sub[2][1], make_float2(c2, sg * s2));
+    sub[2][2] = cmul(sub[2][2], make_float2(c4, sg * s4));
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1) {
+      float2 t[3] = {sub[0][k1], sub[1][k1], sub[2][k1]};
+      Dft<3, INV>::run(t);
+#pragma unroll
+      for (int k2 = 0; k2 < 3; ++k2) v[k1 + 3 * k2] = t[k2];
+    }
+  }
+};
+
+// 15 = 3 x 5 by the prime-factor (Good-Thomas) map: inputs x[(5 n1 + 3 n2) mod 15],
+// DFT-3 over n1, DFT-5 over n2, outputs X[(10 k1 + 6 k2) mod 15]; no twiddles.
+template <bool INV>
+struct Dft<15, INV> {
+  __host__ __device__ __forceinline__ static void run(float2* v) {
+    float2 a[3][5];
+#pragma unroll
+    for (int n2 = 0; n2 < 5; ++n2) {
+      float2 t[3];
+#pragma unroll
+      for (int n1 = 0; n1 < 3; ++n1) t[n1] = v[(5 * n1 + 3 * n2) % 15];
+      Dft<3, INV>::run(t);
+#pragma unroll
+      for (int k1 = 0; k1 < 3; ++k1) a[k1][n2] = t[k1];
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1) {
+      Dft<5, INV>::run(a[k1]);
+#pragma unroll
+      for (int k2 = 0; k2 < 5; ++k2) v[(10 * k1 + 6 * k2) % 15] = a[k1][k2];
+    }
+  }
+};
+
+// Twiddles w^r = exp(-+2 pi i r k / (ns R)) for r = 1..R-1: w^1 and every w^(4a) are read
+// from the table, the others are w^(4a) * w^b with b < 4 (at most three roundings).
+template <int R, bool INV>
+__device__ __forceinline__ void apply_twiddles(float2* v, const float2* __restrict__ tw, int step) {
+  float2 w1 = tw[step];
+  if (INV) w1.y = -w1.y;
+  float2 wb[4];
+  wb[0] = make_float2(1.f, 0.f);
+  wb[1] = w1;
+  wb[2] = cmul(w1, w1);
+  wb[3] = cmul(wb[2], w1);
+  float2 w4a = make_float2(1.f, 0.f);
+#pragma unroll
+  for (int r = 1; r < R; ++r) {
+    if ((r & 3) == 0) {
+      w4a = tw[r * step];
+      if (INV) w4a.y = -w4a.y;
+      v[r] = cmul(v[r], w4a);
+    } else if (r < 4) {
+      v[r] = cmul(v[r], wb[r]);
+    } else {
+      v[r] = cmul(v[r], cmul(w4a, wb[r & 3]));
+    }
+  }
+}
+
 // One out-of-place Stockham pass of radix R.
 template <int R, bool INV, int NT>
 __device__ __forceinline__ void fft_pass(const float2* __restrict__ src, float2* __restrict__ dst,
@@ -164,23 +243,18 @@ __device__ __forceinline__ void fft_pass(const float2* __restrict__ src, float2*
   const int nb = ps.nb;
   const int total = nb * nbatch;
   for (int b = threadIdx.x; b < total; b += NT) {
-    const int fb = (int)fdiv((unsigned)b, ps.dnb);
-    const int j = b - fb * nb;
+    int fb = 0, j = b;
+    if (nbatch > 1) {
+      fb = (int)fdiv((unsigned)b, ps.dnb);
+      j = b - fb * nb;
+    }
     const int jq = (int)fdiv((unsigned)j, ps.dns);
     const int k = j - jq * ps.ns;
     float2 v[R];
     const float2* x = src + fb * bstride + j;
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = x[r * nb];
-    if (ps.ns > 1) {
-      const int step = k * ps.stride;
-#pragma unroll
-      for (int r = 1; r < R; ++r) {
-        float2 w = tw[r * step];
-        if (INV) w.y = -w.y;
-        v[r] = cmul(v[r], w);
-      }
-    }
+    if (ps.ns > 1) apply_twiddles<R, INV>(v, tw, k * ps.stride);
     Dft<R, INV>::run(v);
     float2* y = dst + fb * bstride + jq * ps.ns * R + k;
 #pragma unroll
@@ -204,6 +278,8 @@ __device__ float2* fft_lds(float2* a, float2* b, const FftPlan& pl, int nbatch, 
       case 4: fft_pass<4, INV, NT>(src, dst, ps, nbatch, bstride, tw); break;
       case 5: fft_pass<5, INV, NT>(src, dst, ps, nbatch, bstride, tw); break;
       case 8: fft_pass<8, INV, NT>(src, dst, ps, nbatch, bstride, tw); break;
+      case 9: fft_pass<9, INV, NT>(src, dst, ps, nbatch, bstride, tw); break;
+      case 15: fft_pass<15, INV, NT>(src, dst, ps, nbatch, bstride, tw); break;
       default: fft_pass<16, INV, NT>(src, dst, ps, nbatch, bstride, tw); break;
     }
     float2* t = src;

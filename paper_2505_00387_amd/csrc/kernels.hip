@@ -124,8 +124,14 @@ __global__ __launch_bounds__(kBlock) void k_model_r2c(const float* __restrict__ 
   for (int p = threadIdx.x; p < dm.nh; p += kBlock) {
     const int r0 = 2 * p, r1 = 2 * p + 1;
     float a = 0.f, b = 0.f;
-    if (r0 < dm.nts) a = sc * (tb.s_w0[r0] * row[tb.s_i0[r0]] + tb.s_w1[r0] * row[tb.s_i1[r0]]);
-    if (r1 < dm.nts) b = sc * (tb.s_w0[r1] * row[tb.s_i0[r1]] + tb.s_w1[r1] * row[tb.s_i1[r1]]);
+    if (r0 < dm.nts) {
+      const Tap t = tb.s_tap[r0];
+      a = sc * (t.w0 * row[t.i0] + t.w1 * row[t.i1]);
+    }
+    if (r1 < dm.nts) {
+      const Tap t = tb.s_tap[r1];
+      b = sc * (t.w0 * row[t.i0] + t.w1 * row[t.i1]);
+    }
     A[p] = make_float2(a, b);
   }
   __syncthreads();
@@ -213,8 +219,10 @@ __global__ __launch_bounds__(kBlock) void k_data_c2r(const float2* __restrict__ 
   const float* xs = reinterpret_cast<const float*>(fft_lds<true, kBlock>(A, B, fp, 1, dm.nh, tb.tw_half));
   const float invN = 1.0f / (float)dm.nfft;
   float* dst = d + n * dm.nt;
-  for (int s = threadIdx.x; s < dm.nt; s += kBlock)
-    dst[s] = invN * (tb.u_w0[s] * xs[tb.u_i0[s]] + tb.u_w1[s] * xs[tb.u_i1[s]]);
+  for (int s = threadIdx.x; s < dm.nt; s += kBlock) {
+    const Tap t = tb.u_tap[s];
+    dst[s] = invN * (t.w0 * xs[t.i0] + t.w1 * xs[t.i1]);
+  }
 }
 
 // Transpose of step 5 then the forward real DFT (the data side of L^T).
@@ -262,7 +270,8 @@ __global__ __launch_bounds__(kBlock) void k_residual_r2c(float2* __restrict__ dh
   const float* ob = dobs + n * dm.nt;
   float ss = 0.f;
   for (int s = threadIdx.x; s < dm.nt; s += kBlock) {
-    const float v = invN * (tb.u_w0[s] * xs[tb.u_i0[s]] + tb.u_w1[s] * xs[tb.u_i1[s]]);
+    const Tap t = tb.u_tap[s];
+    const float v = invN * (t.w0 * xs[t.i0] + t.w1 * xs[t.i1]);
     const float r = ob[s] - v;
     g[s] = r;
     ss += r * r;

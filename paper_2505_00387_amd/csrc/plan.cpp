@@ -115,7 +115,8 @@ FastDiv make_fastdiv(unsigned d) {
   return f;
 }
 
-// Radix schedule for a length-n Stockham FFT: 16s, then 8/4/2, then 5s and 3s.
+// Radix schedule for a length-n Stockham FFT, fewest passes first: 16s, then 15 and 9,
+// then 8/4/2, 5, 3.
 bool make_fft_plan(int n, FftPlan& pl) {
   pl.n = n;
   pl.npass = 0;
@@ -124,6 +125,8 @@ bool make_fft_plan(int n, FftPlan& pl) {
   while (m > 1) {
     int R = 0;
     if (m % 16 == 0) R = 16;
+    else if (m % 15 == 0) R = 15;
+    else if (m % 9 == 0) R = 9;
     else if (m % 8 == 0) R = 8;
     else if (m % 4 == 0) R = 4;
     else if (m % 2 == 0) R = 2;
@@ -290,8 +293,7 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
   P.q_alias_ok = dm.nq >= 2.0 * std::max(std::fabs(prm.q_max), std::fabs(prm.q_min)) * fmax * h2max ? 1 : 0;
 
   // ---- stretch tables (FP64 positions)
-  std::vector<int> s_i0(dm.nts), s_i1(dm.nts);
-  std::vector<float> s_w0(dm.nts), s_w1(dm.nts);
+  std::vector<Tap> s_tap(dm.nts);
   std::vector<std::vector<std::pair<int, double>>> st(dm.ntau);
   for (int r = 0; r < dm.nts; ++r) {
     const double pos = std::sqrt(r * dts) / prm.dtau;
@@ -301,7 +303,7 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
     double w0 = 0.0, w1 = 0.0;
     if (i >= 0 && i < dm.ntau) { i0 = (int)i; w0 = 1.0 - a; st[i0].push_back({r, w0}); }
     if (i + 1 >= 0 && i + 1 < dm.ntau) { i1 = (int)(i + 1); w1 = a; st[i1].push_back({r, w1}); }
-    s_i0[r] = i0; s_i1[r] = i1; s_w0[r] = (float)w0; s_w1[r] = (float)w1;
+    s_tap[r] = Tap{i0, i1, (float)w0, (float)w1};
   }
   std::vector<int> st_ptr(dm.ntau + 1, 0), st_idx;
   std::vector<float> st_w;
@@ -309,8 +311,7 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
     for (auto& e : st[i]) { st_idx.push_back(e.first); st_w.push_back((float)e.second); }
     st_ptr[i + 1] = (int)st_idx.size();
   }
-  std::vector<int> u_i0(dm.nt), u_i1(dm.nt);
-  std::vector<float> u_w0(dm.nt), u_w1(dm.nt);
+  std::vector<Tap> u_tap(dm.nt);
   std::vector<std::vector<std::pair<int, double>>> ut(dm.nts);
   for (int s = 0; s < dm.nt; ++s) {
     const double ts = s * prm.dt;
@@ -321,7 +322,7 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
     double w0 = 0.0, w1 = 0.0;
     if (r >= 0 && r < dm.nts) { r0 = (int)r; w0 = 1.0 - b; ut[r0].push_back({s, w0}); }
     if (r + 1 >= 0 && r + 1 < dm.nts) { r1 = (int)(r + 1); w1 = b; ut[r1].push_back({s, w1}); }
-    u_i0[s] = r0; u_i1[s] = r1; u_w0[s] = (float)w0; u_w1[s] = (float)w1;
+    u_tap[s] = Tap{r0, r1, (float)w0, (float)w1};
   }
   std::vector<int> ut_ptr(dm.nts + 1, 0), ut_idx;
   std::vector<float> ut_w;
@@ -394,11 +395,9 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
 
   // ---- upload
   Tables& tb = P.tb;
-  TRY(upload(P, s_i0, &tb.s_i0)); TRY(upload(P, s_i1, &tb.s_i1));
-  TRY(upload(P, s_w0, &tb.s_w0)); TRY(upload(P, s_w1, &tb.s_w1));
+  TRY(upload(P, s_tap, &tb.s_tap));
   TRY(upload(P, st_ptr, &tb.st_ptr)); TRY(upload(P, st_idx, &tb.st_idx)); TRY(upload(P, st_w, &tb.st_w));
-  TRY(upload(P, u_i0, &tb.u_i0)); TRY(upload(P, u_i1, &tb.u_i1));
-  TRY(upload(P, u_w0, &tb.u_w0)); TRY(upload(P, u_w1, &tb.u_w1));
+  TRY(upload(P, u_tap, &tb.u_tap));
   TRY(upload(P, ut_ptr, &tb.ut_ptr)); TRY(upload(P, ut_idx, &tb.ut_idx)); TRY(upload(P, ut_w, &tb.ut_w));
   TRY(upload(P, deapod, &tb.deapod));
   TRY(upload(P, tw_half, &tb.tw_half)); TRY(upload(P, tw_real, &tb.tw_real)); TRY(upload(P, tw_grid, &tb.tw_grid));
