@@ -15,7 +15,6 @@ constexpr int kMaxPasses = 12;
 constexpr int kBlock = 256;     // threads per workgroup of the row kernels and small kernels
 constexpr int kBlockG = 512;    // threads per workgroup of the GFST (nonuniform FFT) kernels
 constexpr int kStageTraces = 64;  // traces staged in LDS per chunk in the GFST kernels
-constexpr int kDecodePer = 8;     // q-grid cells per thread in the in-place fixed-point decode
 
 // x / d = (umulhi(x, m) + x) >> s for 0 <= x < 2^31 (d = 1: x).
 struct FastDiv {
@@ -78,8 +77,10 @@ struct Dims {
   int nts;      // nt'
   int nfft, nh, nf;  // N, N/2, bins carried (= N/2)
   int mg;       // q-grid length
+  int ldr;      // LDS row length of a q-grid slot: mg + w - 1 ghost cells, padded to odd
   int w;        // kernel width
   float beta;
+  float cbeta;  // beta * log2(e)
   int ft;       // frequencies per GFST tile
   int nftile;   // ceil(nf/ft)
   int qhalf;    // nq/2 (mode offset)
@@ -108,7 +109,7 @@ struct Plan {
   float* tmpb = nullptr;    // [batch] scratch scalars
   float* l1row = nullptr;   // [rows] per-row l1 norms (objective)
   float* rss = nullptr;     // [ntr] per-trace residual sums of squares (objective)
-  float* tr_l1 = nullptr;   // [ntr] L1 norm of each stretched trace (spreading scale bound)
+  float* tr_bound = nullptr; // [ntr] max_f |Re Dh| + |Im Dh| of each trace (spreading scale bound)
   const int64_t* trace_ptr_dev = nullptr;
   int red_blocks_model = 0; // partial blocks per gather (model-sized reductions)
   size_t workspace_bytes = 0;

@@ -48,8 +48,10 @@ __device__ __forceinline__ float block_max(float v, float* red) {
 
 // Spectrum of a real sequence of length N from the FFT Z of the packed
 // complex sequence z[p] = x[2p] + i x[2p+1] (length N/2), bins k < N/2.
-__device__ __forceinline__ void store_real_spectrum(const float2* buf, float2* __restrict__ dst,
-                                                    const Tables& tb, const Dims& dm) {
+// Returns this thread's max over its bins of |Re| + |Im|.
+__device__ __forceinline__ float store_real_spectrum(const float2* buf, float2* __restrict__ dst,
+                                                     const Tables& tb, const Dims& dm) {
+  float mx = 0.f;
   for (int k = threadIdx.x; k < dm.nf; k += kBlock) {
     const float2 z = buf[k];
     float2 zc = buf[k == 0 ? 0 : dm.nh - k];
@@ -57,8 +59,11 @@ __device__ __forceinline__ void store_real_spectrum(const float2* buf, float2* _
     const float2 ze = make_float2(0.5f * (z.x + zc.x), 0.5f * (z.y + zc.y));
     const float2 dz = make_float2(0.5f * (z.x - zc.x), 0.5f * (z.y - zc.y));
     const float2 zo = make_float2(dz.y, -dz.x);  // dz / i
-    dst[k] = cadd(ze, cmul(tb.tw_real[k], zo));
+    const float2 X = cadd(ze, cmul(tb.tw_real[k], zo));
+    dst[k] = X;
+    mx = fmaxf(mx, fabsf(X.x) + fabsf(X.y));
   }
+  return mx;
 }
 
 // Packed spectrum Z for the inverse real DFT of X[0..N/2-1] (Im X[0] and the
@@ -226,10 +231,10 @@ __global__ __launch_bounds__(kBlock) void k_data_c2r(const float2* __restrict__ 
 }
 
 // Transpose of step 5 then the forward real DFT (the data side of L^T).
-// tr_l1[n] = sum |x| of the stretched trace (bounds |Dh[n,f]| for the spreading scale).
+// tr_bound[n] = max_f (|Re Dh[n,f]| + |Im Dh[n,f]|) (the spreading scale bound).
 __global__ __launch_bounds__(kBlock) void k_data_r2c(const float* __restrict__ d,
                                                      float2* __restrict__ dhat,
-                                                     float* __restrict__ tr_l1, Tables tb, Dims dm,
+                                                     float* __restrict__ tr_bound, Tables tb, Dims dm,
                                                      FftPlan fp) {
   extern __shared__ float2 lds[];
   __shared__ float red[kBlock / 64];
@@ -240,12 +245,11 @@ __global__ __launch_bounds__(kBlock) void k_data_r2c(const float* __restrict__ d
   const float* src = d + n * dm.nt;
   for (int s = threadIdx.x; s < dm.nt; s += kBlock) g[s] = src[s];
   __syncthreads();
-  const float l1 = pack_from_csr(A, g, tb.ut_ptr, tb.ut_idx, tb.ut_w, dm.nts, dm.nh);
-  const float l1s = block_sum<kBlock>(l1, red);
-  if (threadIdx.x == 0) tr_l1[n] = l1s;
+  pack_from_csr(A, g, tb.ut_ptr, tb.ut_idx, tb.ut_w, dm.nts, dm.nh);
   __syncthreads();
   const float2* X = fft_lds<false, kBlock>(A, B, fp, 1, dm.nh, tb.tw_half);
-  store_real_spectrum(X, dhat + n * dm.nf, tb, dm);
+  const float mx = block_max<kBlock>(store_real_spectrum(X, dhat + n * dm.nf, tb, dm), red);
+  if (threadIdx.x == 0) tr_bound[n] = mx;
 }
 
 // Solver data side, in place on dhat[n]: r = d_obs - S^-1 F1^-1 Dh (steps 4-5),
@@ -253,7 +257,7 @@ __global__ __launch_bounds__(kBlock) void k_data_r2c(const float* __restrict__ d
 __global__ __launch_bounds__(kBlock) void k_residual_r2c(float2* __restrict__ dhat,
                                                          const float* __restrict__ dobs,
                                                          float* __restrict__ rss,
-                                                         float* __restrict__ tr_l1, Tables tb,
+                                                         float* __restrict__ tr_bound, Tables tb,
                                                          Dims dm, FftPlan fp) {
   extern __shared__ float2 lds[];
   __shared__ float red[kBlock / 64];
@@ -277,12 +281,11 @@ __global__ __launch_bounds__(kBlock) void k_residual_r2c(float2* __restrict__ dh
     ss += r * r;
   }
   __syncthreads();
-  const float l1 = pack_from_csr(X, g, tb.ut_ptr, tb.ut_idx, tb.ut_w, dm.nts, dm.nh);
-  const float l1s = block_sum<kBlock>(l1, red);
-  if (threadIdx.x == 0) tr_l1[n] = l1s;
+  pack_from_csr(X, g, tb.ut_ptr, tb.ut_idx, tb.ut_w, dm.nts, dm.nh);
   __syncthreads();
   const float2* Z = fft_lds<false, kBlock>(X, Y, fp, 1, dm.nh, tb.tw_half);
-  store_real_spectrum(Z, dhat + n * dm.nf, tb, dm);
+  const float mx = block_max<kBlock>(store_real_spectrum(Z, dhat + n * dm.nf, tb, dm), red);
+  if (threadIdx.x == 0) tr_bound[n] = mx;
   if (rss) {
     const float t = block_sum<kBlock>(ss, red);
     if (threadIdx.x == 0) rss[n] = t;
@@ -292,48 +295,54 @@ __global__ __launch_bounds__(kBlock) void k_residual_r2c(float2* __restrict__ dh
 // ------------------------------------------------------------------ GFST stage
 // Each workgroup owns one gather b and a tile of ft consecutive frequencies.
 // The oversampled q-grid of one azimuth slice for all ft frequencies lives in
-// LDS as [ft][mg+1] (one pad element against bank conflicts).  Slices are
-// visited in azimuth order; traces are grouped by their lower azimuth bin j_n,
-// so bin j needs slices j and j+1 (mod ntheta).  Slot use: slice 0 stays in
-// slot 0 (the last bin wraps onto it); slice s >= 1 uses slot 1 + ((s-1) & 1);
-// one more slot is the FFT ping-pong scratch.  Per-trace tables of a bin are
-// staged in LDS in chunks of kStageTraces traces.
-
-__device__ __forceinline__ int slot_of(int s) { return s == 0 ? 0 : 1 + ((s - 1) & 1); }
+// LDS as ft rows of ldr complex cells: mg grid cells, then w-1 ghost cells that
+// repeat the first w-1 cells (periodic extension, so a kernel footprint never
+// wraps), then padding to an odd row length (rows of one access fall in
+// distinct LDS banks).  Slices are visited in azimuth order; traces are grouped
+// by their lower azimuth bin j_n, so bin j needs slices j and j+1 (mod ntheta).
+// Per-trace tables of a bin are staged in LDS in chunks of kStageTraces traces.
+//
+// Phases use 0.64 fixed point: frac(f b) for an integer frequency index f is the
+// wrapped 64-bit product, of which only the top 32 bits are formed
+// (f * b_hi + umulhi(f, b_lo)); the grid position u = mg * frac(f b) keeps 32
+// fractional bits before its conversion to FP32.
 
 struct KernelPoint {
-  int base;      // first grid index touched (may be negative before wrapping)
-  float d0;      // distance from the point to the first tap, in grid units
+  int base;   // first grid cell of the footprint, in [0, mg)
+  float z0;   // 2 d0 / w, d0 = distance from the point to the first cell
 };
 
-// Fixed-point position u = mg * frac(f * b) split into integer and fraction.
-__device__ __forceinline__ KernelPoint kernel_point(unsigned long long f, unsigned long long bfix,
-                                                    int mg, int w) {
-  const unsigned long long t = f * bfix;              // frac(f b) in 0.64 fixed point (exact wrap)
-  const unsigned long long u = (t >> 32) * (unsigned long long)mg;  // u in 32.32 fixed point
+template <int W>
+__device__ __forceinline__ KernelPoint kernel_point(unsigned f, unsigned long long bfix, int mg) {
+  const unsigned t32 = f * (unsigned)(bfix >> 32) + __umulhi(f, (unsigned)bfix);
+  const unsigned long long u = (unsigned long long)t32 * (unsigned)mg;
   const int ui = (int)(u >> 32);
-  const float uf = (float)(unsigned int)(u & 0xffffffffull) * 2.3283064365386963e-10f;
-  const int off = (int)floorf(uf - 0.5f * (float)w);
+  const float uf = (float)(unsigned)u * 2.3283064365386963e-10f;
+  int off;
+  if (W % 2 == 0) off = -W / 2;
+  else off = uf < 0.5f ? -(W + 1) / 2 : -(W - 1) / 2;
   KernelPoint kp;
-  kp.base = ui + off + 1;
-  kp.d0 = uf - (float)(off + 1);
+  int base = ui + off + 1;
+  kp.base = base < 0 ? base + mg : base;
+  kp.z0 = (uf - (float)(off + 1)) * (2.0f / (float)W);
   return kp;
 }
 
-// exp(-2 pi i frac(f a)) (sign = -1) or its conjugate (sign = +1).
-__device__ __forceinline__ float2 pre_phase(unsigned long long f, unsigned long long afix, float sign) {
-  const unsigned long long p = f * afix;
-  float rev = (float)(unsigned int)(p >> 40) * 5.9604644775390625e-08f;  // 2^-24
+// exp(-2 pi i frac(f a)) (SIGN = -1) or its conjugate (SIGN = +1), with the
+// hardware sine and cosine, whose argument is in revolutions.
+template <int SIGN>
+__device__ __forceinline__ float2 pre_phase(unsigned f, unsigned long long afix) {
+  const unsigned p32 = f * (unsigned)(afix >> 32) + __umulhi(f, (unsigned)afix);
+  float rev = (float)(p32 >> 8) * 5.9604644775390625e-08f;  // 24 bits, 2^-24
   if (rev >= 0.5f) rev -= 1.0f;
-  float s, c;
-  sincospif(2.0f * rev, &s, &c);
-  return make_float2(c, sign * s);
+  return make_float2(__builtin_amdgcn_cosf(rev), (float)SIGN * __builtin_amdgcn_sinf(rev));
 }
 
-__device__ __forceinline__ float es_kernel(float dist, float inv_half_w, float beta) {
-  const float z = dist * inv_half_w;
-  const float q = fmaxf(1.0f - z * z, 0.0f);
-  return __expf(beta * (__builtin_amdgcn_sqrtf(q) - 1.0f));
+// Exponential-of-semicircle kernel at normalised distance z = 2 d / w:
+// exp(beta (sqrt(1 - z^2) - 1)) = exp2(cbeta sqrt(1 - z^2) - cbeta), cbeta = beta log2(e).
+__device__ __forceinline__ float es_tap(float z, float cbeta) {
+  const float q = fmaxf(fmaf(-z, z, 1.0f), 0.0f);
+  return __builtin_amdgcn_exp2f(fmaf(cbeta, __builtin_amdgcn_sqrtf(q), -cbeta));
 }
 
 // Logical tile index with consecutive tiles (same gather) on one XCD: the
@@ -349,10 +358,10 @@ struct Stage {
   unsigned long long* a;
   float* alpha;
   int* row;
-  float2* dv;  // spread only: [kStageTraces][ft]
+  float2* dv;  // spreading only: [kStageTraces][ft]
 };
 
-__device__ __forceinline__ Stage stage_at(float2* base, int ft) {
+__device__ __forceinline__ Stage stage_at(float2* base) {
   Stage st;
   st.b = reinterpret_cast<unsigned long long*>(base);
   st.a = st.b + kStageTraces;
@@ -362,12 +371,23 @@ __device__ __forceinline__ Stage stage_at(float2* base, int ft) {
   return st;
 }
 
-// Forward q-grid of slice s: g[f][m] = sum_k c_k exp(-2 pi i k m/mg), c_k = Mh[b][s][k + nq/2][f0+f].
+__device__ __forceinline__ void stage_tables(const Stage& st, const Tables& tb, int c0, int cnt) {
+  for (int t = threadIdx.x; t < cnt; t += kBlockG) {
+    st.b[t] = tb.tr_b[c0 + t];
+    st.a[t] = tb.tr_a[c0 + t];
+    st.alpha[t] = tb.tr_alpha[c0 + t];
+    st.row[t] = tb.tr_row[c0 + t];
+  }
+}
+
+// Forward q-grid of slice s: g[f][m] = sum_k c_k exp(-2 pi i k m/mg), c_k = Mh[b][s][k + nq/2][f0+f],
+// then the ghost cells g[f][mg + t] = g[f][t], t < W - 1.
+template <int W>
 __device__ void build_grid(float2* G, float2* scratch, const float2* __restrict__ mhat_slice, int f0,
                            const Tables& tb, const Dims& dm, const FftPlan& fpg, int ftl) {
-  const int ld = dm.mg + 1;
+  const int ldr = dm.ldr;
   const int ft = dm.ft;
-  for (int i = threadIdx.x; i < ft * ld; i += kBlockG) G[i] = make_float2(0.f, 0.f);
+  for (int i = threadIdx.x; i < ft * ldr; i += kBlockG) G[i] = make_float2(0.f, 0.f);
   __syncthreads();
   for (int it = threadIdx.x; it < dm.nq * ft; it += kBlockG) {
     const int l = it >> ftl;
@@ -377,26 +397,32 @@ __device__ void build_grid(float2* G, float2* scratch, const float2* __restrict_
     if (f < dm.nf) c = mhat_slice[(size_t)l * dm.nf + f];
     int m = l - dm.qhalf;
     if (m < 0) m += dm.mg;
-    G[fl * ld + m] = c;
+    G[fl * ldr + m] = c;
   }
   __syncthreads();
-  const float2* R = fft_lds<false, kBlockG>(G, scratch, fpg, ft, ld, tb.tw_grid);
+  const float2* R = fft_lds<false, kBlockG>(G, scratch, fpg, ft, ldr, tb.tw_grid);
   if (R != G) {
-    for (int i = threadIdx.x; i < ft * ld; i += kBlockG) G[i] = R[i];
+    for (int i = threadIdx.x; i < ft * ldr; i += kBlockG) G[i] = R[i];
     __syncthreads();
   }
+  for (int i = threadIdx.x; i < ft * (W - 1); i += kBlockG) {
+    const int fl = i / (W - 1), t = i - fl * (W - 1);
+    G[fl * ldr + dm.mg + t] = G[fl * ldr + t];
+  }
+  __syncthreads();
 }
 
+template <int W>
 __global__ __launch_bounds__(kBlockG) void k_nufft_interp(const float2* __restrict__ mhat,
                                                           float2* __restrict__ dhat, Tables tb,
                                                           Dims dm, FftPlan fpg, int ftl) {
   extern __shared__ float2 lds[];
-  const int ld = dm.mg + 1;
+  const int ldr = dm.ldr;
   const int ft = dm.ft;
-  const int slot_sz = ft * ld;
+  const int slot_sz = ft * ldr;
   const int nslot = dm.ntheta >= 3 ? 3 : dm.ntheta;
   float2* scratch = lds + nslot * slot_sz;
-  const Stage st = stage_at(scratch + slot_sz, ft);
+  const Stage st = stage_at(scratch + slot_sz);
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int b = tile / dm.nftile;
   const int f0 = (tile - b * dm.nftile) * ft;
@@ -404,85 +430,78 @@ __global__ __launch_bounds__(kBlockG) void k_nufft_interp(const float2* __restri
   const size_t slice_stride = (size_t)dm.nq * dm.nf;
   const float2* mb = mhat + (size_t)b * dm.ntheta * slice_stride;
   if (bp[dm.ntheta] == bp[0]) return;  // empty gather: nothing to write
-  const float ihw = 2.0f / (float)dm.w;
+  // slice 0 stays in slot 0 (the last bin wraps onto it); slice s >= 1 uses slot 1 + ((s-1) & 1)
+  auto slot_of = [](int s) { return s == 0 ? 0 : 1 + ((s - 1) & 1); };
 
-  build_grid(lds, scratch, mb, f0, tb, dm, fpg, ftl);
-  if (dm.ntheta > 1) build_grid(lds + slot_sz, scratch, mb + slice_stride, f0, tb, dm, fpg, ftl);
+  build_grid<W>(lds, scratch, mb, f0, tb, dm, fpg, ftl);
+  if (dm.ntheta > 1) build_grid<W>(lds + slot_sz, scratch, mb + slice_stride, f0, tb, dm, fpg, ftl);
   for (int j = 0; j < dm.ntheta; ++j) {
     const int j1 = (j + 1 == dm.ntheta) ? 0 : j + 1;
     const float2* G0 = lds + slot_of(j) * slot_sz;
     const float2* G1 = lds + slot_of(j1) * slot_sz;
     for (int c0 = bp[j]; c0 < bp[j + 1]; c0 += kStageTraces) {
       const int cnt = min(kStageTraces, bp[j + 1] - c0);
-      for (int t = threadIdx.x; t < cnt; t += kBlockG) {
-        st.b[t] = tb.tr_b[c0 + t];
-        st.a[t] = tb.tr_a[c0 + t];
-        st.alpha[t] = tb.tr_alpha[c0 + t];
-        st.row[t] = tb.tr_row[c0 + t];
-      }
+      stage_tables(st, tb, c0, cnt);
       __syncthreads();
       for (int it = threadIdx.x; it < cnt * ft; it += kBlockG) {
         const int ti = it >> ftl;
         const int fl = it & (ft - 1);
-        const int f = f0 + fl;
-        if (f >= dm.nf) continue;
-        const KernelPoint kp = kernel_point((unsigned long long)f, st.b[ti], dm.mg, dm.w);
-        const float alpha = st.alpha[ti];
+        const unsigned f = (unsigned)(f0 + fl);
+        if (f >= (unsigned)dm.nf) continue;
+        const KernelPoint kp = kernel_point<W>(f, st.b[ti], dm.mg);
+        const float2* g0 = G0 + fl * ldr + kp.base;
+        const float2* g1 = G1 + fl * ldr + kp.base;
         float2 a0 = make_float2(0.f, 0.f), a1 = make_float2(0.f, 0.f);
-        int m = kp.base;
-        if (m < 0) m += dm.mg;
-        const float2* g0 = G0 + fl * ld;
-        const float2* g1 = G1 + fl * ld;
-        for (int t = 0; t < dm.w; ++t) {
-          const float ph = es_kernel(kp.d0 - (float)t, ihw, dm.beta);
-          const float2 v0 = g0[m], v1 = g1[m];
-          a0.x += ph * v0.x;
-          a0.y += ph * v0.y;
-          a1.x += ph * v1.x;
-          a1.y += ph * v1.y;
-          m = (m + 1 == dm.mg) ? 0 : m + 1;
+#pragma unroll
+        for (int t = 0; t < W; ++t) {
+          const float ph = es_tap(fmaf((float)t, -2.0f / (float)W, kp.z0), dm.cbeta);
+          const float2 v0 = g0[t], v1 = g1[t];
+          a0.x = fmaf(ph, v0.x, a0.x);
+          a0.y = fmaf(ph, v0.y, a0.y);
+          a1.x = fmaf(ph, v1.x, a1.x);
+          a1.y = fmaf(ph, v1.y, a1.y);
         }
-        const float2 v = make_float2((1.f - alpha) * a0.x + alpha * a1.x,
-                                     (1.f - alpha) * a0.y + alpha * a1.y);
-        const float2 e = pre_phase((unsigned long long)f, st.a[ti], -1.0f);
-        dhat[(size_t)st.row[ti] * dm.nf + f] = cmul(v, e);
+        const float alpha = st.alpha[ti];
+        const float2 v = make_float2(fmaf(alpha, a1.x - a0.x, a0.x), fmaf(alpha, a1.y - a0.y, a0.y));
+        dhat[(size_t)st.row[ti] * dm.nf + f] = cmul(v, pre_phase<-1>(f, st.a[ti]));
       }
       __syncthreads();
     }
     if (j + 2 < dm.ntheta)
-      build_grid(lds + slot_of(j + 2) * slot_sz, scratch, mb + (size_t)(j + 2) * slice_stride, f0, tb,
-                 dm, fpg, ftl);
+      build_grid<W>(lds + slot_of(j + 2) * slot_sz, scratch, mb + (size_t)(j + 2) * slice_stride, f0, tb,
+                    dm, fpg, ftl);
   }
 }
 
-// Type-1 spreading accumulates in LDS as 64-bit fixed point: every contribution
-// c is added as round(c * S) with S = 2^50 / B_b, where B_b = sum over the
-// gather's traces of the L1 norm of the stretched trace bounds every |Dh[n,f]|
-// and therefore every grid cell (the kernel and the azimuth weights are <= 1).
-// Integer adds are exact and order independent, so the result is deterministic
-// and the rounding error is below 2^-50 B_b per contribution.
-__device__ __forceinline__ long long to_fix(double scaled_c) {
-  // round-to-nearest integer of a double with |x| < 2^51: add 1.5*2^52 and read the low bits
-  const double t = scaled_c + 6755399441055744.0;
-  return __double_as_longlong(t) - 0x4338000000000000LL;
+// Type-1 spreading accumulates in LDS in fixed point: a complex contribution c
+// is added as one 64-bit integer round(S Re c) + 2^32 round(S Im c).  Integer
+// addition is exact and order independent (deterministic results), and the
+// two 32-bit fields can be read back exactly while each partial sum stays
+// below 2^31 in magnitude, which the scale guarantees: S = 0.99 (2^31 - 1)/B_b
+// with B_b = sum over the gather's traces of max_f (|Re Dh| + |Im Dh|), an
+// upper bound of every cell sum (the kernel and the azimuth weights are <= 1).
+__device__ __forceinline__ unsigned long long pack_fix(float x, float y) {
+  const int a = __float2int_rn(x), b = __float2int_rn(y);
+  return (unsigned long long)(long long)a + ((unsigned long long)(unsigned)b << 32);
 }
 
-// One azimuth bin into the fixed-point slots lo (weight 1 - alpha, slice j) and
-// hi (weight alpha, slice j+1); a null slot is skipped.
-__device__ void spread_bin(long long* lo, long long* hi, int c_begin, int c_end,
-                           const float2* __restrict__ dhat, const Stage& st, int f0, double S,
+__device__ __forceinline__ float2 unpack_fix(unsigned long long v, float inv_s) {
+  const int lo = (int)(unsigned)v;
+  const int hi = (int)(unsigned)((v - (unsigned long long)(long long)lo) >> 32);
+  return make_float2((float)lo * inv_s, (float)hi * inv_s);
+}
+
+// One azimuth bin into the slots lo (weight 1 - alpha, slice j) and hi (weight
+// alpha, slice j+1); a null slot is skipped.
+template <int W>
+__device__ void spread_bin(unsigned long long* lo, unsigned long long* hi, int c_begin, int c_end,
+                           const float2* __restrict__ dhat, const Stage& st, int f0, float S,
                            const Tables& tb, const Dims& dm, int ftl) {
-  const int ld = dm.mg + 1;
+  const int ldr = dm.ldr;
   const int ft = dm.ft;
-  const float ihw = 2.0f / (float)dm.w;
   for (int c0 = c_begin; c0 < c_end; c0 += kStageTraces) {
     const int cnt = min(kStageTraces, c_end - c0);
-    for (int t = threadIdx.x; t < cnt; t += kBlockG) {
-      st.b[t] = tb.tr_b[c0 + t];
-      st.a[t] = tb.tr_a[c0 + t];
-      st.alpha[t] = tb.tr_alpha[c0 + t];
-      st.row[t] = tb.tr_row[c0 + t];
-    }
+    stage_tables(st, tb, c0, cnt);
     __syncthreads();
     for (int it = threadIdx.x; it < cnt * ft; it += kBlockG) {
       const int ti = it >> ftl;
@@ -493,70 +512,54 @@ __device__ void spread_bin(long long* lo, long long* hi, int c_begin, int c_end,
     for (int it = threadIdx.x; it < cnt * ft; it += kBlockG) {
       const int ti = it >> ftl;
       const int fl = it & (ft - 1);
-      const int f = f0 + fl;
-      if (f >= dm.nf) continue;
-      const float2 s = cmul(st.dv[it], pre_phase((unsigned long long)f, st.a[ti], 1.0f));
-      const KernelPoint kp = kernel_point((unsigned long long)f, st.b[ti], dm.mg, dm.w);
-      const double alpha = st.alpha[ti];
-      const double s0x = (1.0 - alpha) * S * s.x, s0y = (1.0 - alpha) * S * s.y;
-      const double s1x = alpha * S * s.x, s1y = alpha * S * s.y;
-      int m = kp.base;
-      if (m < 0) m += dm.mg;
-      unsigned long long* g0 = reinterpret_cast<unsigned long long*>(lo ? lo + 2 * fl * ld : nullptr);
-      unsigned long long* g1 = reinterpret_cast<unsigned long long*>(hi ? hi + 2 * fl * ld : nullptr);
-      for (int t = 0; t < dm.w; ++t) {
-        const double ph = (double)es_kernel(kp.d0 - (float)t, ihw, dm.beta);
-        if (g0) {
-          atomicAdd(g0 + 2 * m, (unsigned long long)to_fix(ph * s0x));
-          atomicAdd(g0 + 2 * m + 1, (unsigned long long)to_fix(ph * s0y));
-        }
-        if (g1) {
-          atomicAdd(g1 + 2 * m, (unsigned long long)to_fix(ph * s1x));
-          atomicAdd(g1 + 2 * m + 1, (unsigned long long)to_fix(ph * s1y));
-        }
-        m = (m + 1 == dm.mg) ? 0 : m + 1;
+      const unsigned f = (unsigned)(f0 + fl);
+      if (f >= (unsigned)dm.nf) continue;
+      const float2 s = cmul(st.dv[it], pre_phase<1>(f, st.a[ti]));
+      const KernelPoint kp = kernel_point<W>(f, st.b[ti], dm.mg);
+      const float alpha = st.alpha[ti];
+      const float2 s1 = cscale(s, alpha * S);
+      const float2 s0 = cscale(s, (1.0f - alpha) * S);
+      unsigned long long* g0 = lo ? lo + fl * ldr + kp.base : nullptr;
+      unsigned long long* g1 = hi ? hi + fl * ldr + kp.base : nullptr;
+#pragma unroll
+      for (int t = 0; t < W; ++t) {
+        const float ph = es_tap(fmaf((float)t, -2.0f / (float)W, kp.z0), dm.cbeta);
+        if (g0) atomicAdd(g0 + t, pack_fix(ph * s0.x, ph * s0.y));
+        if (g1) atomicAdd(g1 + t, pack_fix(ph * s1.x, ph * s1.y));
       }
     }
     __syncthreads();
   }
 }
 
-// Decode a fixed-point slot to FP32 (in place: the first half of the slot
-// becomes [ft][mg+1] complex), inverse q-grid FFT (the second half is the
-// ping-pong buffer): H[k] = sum_m G[m] exp(+2 pi i k m/mg) for the nq modes,
-// written to Mh[b][s][k + nq/2][f0 + f]; the slot is cleared afterwards.
-__device__ void finish_slot(long long* slot, float2* __restrict__ out_slice, int f0, double inv_s,
-                            const Tables& tb, const Dims& dm, const FftPlan& fpg, int ftl) {
-  const int ld = dm.mg + 1;
+// Fold the ghost cells back, decode the slot in place to FP32, inverse q-grid
+// FFT: H[k] = sum_m G[m] exp(+2 pi i k m/mg) for the nq modes, written to
+// Mh[b][s][k + nq/2][f0 + f]; the slot is cleared afterwards.
+template <int W>
+__device__ void finish_slot(unsigned long long* slot, float2* scratch, float2* __restrict__ out_slice,
+                            int f0, float inv_s, const Tables& tb, const Dims& dm, const FftPlan& fpg,
+                            int ftl) {
+  const int ldr = dm.ldr;
   const int ft = dm.ft;
-  const int cells = ft * ld;
-  constexpr int kPer = kDecodePer;  // cells per thread held in registers during the decode
-  float2 v[kPer];
-#pragma unroll
-  for (int k = 0; k < kPer; ++k) {
-    const int i = threadIdx.x + k * kBlockG;
-    if (i < cells) v[k] = make_float2((float)((double)slot[2 * i] * inv_s), (float)((double)slot[2 * i + 1] * inv_s));
+  for (int i = threadIdx.x; i < ft * (W - 1); i += kBlockG) {
+    const int fl = i / (W - 1), t = i - fl * (W - 1);
+    slot[fl * ldr + t] += slot[fl * ldr + dm.mg + t];
   }
   __syncthreads();
   float2* P = reinterpret_cast<float2*>(slot);
-  float2* Q = P + cells;
-#pragma unroll
-  for (int k = 0; k < kPer; ++k) {
-    const int i = threadIdx.x + k * kBlockG;
-    if (i < cells) P[i] = v[k];
-  }
+  for (int i = threadIdx.x; i < ft * ldr; i += kBlockG) P[i] = unpack_fix(slot[i], inv_s);
   __syncthreads();
-  const float2* R = fft_lds<true, kBlockG>(P, Q, fpg, ft, ld, tb.tw_grid);
+  const float2* R = fft_lds<true, kBlockG>(P, scratch, fpg, ft, ldr, tb.tw_grid);
   for (int it = threadIdx.x; it < dm.nq * ft; it += kBlockG) {
     const int l = it >> ftl;
     const int fl = it & (ft - 1);
     const int f = f0 + fl;
     int m = l - dm.qhalf;
     if (m < 0) m += dm.mg;
-    if (f < dm.nf) out_slice[(size_t)l * dm.nf + f] = R[fl * ld + m];
+    if (f < dm.nf) out_slice[(size_t)l * dm.nf + f] = R[fl * ldr + m];
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < 2 * cells; i += kBlockG) slot[i] = 0;
+  for (int i = threadIdx.x; i < ft * ldr; i += kBlockG) slot[i] = 0ull;
   __syncthreads();
 }
 
@@ -564,19 +567,21 @@ __device__ void finish_slot(long long* slot, float2* __restrict__ out_slice, int
 // s & 1.  The wrap bin ntheta-1 is spread twice, its upper part into slice 0
 // before the sweep and its lower part into slice ntheta-1 at the end, so no
 // slice has to stay resident across the whole sweep.
+template <int W>
 __global__ __launch_bounds__(kBlockG) void k_nufft_spread(const float2* __restrict__ dhat,
-                                                          const float* __restrict__ tr_l1,
+                                                          const float* __restrict__ tr_bound,
                                                           const int64_t* __restrict__ trace_ptr,
                                                           float2* __restrict__ mhat, Tables tb,
                                                           Dims dm, FftPlan fpg, int ftl) {
   extern __shared__ float2 lds[];
   __shared__ float red[kBlockG / 64];
-  __shared__ double scale_sh;
-  const int ld = dm.mg + 1;
+  __shared__ float scale_sh;
   const int ft = dm.ft;
-  const int cells = ft * ld;
-  long long* slots = reinterpret_cast<long long*>(lds);  // 2 slots x cells x (re, im)
-  const Stage st = stage_at(lds + 4 * cells, ft);
+  const int slot_sz = ft * dm.ldr;
+  unsigned long long* slot0 = reinterpret_cast<unsigned long long*>(lds);
+  unsigned long long* slot1 = slot0 + slot_sz;
+  float2* scratch = lds + 2 * slot_sz;
+  const Stage st = stage_at(scratch + slot_sz);
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int b = tile / dm.nftile;
   const int f0 = (tile - b * dm.nftile) * ft;
@@ -585,27 +590,25 @@ __global__ __launch_bounds__(kBlockG) void k_nufft_spread(const float2* __restri
   float2* mb = mhat + (size_t)b * dm.ntheta * slice_stride;
 
   float part = 0.f;
-  for (int64_t n = trace_ptr[b] + threadIdx.x; n < trace_ptr[b + 1]; n += kBlockG) part += tr_l1[n];
+  for (int64_t n = trace_ptr[b] + threadIdx.x; n < trace_ptr[b + 1]; n += kBlockG) part += tr_bound[n];
   const float bsum = block_sum<kBlockG>(part, red);
-  if (threadIdx.x == 0) scale_sh = bsum > 0.f ? 1125899906842624.0 / (double)bsum : 1.0;  // 2^50 / B
-  for (int i = threadIdx.x; i < 4 * cells; i += kBlockG) slots[i] = 0;
+  if (threadIdx.x == 0) scale_sh = bsum > 0.f ? 0.99f * 2147483647.0f / bsum : 1.0f;
+  for (int i = threadIdx.x; i < 2 * slot_sz; i += kBlockG) slot0[i] = 0ull;
   __syncthreads();
-  const double S = scale_sh;
-  const double inv_s = 1.0 / S;
-  long long* slot0 = slots;
-  long long* slot1 = slots + 2 * cells;
+  const float S = scale_sh;
+  const float inv_s = 1.0f / S;
   const int last = dm.ntheta - 1;
 
-  spread_bin(nullptr, slot0, bp[last], bp[last + 1], dhat, st, f0, S, tb, dm, ftl);
+  spread_bin<W>(nullptr, slot0, bp[last], bp[last + 1], dhat, st, f0, S, tb, dm, ftl);
   for (int j = 0; j < last; ++j) {
-    long long* sj = (j & 1) ? slot1 : slot0;
-    long long* sn = (j & 1) ? slot0 : slot1;
-    spread_bin(sj, sn, bp[j], bp[j + 1], dhat, st, f0, S, tb, dm, ftl);
-    finish_slot(sj, mb + (size_t)j * slice_stride, f0, inv_s, tb, dm, fpg, ftl);
+    unsigned long long* sj = (j & 1) ? slot1 : slot0;
+    unsigned long long* sn = (j & 1) ? slot0 : slot1;
+    spread_bin<W>(sj, sn, bp[j], bp[j + 1], dhat, st, f0, S, tb, dm, ftl);
+    finish_slot<W>(sj, scratch, mb + (size_t)j * slice_stride, f0, inv_s, tb, dm, fpg, ftl);
   }
-  long long* sl = (last & 1) ? slot1 : slot0;
-  spread_bin(sl, nullptr, bp[last], bp[last + 1], dhat, st, f0, S, tb, dm, ftl);
-  finish_slot(sl, mb + (size_t)last * slice_stride, f0, inv_s, tb, dm, fpg, ftl);
+  unsigned long long* sl = (last & 1) ? slot1 : slot0;
+  spread_bin<W>(sl, nullptr, bp[last], bp[last + 1], dhat, st, f0, S, tb, dm, ftl);
+  finish_slot<W>(sl, scratch, mb + (size_t)last * slice_stride, f0, inv_s, tb, dm, fpg, ftl);
 }
 
 // ------------------------------------------------------------------ small kernels
@@ -700,15 +703,13 @@ __global__ void k_objective(const float* __restrict__ rss, const int64_t* __rest
 // ------------------------------------------------------------------ launchers
 static size_t row_lds_bytes(const Dims& dm) { return 2 * (size_t)dm.nh * sizeof(float2); }
 
-static size_t grid_lds_bytes(const Dims& dm) {
+static size_t interp_lds_bytes(const Dims& dm) {
   const int nslot = (dm.ntheta >= 3 ? 3 : dm.ntheta) + 1;
-  return (size_t)nslot * dm.ft * (dm.mg + 1) * sizeof(float2) +
-         (size_t)kStageTraces * (24 + dm.ft * sizeof(float2));
+  return (size_t)nslot * dm.ft * dm.ldr * sizeof(float2) + (size_t)kStageTraces * (24 + dm.ft * sizeof(float2));
 }
 
 static size_t spread_lds_bytes(const Dims& dm) {
-  return 2 * (size_t)dm.ft * (dm.mg + 1) * 2 * sizeof(long long) +
-         (size_t)kStageTraces * (24 + dm.ft * sizeof(float2));
+  return 3 * (size_t)dm.ft * dm.ldr * sizeof(float2) + (size_t)kStageTraces * (24 + dm.ft * sizeof(float2));
 }
 
 static int ilog2(int v) {
@@ -772,7 +773,7 @@ hipError_t launch_data_r2c(const Plan& p, const float* d, float2* dhat, hipStrea
   const size_t lds = row_lds_bytes(dm);
   hipError_t e = set_lds(k_data_r2c, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_data_r2c, dim3(dm.ntr), dim3(kBlock), lds, s, d, dhat, p.tr_l1, p.tb, dm,
+  hipLaunchKernelGGL(k_data_r2c, dim3(dm.ntr), dim3(kBlock), lds, s, d, dhat, p.tr_bound, p.tb, dm,
                      p.fft_half);
   return hipGetLastError();
 }
@@ -784,29 +785,53 @@ hipError_t launch_residual_r2c(const Plan& p, float2* dhat, const float* dobs, f
   const size_t lds = row_lds_bytes(dm);
   hipError_t e = set_lds(k_residual_r2c, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_residual_r2c, dim3(dm.ntr), dim3(kBlock), lds, s, dhat, dobs, rss, p.tr_l1,
+  hipLaunchKernelGGL(k_residual_r2c, dim3(dm.ntr), dim3(kBlock), lds, s, dhat, dobs, rss, p.tr_bound,
                      p.tb, dm, p.fft_half);
   return hipGetLastError();
 }
 
+#define AAHRT_W_CASES(MACRO) \
+  MACRO(3) MACRO(4) MACRO(5) MACRO(6) MACRO(7) MACRO(8) MACRO(9) MACRO(10) MACRO(11) MACRO(12)
+
 hipError_t launch_nufft_interp(const Plan& p, const float2* mhat, float2* dhat, hipStream_t s) {
   const Dims& dm = p.dm;
   if (dm.ntr == 0) return hipSuccess;
-  const size_t lds = grid_lds_bytes(dm);
-  hipError_t e = set_lds(k_nufft_interp, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_nufft_interp, dim3((unsigned)dm.batch * dm.nftile), dim3(kBlockG), lds, s,
-                     mhat, dhat, p.tb, dm, p.fft_grid, ilog2(dm.ft));
+  const size_t lds = interp_lds_bytes(dm);
+  const dim3 grid((unsigned)dm.batch * dm.nftile), block(kBlockG);
+  const int ftl = ilog2(dm.ft);
+  switch (dm.w) {
+#define AAHRT_CASE(WW)                                                                       \
+  case WW: {                                                                                 \
+    hipError_t e = set_lds(k_nufft_interp<WW>, lds);                                         \
+    if (e != hipSuccess) return e;                                                           \
+    hipLaunchKernelGGL(k_nufft_interp<WW>, grid, block, lds, s, mhat, dhat, p.tb, dm, p.fft_grid, ftl); \
+    break;                                                                                   \
+  }
+    AAHRT_W_CASES(AAHRT_CASE)
+#undef AAHRT_CASE
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_nufft_spread(const Plan& p, const float2* dhat, float2* mhat, hipStream_t s) {
   const Dims& dm = p.dm;
   const size_t lds = spread_lds_bytes(dm);
-  hipError_t e = set_lds(k_nufft_spread, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_nufft_spread, dim3((unsigned)dm.batch * dm.nftile), dim3(kBlockG), lds, s,
-                     dhat, p.tr_l1, p.trace_ptr_dev, mhat, p.tb, dm, p.fft_grid, ilog2(dm.ft));
+  const dim3 grid((unsigned)dm.batch * dm.nftile), block(kBlockG);
+  const int ftl = ilog2(dm.ft);
+  switch (dm.w) {
+#define AAHRT_CASE(WW)                                                                       \
+  case WW: {                                                                                 \
+    hipError_t e = set_lds(k_nufft_spread<WW>, lds);                                         \
+    if (e != hipSuccess) return e;                                                           \
+    hipLaunchKernelGGL(k_nufft_spread<WW>, grid, block, lds, s, dhat, p.tr_bound, p.trace_ptr_dev, mhat, \
+                       p.tb, dm, p.fft_grid, ftl);                                           \
+    break;                                                                                   \
+  }
+    AAHRT_W_CASES(AAHRT_CASE)
+#undef AAHRT_CASE
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

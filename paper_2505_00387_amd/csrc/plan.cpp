@@ -212,13 +212,14 @@ int validate_params(const aahrt_params& q) {
   return AAHRT_OK;
 }
 
-// LDS of a GFST workgroup: azimuth-slice slots + one FFT scratch slot + staged trace tables
-// (interpolation), or two fixed-point slots of twice the size (spreading); the larger one.
-size_t grid_lds(int ft, int mg, int ntheta) {
+// LDS of a GFST workgroup (rows of ldr cells): interpolation uses up to three
+// azimuth-slice slots + one FFT scratch slot, spreading two fixed-point slots + scratch;
+// both stage per-trace tables.  The larger of the two.
+size_t grid_lds(int ft, int ldr, int ntheta) {
   const int nslot = (ntheta >= 3 ? 3 : ntheta) + 1;
   const size_t stage = (size_t)kStageTraces * (24 + ft * sizeof(float2));
-  const size_t interp = (size_t)nslot * ft * (mg + 1) * sizeof(float2) + stage;
-  const size_t spread = 4 * (size_t)ft * (mg + 1) * sizeof(float2) + stage;
+  const size_t interp = (size_t)nslot * ft * ldr * sizeof(float2) + stage;
+  const size_t spread = 3 * (size_t)ft * ldr * sizeof(float2) + stage;
   return interp > spread ? interp : spread;
 }
 
@@ -276,13 +277,16 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
   P.sigma = (double)mg / dm.nq;
   const double beta = 0.98 * M_PI * (1.0 - 1.0 / (2.0 * P.sigma)) * w;
   dm.beta = (float)beta;
+  dm.cbeta = (float)(beta / std::log(2.0));
+  dm.ldr = mg + w - 1;
+  if (dm.ldr % 2 == 0) dm.ldr += 1;
   dm.qhalf = dm.nq / 2;
 
   // frequency tile
   if (!make_fft_plan(mg, P.fft_grid)) return fail(AAHRT_E_UNSUPPORTED, "q-grid length not 5-smooth");
   int ft = prm.freq_tile == 0 ? 16 : prm.freq_tile;
-  while (ft > 1 && (grid_lds(ft, mg, dm.ntheta) > 160 * 1024 || ft * (mg + 1) > kDecodePer * kBlockG)) ft /= 2;
-  if (grid_lds(ft, mg, dm.ntheta) > 160 * 1024) return fail(AAHRT_E_UNSUPPORTED, "q-grid too large for LDS");
+  while (ft > 1 && grid_lds(ft, dm.ldr, dm.ntheta) > 160 * 1024) ft /= 2;
+  if (grid_lds(ft, dm.ldr, dm.ntheta) > 160 * 1024) return fail(AAHRT_E_UNSUPPORTED, "q-grid too large for LDS");
   dm.ft = ft;
   dm.nftile = (dm.nf + ft - 1) / ft;
   if (2 * (size_t)dm.nh * sizeof(float2) > 160 * 1024 || std::max(dm.nt, dm.ntau) > 2 * dm.nh)
@@ -425,7 +429,7 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
   TRY(alloc(P, (size_t)batch * P.red_blocks_model, &P.red));
   TRY(alloc(P, rows, &P.l1row));
   TRY(alloc(P, (size_t)dm.ntr, &P.rss));
-  TRY(alloc(P, (size_t)dm.ntr, &P.tr_l1));
+  TRY(alloc(P, (size_t)dm.ntr, &P.tr_bound));
   return AAHRT_OK;
 }
 
