@@ -361,6 +361,9 @@ struct Stage {
   float2* dv;  // spreading only: [kStageTraces][ft]
 };
 
+// Two stage buffers (double buffering): stage k starts at base + k * stage_elems(ft).
+__host__ __device__ constexpr int stage_elems(int ft) { return kStageTraces * 3 + kStageTraces * ft; }
+
 __device__ __forceinline__ Stage stage_at(float2* base) {
   Stage st;
   st.b = reinterpret_cast<unsigned long long*>(base);
@@ -371,33 +374,94 @@ __device__ __forceinline__ Stage stage_at(float2* base) {
   return st;
 }
 
-__device__ __forceinline__ void stage_tables(const Stage& st, const Tables& tb, int c0, int cnt) {
-  for (int t = threadIdx.x; t < cnt; t += kBlockG) {
-    st.b[t] = tb.tr_b[c0 + t];
-    st.a[t] = tb.tr_a[c0 + t];
-    st.alpha[t] = tb.tr_alpha[c0 + t];
-    st.row[t] = tb.tr_row[c0 + t];
+// Per-trace tables of one chunk held in registers between their load and their
+// store to LDS (thread t holds trace c0 + t, t < cnt).
+struct TableRegs {
+  unsigned long long b, a;
+  float alpha;
+  int row;
+};
+
+__device__ __forceinline__ void load_tables(TableRegs& r, const Tables& tb, int c0, int cnt) {
+  const int t = threadIdx.x;
+  if (t < cnt) {
+    r.b = tb.tr_b[c0 + t];
+    r.a = tb.tr_a[c0 + t];
+    r.alpha = tb.tr_alpha[c0 + t];
+    r.row = tb.tr_row[c0 + t];
   }
 }
 
-// Forward q-grid of slice s: g[f][m] = sum_k c_k exp(-2 pi i k m/mg), c_k = Mh[b][s][k + nq/2][f0+f],
-// then the ghost cells g[f][mg + t] = g[f][t], t < W - 1.
+__device__ __forceinline__ void store_tables(const Stage& st, const TableRegs& r, int cnt) {
+  const int t = threadIdx.x;
+  if (t < cnt) {
+    st.b[t] = r.b;
+    st.a[t] = r.a;
+    st.alpha[t] = r.alpha;
+    st.row[t] = r.row;
+  }
+}
+
+// Chunks of kStageTraces traces over a sequence of azimuth bins.  Position
+// (step, c0): the chunk starting at trace c0 of the bin visited at `step`;
+// step == nsteps marks the end.
+struct ChunkPos {
+  int step, c0, cnt;
+};
+
+template <typename BinOf>
+__device__ __forceinline__ ChunkPos first_chunk_from(int step, int nsteps, const int* bp, BinOf bin_of) {
+  for (; step < nsteps; ++step) {
+    const int j = bin_of(step);
+    if (bp[j + 1] > bp[j]) return ChunkPos{step, bp[j], min(kStageTraces, bp[j + 1] - bp[j])};
+  }
+  return ChunkPos{nsteps, 0, 0};
+}
+
+template <typename BinOf>
+__device__ __forceinline__ ChunkPos next_chunk(const ChunkPos& c, int nsteps, const int* bp, BinOf bin_of) {
+  const int j = bin_of(c.step);
+  const int c0 = c.c0 + kStageTraces;
+  if (c0 < bp[j + 1]) return ChunkPos{c.step, c0, min(kStageTraces, bp[j + 1] - c0)};
+  return first_chunk_from(c.step + 1, nsteps, bp, bin_of);
+}
+
+constexpr int kCoefRegs = 4;  // q-grid coefficients per thread held while prefetching
+static_assert(kCoefRegs * kBlockG >= kPrefetchCells, "coefficient prefetch capacity");
+
+__device__ __forceinline__ void load_coefs(float2* cr, const float2* __restrict__ mhat_slice, int f0,
+                                           const Dims& dm, int ftl) {
+#pragma unroll
+  for (int k = 0; k < kCoefRegs; ++k) {
+    const int it = threadIdx.x + k * kBlockG;
+    cr[k] = make_float2(0.f, 0.f);
+    if (it < dm.nq * dm.ft) {
+      const int l = it >> ftl;
+      const int f = f0 + (it & (dm.ft - 1));
+      if (f < dm.nf) cr[k] = mhat_slice[(size_t)l * dm.nf + f];
+    }
+  }
+}
+
+// Forward q-grid of one slice from coefficients held in registers:
+// g[f][m] = sum_k c_k exp(-2 pi i k m/mg), then ghost cells g[f][mg + t] = g[f][t], t < W - 1.
 template <int W>
-__device__ void build_grid(float2* G, float2* scratch, const float2* __restrict__ mhat_slice, int f0,
-                           const Tables& tb, const Dims& dm, const FftPlan& fpg, int ftl) {
+__device__ void build_grid(float2* G, float2* scratch, const float2* cr, const Tables& tb, const Dims& dm,
+                           const FftPlan& fpg, int ftl) {
   const int ldr = dm.ldr;
   const int ft = dm.ft;
   for (int i = threadIdx.x; i < ft * ldr; i += kBlockG) G[i] = make_float2(0.f, 0.f);
   __syncthreads();
-  for (int it = threadIdx.x; it < dm.nq * ft; it += kBlockG) {
-    const int l = it >> ftl;
-    const int fl = it & (ft - 1);
-    const int f = f0 + fl;
-    float2 c = make_float2(0.f, 0.f);
-    if (f < dm.nf) c = mhat_slice[(size_t)l * dm.nf + f];
-    int m = l - dm.qhalf;
-    if (m < 0) m += dm.mg;
-    G[fl * ldr + m] = c;
+#pragma unroll
+  for (int k = 0; k < kCoefRegs; ++k) {
+    const int it = threadIdx.x + k * kBlockG;
+    if (it < dm.nq * ft) {
+      const int l = it >> ftl;
+      const int fl = it & (ft - 1);
+      int m = l - dm.qhalf;
+      if (m < 0) m += dm.mg;
+      G[fl * ldr + m] = cr[k];
+    }
   }
   __syncthreads();
   const float2* R = fft_lds<false, kBlockG>(G, scratch, fpg, ft, ldr, tb.tw_grid);
@@ -412,6 +476,12 @@ __device__ void build_grid(float2* G, float2* scratch, const float2* __restrict_
   __syncthreads();
 }
 
+// Type-2 map of one frequency tile: D^[n][f] = e(-f a_n) ((1-alpha_n) g_j(u_n) + alpha_n g_{j+1}(u_n)),
+// g interpolated with the width-W kernel.  Slices are built two bins ahead
+// (slice 0 stays in slot 0 for the wrapping last bin; slice s >= 1 uses slot
+// 1 + ((s-1) & 1)); the q-coefficients of the next slice and the tables of
+// the next chunk are loaded into registers while the current chunk is
+// interpolated.
 template <int W>
 __global__ __launch_bounds__(kBlockG) void k_nufft_interp(const float2* __restrict__ mhat,
                                                           float2* __restrict__ dhat, Tables tb,
@@ -422,7 +492,8 @@ __global__ __launch_bounds__(kBlockG) void k_nufft_interp(const float2* __restri
   const int slot_sz = ft * ldr;
   const int nslot = dm.ntheta >= 3 ? 3 : dm.ntheta;
   float2* scratch = lds + nslot * slot_sz;
-  const Stage st = stage_at(scratch + slot_sz);
+  float2* stage_base = scratch + slot_sz;
+  auto stg = [&](int k) { return stage_at(stage_base + k * stage_elems(ft)); };
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int b = tile / dm.nftile;
   const int f0 = (tile - b * dm.nftile) * ft;
@@ -430,20 +501,34 @@ __global__ __launch_bounds__(kBlockG) void k_nufft_interp(const float2* __restri
   const size_t slice_stride = (size_t)dm.nq * dm.nf;
   const float2* mb = mhat + (size_t)b * dm.ntheta * slice_stride;
   if (bp[dm.ntheta] == bp[0]) return;  // empty gather: nothing to write
-  // slice 0 stays in slot 0 (the last bin wraps onto it); slice s >= 1 uses slot 1 + ((s-1) & 1)
   auto slot_of = [](int s) { return s == 0 ? 0 : 1 + ((s - 1) & 1); };
+  auto bin_of = [](int step) { return step; };
+  const int nsteps = dm.ntheta;
 
-  build_grid<W>(lds, scratch, mb, f0, tb, dm, fpg, ftl);
-  if (dm.ntheta > 1) build_grid<W>(lds + slot_sz, scratch, mb + slice_stride, f0, tb, dm, fpg, ftl);
+  float2 cr[kCoefRegs];
+  TableRegs tr;
+  ChunkPos cur = first_chunk_from(0, nsteps, bp, bin_of);
+  load_tables(tr, tb, cur.c0, cur.cnt);
+  load_coefs(cr, mb, f0, dm, ftl);
+  build_grid<W>(lds, scratch, cr, tb, dm, fpg, ftl);
+  if (dm.ntheta > 1) {
+    load_coefs(cr, mb + slice_stride, f0, dm, ftl);
+    build_grid<W>(lds + slot_sz, scratch, cr, tb, dm, fpg, ftl);
+  }
+  store_tables(stg(0), tr, cur.cnt);
+  __syncthreads();
+  int sb = 0;  // stage buffer of the current chunk
   for (int j = 0; j < dm.ntheta; ++j) {
+    const bool build_next = j + 2 < dm.ntheta;
+    if (build_next) load_coefs(cr, mb + (size_t)(j + 2) * slice_stride, f0, dm, ftl);
     const int j1 = (j + 1 == dm.ntheta) ? 0 : j + 1;
     const float2* G0 = lds + slot_of(j) * slot_sz;
     const float2* G1 = lds + slot_of(j1) * slot_sz;
-    for (int c0 = bp[j]; c0 < bp[j + 1]; c0 += kStageTraces) {
-      const int cnt = min(kStageTraces, bp[j + 1] - c0);
-      stage_tables(st, tb, c0, cnt);
-      __syncthreads();
-      for (int it = threadIdx.x; it < cnt * ft; it += kBlockG) {
+    while (cur.step == j) {
+      const ChunkPos nxt = next_chunk(cur, nsteps, bp, bin_of);
+      if (nxt.step < nsteps) load_tables(tr, tb, nxt.c0, nxt.cnt);
+      const Stage st = stg(sb);
+      for (int it = threadIdx.x; it < cur.cnt * ft; it += kBlockG) {
         const int ti = it >> ftl;
         const int fl = it & (ft - 1);
         const unsigned f = (unsigned)(f0 + fl);
@@ -465,11 +550,12 @@ __global__ __launch_bounds__(kBlockG) void k_nufft_interp(const float2* __restri
         const float2 v = make_float2(fmaf(alpha, a1.x - a0.x, a0.x), fmaf(alpha, a1.y - a0.y, a0.y));
         dhat[(size_t)st.row[ti] * dm.nf + f] = cmul(v, pre_phase<-1>(f, st.a[ti]));
       }
+      if (nxt.step < nsteps) store_tables(stg(sb ^ 1), tr, nxt.cnt);
       __syncthreads();
+      sb ^= 1;
+      cur = nxt;
     }
-    if (j + 2 < dm.ntheta)
-      build_grid<W>(lds + slot_of(j + 2) * slot_sz, scratch, mb + (size_t)(j + 2) * slice_stride, f0, tb,
-                    dm, fpg, ftl);
+    if (build_next) build_grid<W>(lds + slot_of(j + 2) * slot_sz, scratch, cr, tb, dm, fpg, ftl);
   }
 }
 
@@ -491,44 +577,28 @@ __device__ __forceinline__ float2 unpack_fix(unsigned long long v, float inv_s) 
   return make_float2((float)lo * inv_s, (float)hi * inv_s);
 }
 
-// One azimuth bin into the slots lo (weight 1 - alpha, slice j) and hi (weight
-// alpha, slice j+1); a null slot is skipped.
-template <int W>
-__device__ void spread_bin(unsigned long long* lo, unsigned long long* hi, int c_begin, int c_end,
-                           const float2* __restrict__ dhat, const Stage& st, int f0, float S,
-                           const Tables& tb, const Dims& dm, int ftl) {
-  const int ldr = dm.ldr;
-  const int ft = dm.ft;
-  for (int c0 = c_begin; c0 < c_end; c0 += kStageTraces) {
-    const int cnt = min(kStageTraces, c_end - c0);
-    stage_tables(st, tb, c0, cnt);
-    __syncthreads();
-    for (int it = threadIdx.x; it < cnt * ft; it += kBlockG) {
-      const int ti = it >> ftl;
-      const int f = f0 + (it & (ft - 1));
-      st.dv[it] = f < dm.nf ? dhat[(size_t)st.row[ti] * dm.nf + f] : make_float2(0.f, 0.f);
-    }
-    __syncthreads();
-    for (int it = threadIdx.x; it < cnt * ft; it += kBlockG) {
-      const int ti = it >> ftl;
-      const int fl = it & (ft - 1);
-      const unsigned f = (unsigned)(f0 + fl);
-      if (f >= (unsigned)dm.nf) continue;
-      const float2 s = cmul(st.dv[it], pre_phase<1>(f, st.a[ti]));
-      const KernelPoint kp = kernel_point<W>(f, st.b[ti], dm.mg);
-      const float alpha = st.alpha[ti];
-      const float2 s1 = cscale(s, alpha * S);
-      const float2 s0 = cscale(s, (1.0f - alpha) * S);
-      unsigned long long* g0 = lo ? lo + fl * ldr + kp.base : nullptr;
-      unsigned long long* g1 = hi ? hi + fl * ldr + kp.base : nullptr;
+constexpr int kDvRegs = 4;  // staged data values per thread while prefetching
+static_assert(kDvRegs * kBlockG >= kStageTraces * kMaxFreqTile, "data prefetch capacity");
+static_assert(kStageTraces <= kBlockG, "one thread per staged trace");
+
+__device__ __forceinline__ void load_dv(float2* dr, const float2* __restrict__ dhat, const Stage& st, int f0,
+                                        int cnt, const Dims& dm, int ftl) {
 #pragma unroll
-      for (int t = 0; t < W; ++t) {
-        const float ph = es_tap(fmaf((float)t, -2.0f / (float)W, kp.z0), dm.cbeta);
-        if (g0) atomicAdd(g0 + t, pack_fix(ph * s0.x, ph * s0.y));
-        if (g1) atomicAdd(g1 + t, pack_fix(ph * s1.x, ph * s1.y));
-      }
+  for (int k = 0; k < kDvRegs; ++k) {
+    const int it = threadIdx.x + k * kBlockG;
+    dr[k] = make_float2(0.f, 0.f);
+    if (it < cnt * dm.ft) {
+      const int f = f0 + (it & (dm.ft - 1));
+      if (f < dm.nf) dr[k] = dhat[(size_t)st.row[it >> ftl] * dm.nf + f];
     }
-    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ void store_dv(const Stage& st, const float2* dr, int cnt, int ft) {
+#pragma unroll
+  for (int k = 0; k < kDvRegs; ++k) {
+    const int it = threadIdx.x + k * kBlockG;
+    if (it < cnt * ft) st.dv[it] = dr[k];
   }
 }
 
@@ -564,9 +634,12 @@ __device__ void finish_slot(unsigned long long* slot, float2* scratch, float2* _
 }
 
 // Transpose of k_nufft_interp.  Two fixed-point slots: slice s lives in slot
-// s & 1.  The wrap bin ntheta-1 is spread twice, its upper part into slice 0
-// before the sweep and its lower part into slice ntheta-1 at the end, so no
-// slice has to stay resident across the whole sweep.
+// s & 1.  Steps: 0 spreads the upper part of the wrap bin ntheta-1 into slice
+// 0; step s = 1..ntheta-1 spreads bin s-1 into slices s-1 (lower) and s
+// (upper), after which slice s-1 is complete; step ntheta spreads the lower
+// part of bin ntheta-1 into slice ntheta-1.  The tables and data values of the
+// next chunk are loaded while the current chunk is spread and the finished
+// slice is transformed.
 template <int W>
 __global__ __launch_bounds__(kBlockG) void k_nufft_spread(const float2* __restrict__ dhat,
                                                           const float* __restrict__ tr_bound,
@@ -576,39 +649,85 @@ __global__ __launch_bounds__(kBlockG) void k_nufft_spread(const float2* __restri
   extern __shared__ float2 lds[];
   __shared__ float red[kBlockG / 64];
   __shared__ float scale_sh;
+  const int ldr = dm.ldr;
   const int ft = dm.ft;
-  const int slot_sz = ft * dm.ldr;
-  unsigned long long* slot0 = reinterpret_cast<unsigned long long*>(lds);
-  unsigned long long* slot1 = slot0 + slot_sz;
+  const int slot_sz = ft * ldr;
+  unsigned long long* slots = reinterpret_cast<unsigned long long*>(lds);
   float2* scratch = lds + 2 * slot_sz;
-  const Stage st = stage_at(scratch + slot_sz);
+  float2* stage_base = scratch + slot_sz;
+  auto stg = [&](int k) { return stage_at(stage_base + k * stage_elems(ft)); };
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int b = tile / dm.nftile;
   const int f0 = (tile - b * dm.nftile) * ft;
   const int* bp = tb.bin_ptr + (size_t)b * (dm.ntheta + 1);
   const size_t slice_stride = (size_t)dm.nq * dm.nf;
   float2* mb = mhat + (size_t)b * dm.ntheta * slice_stride;
+  const int last = dm.ntheta - 1;
+  const int nsteps = dm.ntheta + 1;
+  auto bin_of = [last](int step) { return step == 0 ? last : (step == last + 1 ? last : step - 1); };
 
+  TableRegs tr;
+  float2 dr[kDvRegs];
+  ChunkPos cur = first_chunk_from(0, nsteps, bp, bin_of);
+  load_tables(tr, tb, cur.c0, cur.cnt);
   float part = 0.f;
   for (int64_t n = trace_ptr[b] + threadIdx.x; n < trace_ptr[b + 1]; n += kBlockG) part += tr_bound[n];
   const float bsum = block_sum<kBlockG>(part, red);
   if (threadIdx.x == 0) scale_sh = bsum > 0.f ? 0.99f * 2147483647.0f / bsum : 1.0f;
-  for (int i = threadIdx.x; i < 2 * slot_sz; i += kBlockG) slot0[i] = 0ull;
+  for (int i = threadIdx.x; i < 2 * slot_sz; i += kBlockG) slots[i] = 0ull;
+  store_tables(stg(0), tr, cur.cnt);
+  __syncthreads();
+  load_dv(dr, dhat, stg(0), f0, cur.cnt, dm, ftl);
+  store_dv(stg(0), dr, cur.cnt, ft);
   __syncthreads();
   const float S = scale_sh;
   const float inv_s = 1.0f / S;
-  const int last = dm.ntheta - 1;
-
-  spread_bin<W>(nullptr, slot0, bp[last], bp[last + 1], dhat, st, f0, S, tb, dm, ftl);
-  for (int j = 0; j < last; ++j) {
-    unsigned long long* sj = (j & 1) ? slot1 : slot0;
-    unsigned long long* sn = (j & 1) ? slot0 : slot1;
-    spread_bin<W>(sj, sn, bp[j], bp[j + 1], dhat, st, f0, S, tb, dm, ftl);
-    finish_slot<W>(sj, scratch, mb + (size_t)j * slice_stride, f0, inv_s, tb, dm, fpg, ftl);
+  int sb = 0;
+  for (int step = 0; step < nsteps; ++step) {
+    // slots: step 0 -> (none, slice 0); step s -> (slice s-1, slice s); step ntheta -> (slice last, none)
+    unsigned long long* lo = step == 0 ? nullptr : slots + (size_t)((step - 1) & 1) * slot_sz;
+    unsigned long long* hi = step == nsteps - 1 ? nullptr : slots + (size_t)(step & 1) * slot_sz;
+    bool finished = step == 0;
+    while (cur.step == step) {
+      const ChunkPos nxt = next_chunk(cur, nsteps, bp, bin_of);
+      if (nxt.step < nsteps) load_tables(tr, tb, nxt.c0, nxt.cnt);
+      const Stage st = stg(sb);
+      for (int it = threadIdx.x; it < cur.cnt * ft; it += kBlockG) {
+        const int ti = it >> ftl;
+        const int fl = it & (ft - 1);
+        const unsigned f = (unsigned)(f0 + fl);
+        if (f >= (unsigned)dm.nf) continue;
+        const float2 sv = cmul(st.dv[it], pre_phase<1>(f, st.a[ti]));
+        const KernelPoint kp = kernel_point<W>(f, st.b[ti], dm.mg);
+        const float alpha = st.alpha[ti];
+        const float2 s1 = cscale(sv, alpha * S);
+        const float2 s0 = cscale(sv, (1.0f - alpha) * S);
+        unsigned long long* g0 = lo ? lo + fl * ldr + kp.base : nullptr;
+        unsigned long long* g1 = hi ? hi + fl * ldr + kp.base : nullptr;
+#pragma unroll
+        for (int t = 0; t < W; ++t) {
+          const float ph = es_tap(fmaf((float)t, -2.0f / (float)W, kp.z0), dm.cbeta);
+          if (g0) atomicAdd(g0 + t, pack_fix(ph * s0.x, ph * s0.y));
+          if (g1) atomicAdd(g1 + t, pack_fix(ph * s1.x, ph * s1.y));
+        }
+      }
+      const bool more = nxt.step < nsteps;
+      if (more) store_tables(stg(sb ^ 1), tr, nxt.cnt);
+      __syncthreads();
+      if (more) load_dv(dr, dhat, stg(sb ^ 1), f0, nxt.cnt, dm, ftl);
+      if (nxt.step != step && !finished) {
+        // the slice completed by this step is transformed while the next data values arrive
+        finish_slot<W>(lo, scratch, mb + (size_t)(step - 1) * slice_stride, f0, inv_s, tb, dm, fpg, ftl);
+        finished = true;
+      }
+      if (more) store_dv(stg(sb ^ 1), dr, nxt.cnt, ft);
+      __syncthreads();
+      sb ^= 1;
+      cur = nxt;
+    }
+    if (!finished)  // a step without traces still completes its slice
+      finish_slot<W>(lo, scratch, mb + (size_t)(step - 1) * slice_stride, f0, inv_s, tb, dm, fpg, ftl);
   }
-  unsigned long long* sl = (last & 1) ? slot1 : slot0;
-  spread_bin<W>(sl, nullptr, bp[last], bp[last + 1], dhat, st, f0, S, tb, dm, ftl);
-  finish_slot<W>(sl, scratch, mb + (size_t)last * slice_stride, f0, inv_s, tb, dm, fpg, ftl);
 }
 
 // ------------------------------------------------------------------ small kernels
@@ -705,11 +824,11 @@ static size_t row_lds_bytes(const Dims& dm) { return 2 * (size_t)dm.nh * sizeof(
 
 static size_t interp_lds_bytes(const Dims& dm) {
   const int nslot = (dm.ntheta >= 3 ? 3 : dm.ntheta) + 1;
-  return (size_t)nslot * dm.ft * dm.ldr * sizeof(float2) + (size_t)kStageTraces * (24 + dm.ft * sizeof(float2));
+  return ((size_t)nslot * dm.ft * dm.ldr + 2 * (size_t)stage_elems(dm.ft)) * sizeof(float2);
 }
 
 static size_t spread_lds_bytes(const Dims& dm) {
-  return 3 * (size_t)dm.ft * dm.ldr * sizeof(float2) + (size_t)kStageTraces * (24 + dm.ft * sizeof(float2));
+  return (3 * (size_t)dm.ft * dm.ldr + 2 * (size_t)stage_elems(dm.ft)) * sizeof(float2);
 }
 
 static int ilog2(int v) {

@@ -217,7 +217,7 @@ int validate_params(const aahrt_params& q) {
 // both stage per-trace tables.  The larger of the two.
 size_t grid_lds(int ft, int ldr, int ntheta) {
   const int nslot = (ntheta >= 3 ? 3 : ntheta) + 1;
-  const size_t stage = (size_t)kStageTraces * (24 + ft * sizeof(float2));
+  const size_t stage = 2 * (size_t)(kStageTraces * 3 + kStageTraces * ft) * sizeof(float2);
   const size_t interp = (size_t)nslot * ft * ldr * sizeof(float2) + stage;
   const size_t spread = 3 * (size_t)ft * ldr * sizeof(float2) + stage;
   return interp > spread ? interp : spread;
@@ -285,7 +285,10 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
   // frequency tile
   if (!make_fft_plan(mg, P.fft_grid)) return fail(AAHRT_E_UNSUPPORTED, "q-grid length not 5-smooth");
   int ft = prm.freq_tile == 0 ? 16 : prm.freq_tile;
-  while (ft > 1 && grid_lds(ft, dm.ldr, dm.ntheta) > 160 * 1024) ft /= 2;
+  while (ft > 1 && (grid_lds(ft, dm.ldr, dm.ntheta) > 160 * 1024 || ft > kMaxFreqTile ||
+                    dm.nq * ft > kPrefetchCells))
+    ft /= 2;
+  if (dm.nq > kPrefetchCells) return fail(AAHRT_E_UNSUPPORTED, "nq too large for the GFST prefetch");
   if (grid_lds(ft, dm.ldr, dm.ntheta) > 160 * 1024) return fail(AAHRT_E_UNSUPPORTED, "q-grid too large for LDS");
   dm.ft = ft;
   dm.nftile = (dm.nf + ft - 1) / ft;

@@ -83,6 +83,18 @@ def test_operator_parity_zero_offset_and_axis_traces():
         assert ef < TOL and ea < TOL
 
 
+def test_operator_parity_single_azimuth_line():
+    """All traces in one azimuth bin (several staging chunks), every other bin empty."""
+    ax = wl.Axes(nt=64, dt=0.008, ntau=64, dtau=0.008, nq=8, q_min=0.05, q_max=0.45, ntheta=5)
+    h = np.linspace(0.05, 1.4, 300)
+    x, y = h * np.cos(0.3), h * np.sin(0.3)
+    w = wl.Workload('line', ax, [wl.Gather(x=x, y=y), wl.Gather(x=-x[:7], y=-y[:7])], 5, 'line')
+    errs = _op_parity(w, seed=8)
+    assert len(errs) == 2
+    for ef, ea in errs:
+        assert ef < TOL and ea < TOL
+
+
 def test_operator_parity_config2():
     for ef, ea in _op_parity(wl.config2(with_data=False), seed=7):
         print(f'config2 forward {ef:.2e} adjoint {ea:.2e}')
