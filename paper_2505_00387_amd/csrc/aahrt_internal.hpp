@@ -86,6 +86,8 @@ struct Dims {
   int ft;       // frequencies per GFST tile
   int nftile;   // ceil(nf/ft)
   int qhalf;    // nq/2 (mode offset)
+  int grid1;    // q-grid FFT runs one butterfly per thread per pass
+  int row1;     // stretched-axis FFT runs one butterfly per thread per pass
 };
 
 struct Plan {

@@ -52,6 +52,7 @@ __device__ __forceinline__ float block_max(float v, float* red) {
 __device__ __forceinline__ float store_real_spectrum(const float2* buf, float2* __restrict__ dst,
                                                      const Tables& tb, const Dims& dm) {
   float mx = 0.f;
+#pragma unroll 4
   for (int k = threadIdx.x; k < dm.nf; k += kBlock) {
     const float2 z = buf[k];
     float2 zc = buf[k == 0 ? 0 : dm.nh - k];
@@ -70,6 +71,7 @@ __device__ __forceinline__ float store_real_spectrum(const float2* buf, float2* 
 // Nyquist bin taken as zero): Z[k] = (X[k] + conj X[N/2-k]) + i e^{2 pi i k/N}(X[k] - conj X[N/2-k]).
 __device__ __forceinline__ void load_packed_c2r(float2* buf, const float2* __restrict__ src,
                                                 const Tables& tb, const Dims& dm) {
+#pragma unroll 4
   for (int k = threadIdx.x; k < dm.nh; k += kBlock) {
     float2 X = src[k];
     float2 Xm = make_float2(0.f, 0.f);
@@ -107,6 +109,18 @@ __device__ __forceinline__ float pack_from_csr(float2* buf, const float* g, cons
   return l1;
 }
 
+// Stretched-axis transform of one row held in LDS (A, with B as ping-pong); returns the result buffer.
+template <bool INV>
+__device__ __forceinline__ float2* row_fft(float2* A, float2* B, const FftPlan& fp, const FftPlan1& p1,
+                                           const Dims& dm, const Tables& tb) {
+  if (dm.row1) return fft_lds_1bpt<INV>(A, B, fp, p1);
+  return fft_lds<INV, kBlock>(A, B, fp, 1, dm.nh, tb.tw_half);
+}
+
+#define ROW_FFT_PREPARE()      \
+  FftPlan1 p1;                 \
+  if (dm.row1) prepare_1bpt<kBlock>(p1, fp, 1, dm.nh, tb.tw_half)
+
 // ------------------------------------------------------------------ model side
 // Row kernels use two LDS buffers of N/2 complex values (FFT ping-pong); the
 // staged input row aliases the second buffer before the first pass.
@@ -117,6 +131,7 @@ __global__ __launch_bounds__(kBlock) void k_model_r2c(const float* __restrict__ 
                                                       float2* __restrict__ mhat, Tables tb, Dims dm,
                                                       FftPlan fp) {
   extern __shared__ float2 lds[];
+  ROW_FFT_PREPARE();
   float2* A = lds;
   float2* B = lds + dm.nh;
   float* row = reinterpret_cast<float*>(B);
@@ -126,6 +141,7 @@ __global__ __launch_bounds__(kBlock) void k_model_r2c(const float* __restrict__ 
   for (int i = threadIdx.x; i < dm.ntau; i += kBlock) row[i] = src[i];
   __syncthreads();
   const float sc = tb.deapod[l];
+#pragma unroll 4
   for (int p = threadIdx.x; p < dm.nh; p += kBlock) {
     const int r0 = 2 * p, r1 = 2 * p + 1;
     float a = 0.f, b = 0.f;
@@ -140,7 +156,7 @@ __global__ __launch_bounds__(kBlock) void k_model_r2c(const float* __restrict__ 
     A[p] = make_float2(a, b);
   }
   __syncthreads();
-  const float2* X = fft_lds<false, kBlock>(A, B, fp, 1, dm.nh, tb.tw_half);
+  const float2* X = row_fft<false>(A, B, fp, p1, dm, tb);
   store_real_spectrum(X, mhat + rid * dm.nf, tb, dm);
 }
 
@@ -148,19 +164,20 @@ __global__ __launch_bounds__(kBlock) void k_model_r2c(const float* __restrict__ 
 // nt' samples, times the deapodisation, then S^T.
 __device__ __forceinline__ const float* model_c2r_core(const float2* __restrict__ mhat, float2* A,
                                                        float2* B, const Tables& tb, const Dims& dm,
-                                                       const FftPlan& fp, size_t rid) {
+                                                       const FftPlan& fp, const FftPlan1& p1, size_t rid) {
   load_packed_c2r(A, mhat + rid * dm.nf, tb, dm);
   __syncthreads();
-  return reinterpret_cast<const float*>(fft_lds<true, kBlock>(A, B, fp, 1, dm.nh, tb.tw_half));
+  return reinterpret_cast<const float*>(row_fft<true>(A, B, fp, p1, dm, tb));
 }
 
 __global__ __launch_bounds__(kBlock) void k_model_c2r(const float2* __restrict__ mhat,
                                                       float* __restrict__ m, Tables tb, Dims dm,
                                                       FftPlan fp) {
   extern __shared__ float2 lds[];
+  ROW_FFT_PREPARE();
   const size_t rid = blockIdx.x;
   const int l = (int)(rid % dm.nq);
-  const float* xs = model_c2r_core(mhat, lds, lds + dm.nh, tb, dm, fp, rid);
+  const float* xs = model_c2r_core(mhat, lds, lds + dm.nh, tb, dm, fp, p1, rid);
   const float sc = tb.deapod[l] / (float)dm.nfft;
   float* dst = m + rid * dm.ntau;
   for (int i = threadIdx.x; i < dm.ntau; i += kBlock) {
@@ -182,11 +199,12 @@ __global__ __launch_bounds__(kBlock) void k_model_c2r_update(const float2* __res
                                                              float beta, int ista,
                                                              float* __restrict__ l1) {
   extern __shared__ float2 lds[];
+  ROW_FFT_PREPARE();
   __shared__ float red[kBlock / 64];
   const size_t rid = blockIdx.x;
   const int l = (int)(rid % dm.nq);
   const int b = (int)(rid / ((size_t)dm.nq * dm.ntheta));
-  const float* xs = model_c2r_core(mhat, lds, lds + dm.nh, tb, dm, fp, rid);
+  const float* xs = model_c2r_core(mhat, lds, lds + dm.nh, tb, dm, fp, p1, rid);
   const float sc = tb.deapod[l] / (float)dm.nfft;
   const float g = gam[b];
   const float thr = g * lam[b];
@@ -216,14 +234,16 @@ __global__ __launch_bounds__(kBlock) void k_data_c2r(const float2* __restrict__ 
                                                      float* __restrict__ d, Tables tb, Dims dm,
                                                      FftPlan fp) {
   extern __shared__ float2 lds[];
+  ROW_FFT_PREPARE();
   float2* A = lds;
   float2* B = lds + dm.nh;
   const size_t n = blockIdx.x;
   load_packed_c2r(A, dhat + n * dm.nf, tb, dm);
   __syncthreads();
-  const float* xs = reinterpret_cast<const float*>(fft_lds<true, kBlock>(A, B, fp, 1, dm.nh, tb.tw_half));
+  const float* xs = reinterpret_cast<const float*>(row_fft<true>(A, B, fp, p1, dm, tb));
   const float invN = 1.0f / (float)dm.nfft;
   float* dst = d + n * dm.nt;
+#pragma unroll 4
   for (int s = threadIdx.x; s < dm.nt; s += kBlock) {
     const Tap t = tb.u_tap[s];
     dst[s] = invN * (t.w0 * xs[t.i0] + t.w1 * xs[t.i1]);
@@ -237,6 +257,7 @@ __global__ __launch_bounds__(kBlock) void k_data_r2c(const float* __restrict__ d
                                                      float* __restrict__ tr_bound, Tables tb, Dims dm,
                                                      FftPlan fp) {
   extern __shared__ float2 lds[];
+  ROW_FFT_PREPARE();
   __shared__ float red[kBlock / 64];
   float2* A = lds;
   float2* B = lds + dm.nh;
@@ -247,7 +268,7 @@ __global__ __launch_bounds__(kBlock) void k_data_r2c(const float* __restrict__ d
   __syncthreads();
   pack_from_csr(A, g, tb.ut_ptr, tb.ut_idx, tb.ut_w, dm.nts, dm.nh);
   __syncthreads();
-  const float2* X = fft_lds<false, kBlock>(A, B, fp, 1, dm.nh, tb.tw_half);
+  const float2* X = row_fft<false>(A, B, fp, p1, dm, tb);
   const float mx = block_max<kBlock>(store_real_spectrum(X, dhat + n * dm.nf, tb, dm), red);
   if (threadIdx.x == 0) tr_bound[n] = mx;
 }
@@ -260,19 +281,21 @@ __global__ __launch_bounds__(kBlock) void k_residual_r2c(float2* __restrict__ dh
                                                          float* __restrict__ tr_bound, Tables tb,
                                                          Dims dm, FftPlan fp) {
   extern __shared__ float2 lds[];
+  ROW_FFT_PREPARE();
   __shared__ float red[kBlock / 64];
   float2* A = lds;
   float2* B = lds + dm.nh;
   const size_t n = blockIdx.x;
   load_packed_c2r(A, dhat + n * dm.nf, tb, dm);
   __syncthreads();
-  float2* X = fft_lds<true, kBlock>(A, B, fp, 1, dm.nh, tb.tw_half);
+  float2* X = row_fft<true>(A, B, fp, p1, dm, tb);
   float2* Y = (X == A) ? B : A;
   const float* xs = reinterpret_cast<const float*>(X);
   float* g = reinterpret_cast<float*>(Y);
   const float invN = 1.0f / (float)dm.nfft;
   const float* ob = dobs + n * dm.nt;
   float ss = 0.f;
+#pragma unroll 4
   for (int s = threadIdx.x; s < dm.nt; s += kBlock) {
     const Tap t = tb.u_tap[s];
     const float v = invN * (t.w0 * xs[t.i0] + t.w1 * xs[t.i1]);
@@ -283,7 +306,7 @@ __global__ __launch_bounds__(kBlock) void k_residual_r2c(float2* __restrict__ dh
   __syncthreads();
   pack_from_csr(X, g, tb.ut_ptr, tb.ut_idx, tb.ut_w, dm.nts, dm.nh);
   __syncthreads();
-  const float2* Z = fft_lds<false, kBlock>(X, Y, fp, 1, dm.nh, tb.tw_half);
+  const float2* Z = row_fft<false>(X, Y, fp, p1, dm, tb);
   const float mx = block_max<kBlock>(store_real_spectrum(Z, dhat + n * dm.nf, tb, dm), red);
   if (threadIdx.x == 0) tr_bound[n] = mx;
   if (rss) {
@@ -426,45 +449,39 @@ __device__ __forceinline__ ChunkPos next_chunk(const ChunkPos& c, int nsteps, co
   return first_chunk_from(c.step + 1, nsteps, bp, bin_of);
 }
 
-constexpr int kCoefRegs = 4;  // q-grid coefficients per thread held while prefetching
-static_assert(kCoefRegs * kBlockG >= kPrefetchCells, "coefficient prefetch capacity");
-
-__device__ __forceinline__ void load_coefs(float2* cr, const float2* __restrict__ mhat_slice, int f0,
-                                           const Dims& dm, int ftl) {
-#pragma unroll
-  for (int k = 0; k < kCoefRegs; ++k) {
-    const int it = threadIdx.x + k * kBlockG;
-    cr[k] = make_float2(0.f, 0.f);
-    if (it < dm.nq * dm.ft) {
-      const int l = it >> ftl;
-      const int f = f0 + (it & (dm.ft - 1));
-      if (f < dm.nf) cr[k] = mhat_slice[(size_t)l * dm.nf + f];
-    }
-  }
+// q-grid transform of one slot (ft rows of ldr cells, the first mg used); returns the result buffer.
+template <bool INV>
+__device__ __forceinline__ float2* grid_fft(float2* G, float2* scratch, const FftPlan& fpg,
+                                            const FftPlan1& p1, const Dims& dm, const Tables& tb) {
+  if (dm.grid1) return fft_lds_1bpt<INV>(G, scratch, fpg, p1);
+  return fft_lds<INV, kBlockG>(G, scratch, fpg, dm.ft, dm.ldr, tb.tw_grid);
 }
 
-// Forward q-grid of one slice from coefficients held in registers:
-// g[f][m] = sum_k c_k exp(-2 pi i k m/mg), then ghost cells g[f][mg + t] = g[f][t], t < W - 1.
+// Forward q-grid of slice s: g[f][m] = sum_k c_k exp(-2 pi i k m/mg), c_k = Mh[b][s][k + nq/2][f0+f],
+// then the ghost cells g[f][mg + t] = g[f][t], t < W - 1.
 template <int W>
-__device__ void build_grid(float2* G, float2* scratch, const float2* cr, const Tables& tb, const Dims& dm,
-                           const FftPlan& fpg, int ftl) {
+__device__ void build_grid(float2* G, float2* scratch, const float2* __restrict__ mhat_slice, int f0,
+                           const Tables& tb, const Dims& dm, const FftPlan& fpg, const FftPlan1& p1,
+                           int ftl) {
   const int ldr = dm.ldr;
   const int ft = dm.ft;
-  for (int i = threadIdx.x; i < ft * ldr; i += kBlockG) G[i] = make_float2(0.f, 0.f);
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < kCoefRegs; ++k) {
-    const int it = threadIdx.x + k * kBlockG;
-    if (it < dm.nq * ft) {
-      const int l = it >> ftl;
-      const int fl = it & (ft - 1);
-      int m = l - dm.qhalf;
-      if (m < 0) m += dm.mg;
-      G[fl * ldr + m] = cr[k];
-    }
+  const int nz = dm.mg - dm.nq;  // zero-padded cells [nq - qhalf, mg - qhalf) of each row
+  for (int i = threadIdx.x; i < ft * nz; i += kBlockG) {
+    const int fl = i / nz;
+    G[fl * ldr + dm.nq - dm.qhalf + (i - fl * nz)] = make_float2(0.f, 0.f);
+  }
+  for (int it = threadIdx.x; it < dm.nq * ft; it += kBlockG) {
+    const int l = it >> ftl;
+    const int fl = it & (ft - 1);
+    const int f = f0 + fl;
+    float2 c = make_float2(0.f, 0.f);
+    if (f < dm.nf) c = mhat_slice[(size_t)l * dm.nf + f];
+    int m = l - dm.qhalf;
+    if (m < 0) m += dm.mg;
+    G[fl * ldr + m] = c;
   }
   __syncthreads();
-  const float2* R = fft_lds<false, kBlockG>(G, scratch, fpg, ft, ldr, tb.tw_grid);
+  const float2* R = grid_fft<false>(G, scratch, fpg, p1, dm, tb);
   if (R != G) {
     for (int i = threadIdx.x; i < ft * ldr; i += kBlockG) G[i] = R[i];
     __syncthreads();
@@ -477,11 +494,9 @@ __device__ void build_grid(float2* G, float2* scratch, const float2* cr, const T
 }
 
 // Type-2 map of one frequency tile: D^[n][f] = e(-f a_n) ((1-alpha_n) g_j(u_n) + alpha_n g_{j+1}(u_n)),
-// g interpolated with the width-W kernel.  Slices are built two bins ahead
-// (slice 0 stays in slot 0 for the wrapping last bin; slice s >= 1 uses slot
-// 1 + ((s-1) & 1)); the q-coefficients of the next slice and the tables of
-// the next chunk are loaded into registers while the current chunk is
-// interpolated.
+// g interpolated with the width-W kernel.  Slices are built two bins ahead:
+// slice 0 stays in slot 0 (the last bin wraps onto it); slice s >= 1 uses slot
+// 1 + ((s-1) & 1); one more slot is the FFT ping-pong scratch.
 template <int W>
 __global__ __launch_bounds__(kBlockG) void k_nufft_interp(const float2* __restrict__ mhat,
                                                           float2* __restrict__ dhat, Tables tb,
@@ -492,8 +507,7 @@ __global__ __launch_bounds__(kBlockG) void k_nufft_interp(const float2* __restri
   const int slot_sz = ft * ldr;
   const int nslot = dm.ntheta >= 3 ? 3 : dm.ntheta;
   float2* scratch = lds + nslot * slot_sz;
-  float2* stage_base = scratch + slot_sz;
-  auto stg = [&](int k) { return stage_at(stage_base + k * stage_elems(ft)); };
+  const Stage st = stage_at(scratch + slot_sz);
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int b = tile / dm.nftile;
   const int f0 = (tile - b * dm.nftile) * ft;
@@ -502,33 +516,22 @@ __global__ __launch_bounds__(kBlockG) void k_nufft_interp(const float2* __restri
   const float2* mb = mhat + (size_t)b * dm.ntheta * slice_stride;
   if (bp[dm.ntheta] == bp[0]) return;  // empty gather: nothing to write
   auto slot_of = [](int s) { return s == 0 ? 0 : 1 + ((s - 1) & 1); };
-  auto bin_of = [](int step) { return step; };
-  const int nsteps = dm.ntheta;
+  FftPlan1 p1;
+  if (dm.grid1) prepare_1bpt<kBlockG>(p1, fpg, ft, ldr, tb.tw_grid);
 
-  float2 cr[kCoefRegs];
-  TableRegs tr;
-  ChunkPos cur = first_chunk_from(0, nsteps, bp, bin_of);
-  load_tables(tr, tb, cur.c0, cur.cnt);
-  load_coefs(cr, mb, f0, dm, ftl);
-  build_grid<W>(lds, scratch, cr, tb, dm, fpg, ftl);
-  if (dm.ntheta > 1) {
-    load_coefs(cr, mb + slice_stride, f0, dm, ftl);
-    build_grid<W>(lds + slot_sz, scratch, cr, tb, dm, fpg, ftl);
-  }
-  store_tables(stg(0), tr, cur.cnt);
-  __syncthreads();
-  int sb = 0;  // stage buffer of the current chunk
+  build_grid<W>(lds, scratch, mb, f0, tb, dm, fpg, p1, ftl);
+  if (dm.ntheta > 1) build_grid<W>(lds + slot_sz, scratch, mb + slice_stride, f0, tb, dm, fpg, p1, ftl);
   for (int j = 0; j < dm.ntheta; ++j) {
-    const bool build_next = j + 2 < dm.ntheta;
-    if (build_next) load_coefs(cr, mb + (size_t)(j + 2) * slice_stride, f0, dm, ftl);
     const int j1 = (j + 1 == dm.ntheta) ? 0 : j + 1;
     const float2* G0 = lds + slot_of(j) * slot_sz;
     const float2* G1 = lds + slot_of(j1) * slot_sz;
-    while (cur.step == j) {
-      const ChunkPos nxt = next_chunk(cur, nsteps, bp, bin_of);
-      if (nxt.step < nsteps) load_tables(tr, tb, nxt.c0, nxt.cnt);
-      const Stage st = stg(sb);
-      for (int it = threadIdx.x; it < cur.cnt * ft; it += kBlockG) {
+    for (int c0 = bp[j]; c0 < bp[j + 1]; c0 += kStageTraces) {
+      const int cnt = min(kStageTraces, bp[j + 1] - c0);
+      TableRegs tr;
+      load_tables(tr, tb, c0, cnt);
+      store_tables(st, tr, cnt);
+      __syncthreads();
+      for (int it = threadIdx.x; it < cnt * ft; it += kBlockG) {
         const int ti = it >> ftl;
         const int fl = it & (ft - 1);
         const unsigned f = (unsigned)(f0 + fl);
@@ -550,12 +553,11 @@ __global__ __launch_bounds__(kBlockG) void k_nufft_interp(const float2* __restri
         const float2 v = make_float2(fmaf(alpha, a1.x - a0.x, a0.x), fmaf(alpha, a1.y - a0.y, a0.y));
         dhat[(size_t)st.row[ti] * dm.nf + f] = cmul(v, pre_phase<-1>(f, st.a[ti]));
       }
-      if (nxt.step < nsteps) store_tables(stg(sb ^ 1), tr, nxt.cnt);
       __syncthreads();
-      sb ^= 1;
-      cur = nxt;
     }
-    if (build_next) build_grid<W>(lds + slot_of(j + 2) * slot_sz, scratch, cr, tb, dm, fpg, ftl);
+    if (j + 2 < dm.ntheta)
+      build_grid<W>(lds + slot_of(j + 2) * slot_sz, scratch, mb + (size_t)(j + 2) * slice_stride, f0, tb,
+                    dm, fpg, p1, ftl);
   }
 }
 
@@ -608,7 +610,7 @@ __device__ __forceinline__ void store_dv(const Stage& st, const float2* dr, int 
 template <int W>
 __device__ void finish_slot(unsigned long long* slot, float2* scratch, float2* __restrict__ out_slice,
                             int f0, float inv_s, const Tables& tb, const Dims& dm, const FftPlan& fpg,
-                            int ftl) {
+                            const FftPlan1& p1, int ftl) {
   const int ldr = dm.ldr;
   const int ft = dm.ft;
   for (int i = threadIdx.x; i < ft * (W - 1); i += kBlockG) {
@@ -619,7 +621,7 @@ __device__ void finish_slot(unsigned long long* slot, float2* scratch, float2* _
   float2* P = reinterpret_cast<float2*>(slot);
   for (int i = threadIdx.x; i < ft * ldr; i += kBlockG) P[i] = unpack_fix(slot[i], inv_s);
   __syncthreads();
-  const float2* R = fft_lds<true, kBlockG>(P, scratch, fpg, ft, ldr, tb.tw_grid);
+  const float2* R = grid_fft<true>(P, scratch, fpg, p1, dm, tb);
   for (int it = threadIdx.x; it < dm.nq * ft; it += kBlockG) {
     const int l = it >> ftl;
     const int fl = it & (ft - 1);
@@ -666,6 +668,8 @@ __global__ __launch_bounds__(kBlockG) void k_nufft_spread(const float2* __restri
   const int nsteps = dm.ntheta + 1;
   auto bin_of = [last](int step) { return step == 0 ? last : (step == last + 1 ? last : step - 1); };
 
+  FftPlan1 p1;
+  if (dm.grid1) prepare_1bpt<kBlockG>(p1, fpg, ft, ldr, tb.tw_grid);
   TableRegs tr;
   float2 dr[kDvRegs];
   ChunkPos cur = first_chunk_from(0, nsteps, bp, bin_of);
@@ -717,7 +721,7 @@ __global__ __launch_bounds__(kBlockG) void k_nufft_spread(const float2* __restri
       if (more) load_dv(dr, dhat, stg(sb ^ 1), f0, nxt.cnt, dm, ftl);
       if (nxt.step != step && !finished) {
         // the slice completed by this step is transformed while the next data values arrive
-        finish_slot<W>(lo, scratch, mb + (size_t)(step - 1) * slice_stride, f0, inv_s, tb, dm, fpg, ftl);
+        finish_slot<W>(lo, scratch, mb + (size_t)(step - 1) * slice_stride, f0, inv_s, tb, dm, fpg, p1, ftl);
         finished = true;
       }
       if (more) store_dv(stg(sb ^ 1), dr, nxt.cnt, ft);
@@ -726,7 +730,7 @@ __global__ __launch_bounds__(kBlockG) void k_nufft_spread(const float2* __restri
       cur = nxt;
     }
     if (!finished)  // a step without traces still completes its slice
-      finish_slot<W>(lo, scratch, mb + (size_t)(step - 1) * slice_stride, f0, inv_s, tb, dm, fpg, ftl);
+      finish_slot<W>(lo, scratch, mb + (size_t)(step - 1) * slice_stride, f0, inv_s, tb, dm, fpg, p1, ftl);
   }
 }
 
@@ -824,7 +828,7 @@ static size_t row_lds_bytes(const Dims& dm) { return 2 * (size_t)dm.nh * sizeof(
 
 static size_t interp_lds_bytes(const Dims& dm) {
   const int nslot = (dm.ntheta >= 3 ? 3 : dm.ntheta) + 1;
-  return ((size_t)nslot * dm.ft * dm.ldr + 2 * (size_t)stage_elems(dm.ft)) * sizeof(float2);
+  return ((size_t)nslot * dm.ft * dm.ldr + (size_t)stage_elems(dm.ft)) * sizeof(float2);
 }
 
 static size_t spread_lds_bytes(const Dims& dm) {

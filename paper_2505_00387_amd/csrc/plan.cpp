@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "aahrt_internal.hpp"
+#include "fft_lds.hpp"
 
 namespace aahrt {
 hipError_t launch_objective(const Plan& p, const float* rss, const int64_t* trace_ptr_dev,
@@ -292,6 +293,8 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
   if (grid_lds(ft, dm.ldr, dm.ntheta) > 160 * 1024) return fail(AAHRT_E_UNSUPPORTED, "q-grid too large for LDS");
   dm.ft = ft;
   dm.nftile = (dm.nf + ft - 1) / ft;
+  dm.grid1 = fits_1bpt(P.fft_grid, ft, kBlockG) ? 1 : 0;
+  dm.row1 = fits_1bpt(P.fft_half, 1, kBlock) ? 1 : 0;
   if (2 * (size_t)dm.nh * sizeof(float2) > 160 * 1024 || std::max(dm.nt, dm.ntau) > 2 * dm.nh)
     return fail(AAHRT_E_UNSUPPORTED, "row FFT too large for LDS");
 
