@@ -15,8 +15,6 @@ constexpr int kMaxPasses = 12;
 constexpr int kBlock = 256;     // threads per workgroup of the row kernels and small kernels
 constexpr int kBlockG = 512;    // threads per workgroup of the GFST (nonuniform FFT) kernels
 constexpr int kStageTraces = 64;  // traces staged in LDS per chunk in the GFST kernels
-constexpr int kMaxFreqTile = 32;  // frequencies per GFST tile at most (register prefetch capacity)
-constexpr int kPrefetchCells = 4 * 512;  // q-coefficients (nq * ft) one GFST workgroup prefetches
 
 // x / d = (umulhi(x, m) + x) >> s for 0 <= x < 2^31 (d = 1: x).
 struct FastDiv {
@@ -78,6 +76,7 @@ struct Dims {
   int nt, ntau, nq, ntheta;
   int nts;      // nt'
   int nfft, nh, nf;  // N, N/2, bins carried (= N/2)
+  int nhp;      // LDS cells of one row FFT buffer: room for the padded first pass
   int mg;       // q-grid length
   int ldr;      // LDS row length of a q-grid slot: mg + w - 1 ghost cells, padded to odd
   int w;        // kernel width
@@ -86,8 +85,6 @@ struct Dims {
   int ft;       // frequencies per GFST tile
   int nftile;   // ceil(nf/ft)
   int qhalf;    // nq/2 (mode offset)
-  int grid1;    // q-grid FFT runs one butterfly per thread per pass
-  int row1;     // stretched-axis FFT runs one butterfly per thread per pass
 };
 
 struct Plan {

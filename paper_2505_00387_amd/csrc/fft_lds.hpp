@@ -235,8 +235,12 @@ __device__ __forceinline__ void apply_twiddles(float2* v, const float2* __restri
   }
 }
 
-// One out-of-place Stockham pass of radix R.
-template <int R, bool INV, int NT>
+// Index of element i in a padded buffer: one spare cell after every 16, so
+// the stride-R writes of a first pass (Ns = 1) spread over the LDS banks.
+__host__ __device__ __forceinline__ int pad16(int i) { return i + (i >> 4); }
+
+// One out-of-place Stockham pass of radix R; PIN/POUT read/write padded buffers.
+template <int R, bool INV, int NT, bool PIN, bool POUT>
 __device__ __forceinline__ void fft_pass(const float2* __restrict__ src, float2* __restrict__ dst,
                                          const FftPass& ps, int nbatch, int bstride,
                                          const float2* __restrict__ tw) {
@@ -251,157 +255,58 @@ __device__ __forceinline__ void fft_pass(const float2* __restrict__ src, float2*
     const int jq = (int)fdiv((unsigned)j, ps.dns);
     const int k = j - jq * ps.ns;
     float2 v[R];
-    const float2* x = src + fb * bstride + j;
+    const float2* x = src + fb * bstride;
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = x[r * nb];
+    for (int r = 0; r < R; ++r) {
+      const int i = j + r * nb;
+      v[r] = x[PIN ? pad16(i) : i];
+    }
     if (ps.ns > 1) apply_twiddles<R, INV>(v, tw, k * ps.stride);
     Dft<R, INV>::run(v);
-    float2* y = dst + fb * bstride + jq * ps.ns * R + k;
+    float2* y = dst + fb * bstride;
+    const int o = jq * ps.ns * R + k;
 #pragma unroll
-    for (int r = 0; r < R; ++r) y[r * ps.ns] = v[r];
+    for (int r = 0; r < R; ++r) {
+      const int i = o + r * ps.ns;
+      y[POUT ? pad16(i) : i] = v[r];
+    }
   }
   __syncthreads();
 }
 
+template <int R, bool INV, int NT>
+__device__ __forceinline__ void fft_pass_sel(const float2* src, float2* dst, const FftPass& ps, int nbatch,
+                                             int bstride, const float2* tw, int mode) {
+  if (mode == 1) fft_pass<R, INV, NT, false, true>(src, dst, ps, nbatch, bstride, tw);
+  else if (mode == 2) fft_pass<R, INV, NT, true, false>(src, dst, ps, nbatch, bstride, tw);
+  else fft_pass<R, INV, NT, false, false>(src, dst, ps, nbatch, bstride, tw);
+}
+
 // Full transform of the data in `a` (the caller synchronises before calling).
-// Returns the buffer (a or b) holding the result.
+// Returns the buffer (a or b) holding the result.  With two or more passes the
+// first pass writes b padded (pad16) and the second reads it so; b must hold
+// pad16(n - 1) + 1 cells per sequence.  Input and result are unpadded.
 template <bool INV, int NT>
-__device__ float2* fft_lds(float2* a, float2* b, const FftPlan& pl, int nbatch, int bstride,
+__device__ __forceinline__ float2* fft_lds(float2* a, float2* b, const FftPlan& pl, int nbatch, int bstride,
                            const float2* __restrict__ tw) {
   float2* src = a;
   float2* dst = b;
   for (int s = 0; s < pl.npass; ++s) {
     const FftPass& ps = pl.pass[s];
+    const int mode = pl.npass < 2 ? 0 : (s == 0 ? 1 : (s == 1 ? 2 : 0));
     switch (ps.r) {
-      case 2: fft_pass<2, INV, NT>(src, dst, ps, nbatch, bstride, tw); break;
-      case 3: fft_pass<3, INV, NT>(src, dst, ps, nbatch, bstride, tw); break;
-      case 4: fft_pass<4, INV, NT>(src, dst, ps, nbatch, bstride, tw); break;
-      case 5: fft_pass<5, INV, NT>(src, dst, ps, nbatch, bstride, tw); break;
-      case 8: fft_pass<8, INV, NT>(src, dst, ps, nbatch, bstride, tw); break;
-      case 9: fft_pass<9, INV, NT>(src, dst, ps, nbatch, bstride, tw); break;
-      case 15: fft_pass<15, INV, NT>(src, dst, ps, nbatch, bstride, tw); break;
-      default: fft_pass<16, INV, NT>(src, dst, ps, nbatch, bstride, tw); break;
+      case 2: fft_pass_sel<2, INV, NT>(src, dst, ps, nbatch, bstride, tw, mode); break;
+      case 3: fft_pass_sel<3, INV, NT>(src, dst, ps, nbatch, bstride, tw, mode); break;
+      case 4: fft_pass_sel<4, INV, NT>(src, dst, ps, nbatch, bstride, tw, mode); break;
+      case 5: fft_pass_sel<5, INV, NT>(src, dst, ps, nbatch, bstride, tw, mode); break;
+      case 8: fft_pass_sel<8, INV, NT>(src, dst, ps, nbatch, bstride, tw, mode); break;
+      case 9: fft_pass_sel<9, INV, NT>(src, dst, ps, nbatch, bstride, tw, mode); break;
+      case 15: fft_pass_sel<15, INV, NT>(src, dst, ps, nbatch, bstride, tw, mode); break;
+      default: fft_pass_sel<16, INV, NT>(src, dst, ps, nbatch, bstride, tw, mode); break;
     }
     float2* t = src;
     src = dst;
     dst = t;
-  }
-  return src;
-}
-
-// ---------------------------------------------------------------------------
-// One-butterfly-per-thread schedule.  When every pass has at most NT
-// butterflies (n*nbatch/R <= NT), each thread owns one fixed butterfly per
-// pass: its input/output offsets and its twiddle anchors (w^1, w^4, w^8, w^12)
-// are computed once, so a transform that is repeated (many rows, many q-grid
-// slices) issues no table loads inside its passes.
-constexpr int kMaxPasses1 = 4;
-
-struct PassSlot {
-  int in_off;    // offset of input 0 (inputs at in_off + r * nb)
-  int out_off;   // offset of output 0 (outputs at out_off + r * ns)
-  int active;    // this thread owns a butterfly in this pass
-  float2 w1, w4, w8, w12;
-};
-
-struct FftPlan1 {
-  PassSlot ps[kMaxPasses1];
-};
-
-__host__ __device__ inline bool fits_1bpt(const FftPlan& pl, int nbatch, int nt) {
-  if (pl.npass > kMaxPasses1) return false;
-  for (int s = 0; s < pl.npass; ++s)
-    if (pl.pass[s].nb * nbatch > nt) return false;
-  return true;
-}
-
-// Anchors are stored for the forward sign; inverse passes conjugate them.
-template <int NT>
-__device__ __forceinline__ void prepare_1bpt(FftPlan1& p1, const FftPlan& pl, int nbatch, int bstride,
-                                             const float2* __restrict__ tw) {
-#pragma unroll
-  for (int s = 0; s < kMaxPasses1; ++s) {
-    PassSlot& q = p1.ps[s];
-    q.active = 0;
-    q.in_off = q.out_off = 0;
-    q.w1 = q.w4 = q.w8 = q.w12 = make_float2(1.f, 0.f);
-    if (s < pl.npass) {
-      const FftPass& ps = pl.pass[s];
-      const int b = threadIdx.x;
-      if (b < ps.nb * nbatch) {
-        const int fb = nbatch > 1 ? (int)fdiv((unsigned)b, ps.dnb) : 0;
-        const int j = b - fb * ps.nb;
-        const int jq = (int)fdiv((unsigned)j, ps.dns);
-        const int k = j - jq * ps.ns;
-        q.active = 1;
-        q.in_off = fb * bstride + j;
-        q.out_off = fb * bstride + jq * ps.ns * ps.r + k;
-        if (ps.ns > 1) {
-          const int step = k * ps.stride;
-          q.w1 = tw[step];
-          if (ps.r > 4) q.w4 = tw[4 * step];
-          if (ps.r > 8) q.w8 = tw[8 * step];
-          if (ps.r > 12) q.w12 = tw[12 * step];
-        }
-      }
-    }
-  }
-}
-
-template <int R, bool INV>
-__device__ __forceinline__ void pass_1bpt(const float2* __restrict__ src, float2* __restrict__ dst,
-                                          const PassSlot& q, int nb, int ns) {
-  if (q.active) {
-    float2 v[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = src[q.in_off + r * nb];
-    if (ns > 1) {
-      const float sg = INV ? -1.f : 1.f;
-      const float2 a1 = make_float2(q.w1.x, sg * q.w1.y), a4 = make_float2(q.w4.x, sg * q.w4.y);
-      const float2 a8 = make_float2(q.w8.x, sg * q.w8.y), a12 = make_float2(q.w12.x, sg * q.w12.y);
-      float2 wb[4];
-      wb[0] = make_float2(1.f, 0.f);
-      wb[1] = a1;
-      wb[2] = cmul(a1, a1);
-      wb[3] = cmul(wb[2], a1);
-#pragma unroll
-      for (int r = 1; r < R; ++r) {
-        const float2 w4a = (r >> 2) == 0 ? make_float2(1.f, 0.f)
-                           : (r >> 2) == 1 ? a4 : ((r >> 2) == 2 ? a8 : a12);
-        const float2 w = (r & 3) == 0 ? w4a : ((r >> 2) == 0 ? wb[r & 3] : cmul(w4a, wb[r & 3]));
-        v[r] = cmul(v[r], w);
-      }
-    }
-    Dft<R, INV>::run(v);
-#pragma unroll
-    for (int r = 0; r < R; ++r) dst[q.out_off + r * ns] = v[r];
-  }
-  __syncthreads();
-}
-
-// Transform with a prepared one-butterfly-per-thread schedule; returns the result buffer.
-template <bool INV>
-__device__ float2* fft_lds_1bpt(float2* a, float2* b, const FftPlan& pl, const FftPlan1& p1) {
-  float2* src = a;
-  float2* dst = b;
-#pragma unroll
-  for (int s = 0; s < kMaxPasses1; ++s) {
-    if (s < pl.npass) {
-      const FftPass& ps = pl.pass[s];
-      switch (ps.r) {
-        case 2: pass_1bpt<2, INV>(src, dst, p1.ps[s], ps.nb, ps.ns); break;
-        case 3: pass_1bpt<3, INV>(src, dst, p1.ps[s], ps.nb, ps.ns); break;
-        case 4: pass_1bpt<4, INV>(src, dst, p1.ps[s], ps.nb, ps.ns); break;
-        case 5: pass_1bpt<5, INV>(src, dst, p1.ps[s], ps.nb, ps.ns); break;
-        case 8: pass_1bpt<8, INV>(src, dst, p1.ps[s], ps.nb, ps.ns); break;
-        case 9: pass_1bpt<9, INV>(src, dst, p1.ps[s], ps.nb, ps.ns); break;
-        case 15: pass_1bpt<15, INV>(src, dst, p1.ps[s], ps.nb, ps.ns); break;
-        default: pass_1bpt<16, INV>(src, dst, p1.ps[s], ps.nb, ps.ns); break;
-      }
-      float2* t = src;
-      src = dst;
-      dst = t;
-    }
   }
   return src;
 }

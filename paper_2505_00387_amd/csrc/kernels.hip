@@ -109,18 +109,6 @@ __device__ __forceinline__ float pack_from_csr(float2* buf, const float* g, cons
   return l1;
 }
 
-// Stretched-axis transform of one row held in LDS (A, with B as ping-pong); returns the result buffer.
-template <bool INV>
-__device__ __forceinline__ float2* row_fft(float2* A, float2* B, const FftPlan& fp, const FftPlan1& p1,
-                                           const Dims& dm, const Tables& tb) {
-  if (dm.row1) return fft_lds_1bpt<INV>(A, B, fp, p1);
-  return fft_lds<INV, kBlock>(A, B, fp, 1, dm.nh, tb.tw_half);
-}
-
-#define ROW_FFT_PREPARE()      \
-  FftPlan1 p1;                 \
-  if (dm.row1) prepare_1bpt<kBlock>(p1, fp, 1, dm.nh, tb.tw_half)
-
 // ------------------------------------------------------------------ model side
 // Row kernels use two LDS buffers of N/2 complex values (FFT ping-pong); the
 // staged input row aliases the second buffer before the first pass.
@@ -131,9 +119,8 @@ __global__ __launch_bounds__(kBlock) void k_model_r2c(const float* __restrict__ 
                                                       float2* __restrict__ mhat, Tables tb, Dims dm,
                                                       FftPlan fp) {
   extern __shared__ float2 lds[];
-  ROW_FFT_PREPARE();
   float2* A = lds;
-  float2* B = lds + dm.nh;
+  float2* B = lds + dm.nhp;
   float* row = reinterpret_cast<float*>(B);
   const size_t rid = blockIdx.x;
   const int l = (int)(rid % dm.nq);
@@ -156,7 +143,7 @@ __global__ __launch_bounds__(kBlock) void k_model_r2c(const float* __restrict__ 
     A[p] = make_float2(a, b);
   }
   __syncthreads();
-  const float2* X = row_fft<false>(A, B, fp, p1, dm, tb);
+  const float2* X = fft_lds<false, kBlock>(A, B, fp, 1, dm.nh, tb.tw_half);
   store_real_spectrum(X, mhat + rid * dm.nf, tb, dm);
 }
 
@@ -164,20 +151,19 @@ __global__ __launch_bounds__(kBlock) void k_model_r2c(const float* __restrict__ 
 // nt' samples, times the deapodisation, then S^T.
 __device__ __forceinline__ const float* model_c2r_core(const float2* __restrict__ mhat, float2* A,
                                                        float2* B, const Tables& tb, const Dims& dm,
-                                                       const FftPlan& fp, const FftPlan1& p1, size_t rid) {
+                                                       const FftPlan& fp, size_t rid) {
   load_packed_c2r(A, mhat + rid * dm.nf, tb, dm);
   __syncthreads();
-  return reinterpret_cast<const float*>(row_fft<true>(A, B, fp, p1, dm, tb));
+  return reinterpret_cast<const float*>(fft_lds<true, kBlock>(A, B, fp, 1, dm.nh, tb.tw_half));
 }
 
 __global__ __launch_bounds__(kBlock) void k_model_c2r(const float2* __restrict__ mhat,
                                                       float* __restrict__ m, Tables tb, Dims dm,
                                                       FftPlan fp) {
   extern __shared__ float2 lds[];
-  ROW_FFT_PREPARE();
   const size_t rid = blockIdx.x;
   const int l = (int)(rid % dm.nq);
-  const float* xs = model_c2r_core(mhat, lds, lds + dm.nh, tb, dm, fp, p1, rid);
+  const float* xs = model_c2r_core(mhat, lds, lds + dm.nhp, tb, dm, fp, rid);
   const float sc = tb.deapod[l] / (float)dm.nfft;
   float* dst = m + rid * dm.ntau;
   for (int i = threadIdx.x; i < dm.ntau; i += kBlock) {
@@ -199,12 +185,11 @@ __global__ __launch_bounds__(kBlock) void k_model_c2r_update(const float2* __res
                                                              float beta, int ista,
                                                              float* __restrict__ l1) {
   extern __shared__ float2 lds[];
-  ROW_FFT_PREPARE();
   __shared__ float red[kBlock / 64];
   const size_t rid = blockIdx.x;
   const int l = (int)(rid % dm.nq);
   const int b = (int)(rid / ((size_t)dm.nq * dm.ntheta));
-  const float* xs = model_c2r_core(mhat, lds, lds + dm.nh, tb, dm, fp, p1, rid);
+  const float* xs = model_c2r_core(mhat, lds, lds + dm.nhp, tb, dm, fp, rid);
   const float sc = tb.deapod[l] / (float)dm.nfft;
   const float g = gam[b];
   const float thr = g * lam[b];
@@ -234,13 +219,12 @@ __global__ __launch_bounds__(kBlock) void k_data_c2r(const float2* __restrict__ 
                                                      float* __restrict__ d, Tables tb, Dims dm,
                                                      FftPlan fp) {
   extern __shared__ float2 lds[];
-  ROW_FFT_PREPARE();
   float2* A = lds;
-  float2* B = lds + dm.nh;
+  float2* B = lds + dm.nhp;
   const size_t n = blockIdx.x;
   load_packed_c2r(A, dhat + n * dm.nf, tb, dm);
   __syncthreads();
-  const float* xs = reinterpret_cast<const float*>(row_fft<true>(A, B, fp, p1, dm, tb));
+  const float* xs = reinterpret_cast<const float*>(fft_lds<true, kBlock>(A, B, fp, 1, dm.nh, tb.tw_half));
   const float invN = 1.0f / (float)dm.nfft;
   float* dst = d + n * dm.nt;
 #pragma unroll 4
@@ -257,10 +241,9 @@ __global__ __launch_bounds__(kBlock) void k_data_r2c(const float* __restrict__ d
                                                      float* __restrict__ tr_bound, Tables tb, Dims dm,
                                                      FftPlan fp) {
   extern __shared__ float2 lds[];
-  ROW_FFT_PREPARE();
   __shared__ float red[kBlock / 64];
   float2* A = lds;
-  float2* B = lds + dm.nh;
+  float2* B = lds + dm.nhp;
   float* g = reinterpret_cast<float*>(B);
   const size_t n = blockIdx.x;
   const float* src = d + n * dm.nt;
@@ -268,7 +251,7 @@ __global__ __launch_bounds__(kBlock) void k_data_r2c(const float* __restrict__ d
   __syncthreads();
   pack_from_csr(A, g, tb.ut_ptr, tb.ut_idx, tb.ut_w, dm.nts, dm.nh);
   __syncthreads();
-  const float2* X = row_fft<false>(A, B, fp, p1, dm, tb);
+  const float2* X = fft_lds<false, kBlock>(A, B, fp, 1, dm.nh, tb.tw_half);
   const float mx = block_max<kBlock>(store_real_spectrum(X, dhat + n * dm.nf, tb, dm), red);
   if (threadIdx.x == 0) tr_bound[n] = mx;
 }
@@ -281,14 +264,13 @@ __global__ __launch_bounds__(kBlock) void k_residual_r2c(float2* __restrict__ dh
                                                          float* __restrict__ tr_bound, Tables tb,
                                                          Dims dm, FftPlan fp) {
   extern __shared__ float2 lds[];
-  ROW_FFT_PREPARE();
   __shared__ float red[kBlock / 64];
   float2* A = lds;
-  float2* B = lds + dm.nh;
+  float2* B = lds + dm.nhp;
   const size_t n = blockIdx.x;
   load_packed_c2r(A, dhat + n * dm.nf, tb, dm);
   __syncthreads();
-  float2* X = row_fft<true>(A, B, fp, p1, dm, tb);
+  float2* X = fft_lds<true, kBlock>(A, B, fp, 1, dm.nh, tb.tw_half);
   float2* Y = (X == A) ? B : A;
   const float* xs = reinterpret_cast<const float*>(X);
   float* g = reinterpret_cast<float*>(Y);
@@ -306,7 +288,7 @@ __global__ __launch_bounds__(kBlock) void k_residual_r2c(float2* __restrict__ dh
   __syncthreads();
   pack_from_csr(X, g, tb.ut_ptr, tb.ut_idx, tb.ut_w, dm.nts, dm.nh);
   __syncthreads();
-  const float2* Z = row_fft<false>(X, Y, fp, p1, dm, tb);
+  const float2* Z = fft_lds<false, kBlock>(X, Y, fp, 1, dm.nh, tb.tw_half);
   const float mx = block_max<kBlock>(store_real_spectrum(Z, dhat + n * dm.nf, tb, dm), red);
   if (threadIdx.x == 0) tr_bound[n] = mx;
   if (rss) {
@@ -384,9 +366,6 @@ struct Stage {
   float2* dv;  // spreading only: [kStageTraces][ft]
 };
 
-// Two stage buffers (double buffering): stage k starts at base + k * stage_elems(ft).
-__host__ __device__ constexpr int stage_elems(int ft) { return kStageTraces * 3 + kStageTraces * ft; }
-
 __device__ __forceinline__ Stage stage_at(float2* base) {
   Stage st;
   st.b = reinterpret_cast<unsigned long long*>(base);
@@ -397,79 +376,24 @@ __device__ __forceinline__ Stage stage_at(float2* base) {
   return st;
 }
 
-// Per-trace tables of one chunk held in registers between their load and their
-// store to LDS (thread t holds trace c0 + t, t < cnt).
-struct TableRegs {
-  unsigned long long b, a;
-  float alpha;
-  int row;
-};
-
-__device__ __forceinline__ void load_tables(TableRegs& r, const Tables& tb, int c0, int cnt) {
-  const int t = threadIdx.x;
-  if (t < cnt) {
-    r.b = tb.tr_b[c0 + t];
-    r.a = tb.tr_a[c0 + t];
-    r.alpha = tb.tr_alpha[c0 + t];
-    r.row = tb.tr_row[c0 + t];
+__device__ __forceinline__ void stage_tables(const Stage& st, const Tables& tb, int c0, int cnt) {
+  for (int t = threadIdx.x; t < cnt; t += kBlockG) {
+    st.b[t] = tb.tr_b[c0 + t];
+    st.a[t] = tb.tr_a[c0 + t];
+    st.alpha[t] = tb.tr_alpha[c0 + t];
+    st.row[t] = tb.tr_row[c0 + t];
   }
-}
-
-__device__ __forceinline__ void store_tables(const Stage& st, const TableRegs& r, int cnt) {
-  const int t = threadIdx.x;
-  if (t < cnt) {
-    st.b[t] = r.b;
-    st.a[t] = r.a;
-    st.alpha[t] = r.alpha;
-    st.row[t] = r.row;
-  }
-}
-
-// Chunks of kStageTraces traces over a sequence of azimuth bins.  Position
-// (step, c0): the chunk starting at trace c0 of the bin visited at `step`;
-// step == nsteps marks the end.
-struct ChunkPos {
-  int step, c0, cnt;
-};
-
-template <typename BinOf>
-__device__ __forceinline__ ChunkPos first_chunk_from(int step, int nsteps, const int* bp, BinOf bin_of) {
-  for (; step < nsteps; ++step) {
-    const int j = bin_of(step);
-    if (bp[j + 1] > bp[j]) return ChunkPos{step, bp[j], min(kStageTraces, bp[j + 1] - bp[j])};
-  }
-  return ChunkPos{nsteps, 0, 0};
-}
-
-template <typename BinOf>
-__device__ __forceinline__ ChunkPos next_chunk(const ChunkPos& c, int nsteps, const int* bp, BinOf bin_of) {
-  const int j = bin_of(c.step);
-  const int c0 = c.c0 + kStageTraces;
-  if (c0 < bp[j + 1]) return ChunkPos{c.step, c0, min(kStageTraces, bp[j + 1] - c0)};
-  return first_chunk_from(c.step + 1, nsteps, bp, bin_of);
-}
-
-// q-grid transform of one slot (ft rows of ldr cells, the first mg used); returns the result buffer.
-template <bool INV>
-__device__ __forceinline__ float2* grid_fft(float2* G, float2* scratch, const FftPlan& fpg,
-                                            const FftPlan1& p1, const Dims& dm, const Tables& tb) {
-  if (dm.grid1) return fft_lds_1bpt<INV>(G, scratch, fpg, p1);
-  return fft_lds<INV, kBlockG>(G, scratch, fpg, dm.ft, dm.ldr, tb.tw_grid);
 }
 
 // Forward q-grid of slice s: g[f][m] = sum_k c_k exp(-2 pi i k m/mg), c_k = Mh[b][s][k + nq/2][f0+f],
 // then the ghost cells g[f][mg + t] = g[f][t], t < W - 1.
 template <int W>
-__device__ void build_grid(float2* G, float2* scratch, const float2* __restrict__ mhat_slice, int f0,
-                           const Tables& tb, const Dims& dm, const FftPlan& fpg, const FftPlan1& p1,
-                           int ftl) {
+__device__ __forceinline__ void build_grid(float2* G, float2* scratch, const float2* __restrict__ mhat_slice, int f0,
+                           const float2* twl, const Dims& dm, const FftPlan& fpg, int ftl) {
   const int ldr = dm.ldr;
   const int ft = dm.ft;
-  const int nz = dm.mg - dm.nq;  // zero-padded cells [nq - qhalf, mg - qhalf) of each row
-  for (int i = threadIdx.x; i < ft * nz; i += kBlockG) {
-    const int fl = i / nz;
-    G[fl * ldr + dm.nq - dm.qhalf + (i - fl * nz)] = make_float2(0.f, 0.f);
-  }
+  for (int i = threadIdx.x; i < ft * ldr; i += kBlockG) G[i] = make_float2(0.f, 0.f);
+  __syncthreads();
   for (int it = threadIdx.x; it < dm.nq * ft; it += kBlockG) {
     const int l = it >> ftl;
     const int fl = it & (ft - 1);
@@ -481,7 +405,7 @@ __device__ void build_grid(float2* G, float2* scratch, const float2* __restrict_
     G[fl * ldr + m] = c;
   }
   __syncthreads();
-  const float2* R = grid_fft<false>(G, scratch, fpg, p1, dm, tb);
+  const float2* R = fft_lds<false, kBlockG>(G, scratch, fpg, ft, ldr, twl);
   if (R != G) {
     for (int i = threadIdx.x; i < ft * ldr; i += kBlockG) G[i] = R[i];
     __syncthreads();
@@ -493,10 +417,6 @@ __device__ void build_grid(float2* G, float2* scratch, const float2* __restrict_
   __syncthreads();
 }
 
-// Type-2 map of one frequency tile: D^[n][f] = e(-f a_n) ((1-alpha_n) g_j(u_n) + alpha_n g_{j+1}(u_n)),
-// g interpolated with the width-W kernel.  Slices are built two bins ahead:
-// slice 0 stays in slot 0 (the last bin wraps onto it); slice s >= 1 uses slot
-// 1 + ((s-1) & 1); one more slot is the FFT ping-pong scratch.
 template <int W>
 __global__ __launch_bounds__(kBlockG) void k_nufft_interp(const float2* __restrict__ mhat,
                                                           float2* __restrict__ dhat, Tables tb,
@@ -508,6 +428,7 @@ __global__ __launch_bounds__(kBlockG) void k_nufft_interp(const float2* __restri
   const int nslot = dm.ntheta >= 3 ? 3 : dm.ntheta;
   float2* scratch = lds + nslot * slot_sz;
   const Stage st = stage_at(scratch + slot_sz);
+  float2* twl = scratch + slot_sz + kStageTraces * (3 + ft);  // q-grid twiddles
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int b = tile / dm.nftile;
   const int f0 = (tile - b * dm.nftile) * ft;
@@ -515,49 +436,48 @@ __global__ __launch_bounds__(kBlockG) void k_nufft_interp(const float2* __restri
   const size_t slice_stride = (size_t)dm.nq * dm.nf;
   const float2* mb = mhat + (size_t)b * dm.ntheta * slice_stride;
   if (bp[dm.ntheta] == bp[0]) return;  // empty gather: nothing to write
+  for (int i = threadIdx.x; i < dm.mg; i += kBlockG) twl[i] = tb.tw_grid[i];
+  // slice 0 stays in slot 0 (the last bin wraps onto it); slice s >= 1 uses slot 1 + ((s-1) & 1)
   auto slot_of = [](int s) { return s == 0 ? 0 : 1 + ((s - 1) & 1); };
-  FftPlan1 p1;
-  if (dm.grid1) prepare_1bpt<kBlockG>(p1, fpg, ft, ldr, tb.tw_grid);
 
-  build_grid<W>(lds, scratch, mb, f0, tb, dm, fpg, p1, ftl);
-  if (dm.ntheta > 1) build_grid<W>(lds + slot_sz, scratch, mb + slice_stride, f0, tb, dm, fpg, p1, ftl);
-  for (int j = 0; j < dm.ntheta; ++j) {
-    const int j1 = (j + 1 == dm.ntheta) ? 0 : j + 1;
-    const float2* G0 = lds + slot_of(j) * slot_sz;
-    const float2* G1 = lds + slot_of(j1) * slot_sz;
-    for (int c0 = bp[j]; c0 < bp[j + 1]; c0 += kStageTraces) {
-      const int cnt = min(kStageTraces, bp[j + 1] - c0);
-      TableRegs tr;
-      load_tables(tr, tb, c0, cnt);
-      store_tables(st, tr, cnt);
-      __syncthreads();
-      for (int it = threadIdx.x; it < cnt * ft; it += kBlockG) {
-        const int ti = it >> ftl;
-        const int fl = it & (ft - 1);
-        const unsigned f = (unsigned)(f0 + fl);
-        if (f >= (unsigned)dm.nf) continue;
-        const KernelPoint kp = kernel_point<W>(f, st.b[ti], dm.mg);
-        const float2* g0 = G0 + fl * ldr + kp.base;
-        const float2* g1 = G1 + fl * ldr + kp.base;
-        float2 a0 = make_float2(0.f, 0.f), a1 = make_float2(0.f, 0.f);
+  // step -2 and -1 build slices 0 and 1; step j >= 0 interpolates bin j, then builds slice j + 2
+  for (int j = -2; j < dm.ntheta; ++j) {
+    if (j >= 0) {
+      const int j1 = (j + 1 == dm.ntheta) ? 0 : j + 1;
+      const float2* G0 = lds + slot_of(j) * slot_sz;
+      const float2* G1 = lds + slot_of(j1) * slot_sz;
+      for (int c0 = bp[j]; c0 < bp[j + 1]; c0 += kStageTraces) {
+        const int cnt = min(kStageTraces, bp[j + 1] - c0);
+        stage_tables(st, tb, c0, cnt);
+        __syncthreads();
+        for (int it = threadIdx.x; it < cnt * ft; it += kBlockG) {
+          const int ti = it >> ftl;
+          const int fl = it & (ft - 1);
+          const unsigned f = (unsigned)(f0 + fl);
+          if (f >= (unsigned)dm.nf) continue;
+          const KernelPoint kp = kernel_point<W>(f, st.b[ti], dm.mg);
+          const float2* g0 = G0 + fl * ldr + kp.base;
+          const float2* g1 = G1 + fl * ldr + kp.base;
+          float2 a0 = make_float2(0.f, 0.f), a1 = make_float2(0.f, 0.f);
 #pragma unroll
-        for (int t = 0; t < W; ++t) {
-          const float ph = es_tap(fmaf((float)t, -2.0f / (float)W, kp.z0), dm.cbeta);
-          const float2 v0 = g0[t], v1 = g1[t];
-          a0.x = fmaf(ph, v0.x, a0.x);
-          a0.y = fmaf(ph, v0.y, a0.y);
-          a1.x = fmaf(ph, v1.x, a1.x);
-          a1.y = fmaf(ph, v1.y, a1.y);
+          for (int t = 0; t < W; ++t) {
+            const float ph = es_tap(fmaf((float)t, -2.0f / (float)W, kp.z0), dm.cbeta);
+            const float2 v0 = g0[t], v1 = g1[t];
+            a0.x = fmaf(ph, v0.x, a0.x);
+            a0.y = fmaf(ph, v0.y, a0.y);
+            a1.x = fmaf(ph, v1.x, a1.x);
+            a1.y = fmaf(ph, v1.y, a1.y);
+          }
+          const float alpha = st.alpha[ti];
+          const float2 v = make_float2(fmaf(alpha, a1.x - a0.x, a0.x), fmaf(alpha, a1.y - a0.y, a0.y));
+          dhat[(size_t)st.row[ti] * dm.nf + f] = cmul(v, pre_phase<-1>(f, st.a[ti]));
         }
-        const float alpha = st.alpha[ti];
-        const float2 v = make_float2(fmaf(alpha, a1.x - a0.x, a0.x), fmaf(alpha, a1.y - a0.y, a0.y));
-        dhat[(size_t)st.row[ti] * dm.nf + f] = cmul(v, pre_phase<-1>(f, st.a[ti]));
+        __syncthreads();
       }
-      __syncthreads();
     }
-    if (j + 2 < dm.ntheta)
-      build_grid<W>(lds + slot_of(j + 2) * slot_sz, scratch, mb + (size_t)(j + 2) * slice_stride, f0, tb,
-                    dm, fpg, p1, ftl);
+    const int sb = j + 2;
+    if (sb < dm.ntheta)
+      build_grid<W>(lds + slot_of(sb) * slot_sz, scratch, mb + (size_t)sb * slice_stride, f0, twl, dm, fpg, ftl);
   }
 }
 
@@ -579,28 +499,44 @@ __device__ __forceinline__ float2 unpack_fix(unsigned long long v, float inv_s) 
   return make_float2((float)lo * inv_s, (float)hi * inv_s);
 }
 
-constexpr int kDvRegs = 4;  // staged data values per thread while prefetching
-static_assert(kDvRegs * kBlockG >= kStageTraces * kMaxFreqTile, "data prefetch capacity");
-static_assert(kStageTraces <= kBlockG, "one thread per staged trace");
-
-__device__ __forceinline__ void load_dv(float2* dr, const float2* __restrict__ dhat, const Stage& st, int f0,
-                                        int cnt, const Dims& dm, int ftl) {
-#pragma unroll
-  for (int k = 0; k < kDvRegs; ++k) {
-    const int it = threadIdx.x + k * kBlockG;
-    dr[k] = make_float2(0.f, 0.f);
-    if (it < cnt * dm.ft) {
-      const int f = f0 + (it & (dm.ft - 1));
-      if (f < dm.nf) dr[k] = dhat[(size_t)st.row[it >> ftl] * dm.nf + f];
+// One azimuth bin into the slots lo (weight 1 - alpha, slice j) and hi (weight
+// alpha, slice j+1); a null slot is skipped.
+template <int W>
+__device__ __forceinline__ void spread_bin(unsigned long long* lo, unsigned long long* hi, int c_begin, int c_end,
+                           const float2* __restrict__ dhat, const Stage& st, int f0, float S,
+                           const Tables& tb, const Dims& dm, int ftl) {
+  const int ldr = dm.ldr;
+  const int ft = dm.ft;
+  for (int c0 = c_begin; c0 < c_end; c0 += kStageTraces) {
+    const int cnt = min(kStageTraces, c_end - c0);
+    stage_tables(st, tb, c0, cnt);
+    __syncthreads();
+    for (int it = threadIdx.x; it < cnt * ft; it += kBlockG) {
+      const int ti = it >> ftl;
+      const int f = f0 + (it & (ft - 1));
+      st.dv[it] = f < dm.nf ? dhat[(size_t)st.row[ti] * dm.nf + f] : make_float2(0.f, 0.f);
     }
-  }
-}
-
-__device__ __forceinline__ void store_dv(const Stage& st, const float2* dr, int cnt, int ft) {
+    __syncthreads();
+    for (int it = threadIdx.x; it < cnt * ft; it += kBlockG) {
+      const int ti = it >> ftl;
+      const int fl = it & (ft - 1);
+      const unsigned f = (unsigned)(f0 + fl);
+      if (f >= (unsigned)dm.nf) continue;
+      const float2 s = cmul(st.dv[it], pre_phase<1>(f, st.a[ti]));
+      const KernelPoint kp = kernel_point<W>(f, st.b[ti], dm.mg);
+      const float alpha = st.alpha[ti];
+      const float2 s1 = cscale(s, alpha * S);
+      const float2 s0 = cscale(s, (1.0f - alpha) * S);
+      unsigned long long* g0 = lo ? lo + fl * ldr + kp.base : nullptr;
+      unsigned long long* g1 = hi ? hi + fl * ldr + kp.base : nullptr;
 #pragma unroll
-  for (int k = 0; k < kDvRegs; ++k) {
-    const int it = threadIdx.x + k * kBlockG;
-    if (it < cnt * ft) st.dv[it] = dr[k];
+      for (int t = 0; t < W; ++t) {
+        const float ph = es_tap(fmaf((float)t, -2.0f / (float)W, kp.z0), dm.cbeta);
+        if (g0) atomicAdd(g0 + t, pack_fix(ph * s0.x, ph * s0.y));
+        if (g1) atomicAdd(g1 + t, pack_fix(ph * s1.x, ph * s1.y));
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -608,9 +544,9 @@ __device__ __forceinline__ void store_dv(const Stage& st, const float2* dr, int 
 // FFT: H[k] = sum_m G[m] exp(+2 pi i k m/mg) for the nq modes, written to
 // Mh[b][s][k + nq/2][f0 + f]; the slot is cleared afterwards.
 template <int W>
-__device__ void finish_slot(unsigned long long* slot, float2* scratch, float2* __restrict__ out_slice,
-                            int f0, float inv_s, const Tables& tb, const Dims& dm, const FftPlan& fpg,
-                            const FftPlan1& p1, int ftl) {
+__device__ __forceinline__ void finish_slot(unsigned long long* slot, float2* scratch, float2* __restrict__ out_slice,
+                            int f0, float inv_s, const float2* twl, const Dims& dm, const FftPlan& fpg,
+                            int ftl) {
   const int ldr = dm.ldr;
   const int ft = dm.ft;
   for (int i = threadIdx.x; i < ft * (W - 1); i += kBlockG) {
@@ -621,7 +557,7 @@ __device__ void finish_slot(unsigned long long* slot, float2* scratch, float2* _
   float2* P = reinterpret_cast<float2*>(slot);
   for (int i = threadIdx.x; i < ft * ldr; i += kBlockG) P[i] = unpack_fix(slot[i], inv_s);
   __syncthreads();
-  const float2* R = grid_fft<true>(P, scratch, fpg, p1, dm, tb);
+  const float2* R = fft_lds<true, kBlockG>(P, scratch, fpg, ft, ldr, twl);
   for (int it = threadIdx.x; it < dm.nq * ft; it += kBlockG) {
     const int l = it >> ftl;
     const int fl = it & (ft - 1);
@@ -636,12 +572,9 @@ __device__ void finish_slot(unsigned long long* slot, float2* scratch, float2* _
 }
 
 // Transpose of k_nufft_interp.  Two fixed-point slots: slice s lives in slot
-// s & 1.  Steps: 0 spreads the upper part of the wrap bin ntheta-1 into slice
-// 0; step s = 1..ntheta-1 spreads bin s-1 into slices s-1 (lower) and s
-// (upper), after which slice s-1 is complete; step ntheta spreads the lower
-// part of bin ntheta-1 into slice ntheta-1.  The tables and data values of the
-// next chunk are loaded while the current chunk is spread and the finished
-// slice is transformed.
+// s & 1.  The wrap bin ntheta-1 is spread twice, its upper part into slice 0
+// before the sweep and its lower part into slice ntheta-1 at the end, so no
+// slice has to stay resident across the whole sweep.
 template <int W>
 __global__ __launch_bounds__(kBlockG) void k_nufft_spread(const float2* __restrict__ dhat,
                                                           const float* __restrict__ tr_bound,
@@ -651,86 +584,40 @@ __global__ __launch_bounds__(kBlockG) void k_nufft_spread(const float2* __restri
   extern __shared__ float2 lds[];
   __shared__ float red[kBlockG / 64];
   __shared__ float scale_sh;
-  const int ldr = dm.ldr;
   const int ft = dm.ft;
-  const int slot_sz = ft * ldr;
-  unsigned long long* slots = reinterpret_cast<unsigned long long*>(lds);
+  const int slot_sz = ft * dm.ldr;
+  unsigned long long* slot0 = reinterpret_cast<unsigned long long*>(lds);
+  unsigned long long* slot1 = slot0 + slot_sz;
   float2* scratch = lds + 2 * slot_sz;
-  float2* stage_base = scratch + slot_sz;
-  auto stg = [&](int k) { return stage_at(stage_base + k * stage_elems(ft)); };
+  const Stage st = stage_at(scratch + slot_sz);
+  float2* twl = scratch + slot_sz + kStageTraces * (3 + ft);  // q-grid twiddles
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int b = tile / dm.nftile;
   const int f0 = (tile - b * dm.nftile) * ft;
   const int* bp = tb.bin_ptr + (size_t)b * (dm.ntheta + 1);
   const size_t slice_stride = (size_t)dm.nq * dm.nf;
   float2* mb = mhat + (size_t)b * dm.ntheta * slice_stride;
-  const int last = dm.ntheta - 1;
-  const int nsteps = dm.ntheta + 1;
-  auto bin_of = [last](int step) { return step == 0 ? last : (step == last + 1 ? last : step - 1); };
 
-  FftPlan1 p1;
-  if (dm.grid1) prepare_1bpt<kBlockG>(p1, fpg, ft, ldr, tb.tw_grid);
-  TableRegs tr;
-  float2 dr[kDvRegs];
-  ChunkPos cur = first_chunk_from(0, nsteps, bp, bin_of);
-  load_tables(tr, tb, cur.c0, cur.cnt);
   float part = 0.f;
   for (int64_t n = trace_ptr[b] + threadIdx.x; n < trace_ptr[b + 1]; n += kBlockG) part += tr_bound[n];
   const float bsum = block_sum<kBlockG>(part, red);
   if (threadIdx.x == 0) scale_sh = bsum > 0.f ? 0.99f * 2147483647.0f / bsum : 1.0f;
-  for (int i = threadIdx.x; i < 2 * slot_sz; i += kBlockG) slots[i] = 0ull;
-  store_tables(stg(0), tr, cur.cnt);
-  __syncthreads();
-  load_dv(dr, dhat, stg(0), f0, cur.cnt, dm, ftl);
-  store_dv(stg(0), dr, cur.cnt, ft);
+  for (int i = threadIdx.x; i < 2 * slot_sz; i += kBlockG) slot0[i] = 0ull;
+  for (int i = threadIdx.x; i < dm.mg; i += kBlockG) twl[i] = tb.tw_grid[i];
   __syncthreads();
   const float S = scale_sh;
   const float inv_s = 1.0f / S;
-  int sb = 0;
-  for (int step = 0; step < nsteps; ++step) {
-    // slots: step 0 -> (none, slice 0); step s -> (slice s-1, slice s); step ntheta -> (slice last, none)
-    unsigned long long* lo = step == 0 ? nullptr : slots + (size_t)((step - 1) & 1) * slot_sz;
-    unsigned long long* hi = step == nsteps - 1 ? nullptr : slots + (size_t)(step & 1) * slot_sz;
-    bool finished = step == 0;
-    while (cur.step == step) {
-      const ChunkPos nxt = next_chunk(cur, nsteps, bp, bin_of);
-      if (nxt.step < nsteps) load_tables(tr, tb, nxt.c0, nxt.cnt);
-      const Stage st = stg(sb);
-      for (int it = threadIdx.x; it < cur.cnt * ft; it += kBlockG) {
-        const int ti = it >> ftl;
-        const int fl = it & (ft - 1);
-        const unsigned f = (unsigned)(f0 + fl);
-        if (f >= (unsigned)dm.nf) continue;
-        const float2 sv = cmul(st.dv[it], pre_phase<1>(f, st.a[ti]));
-        const KernelPoint kp = kernel_point<W>(f, st.b[ti], dm.mg);
-        const float alpha = st.alpha[ti];
-        const float2 s1 = cscale(sv, alpha * S);
-        const float2 s0 = cscale(sv, (1.0f - alpha) * S);
-        unsigned long long* g0 = lo ? lo + fl * ldr + kp.base : nullptr;
-        unsigned long long* g1 = hi ? hi + fl * ldr + kp.base : nullptr;
-#pragma unroll
-        for (int t = 0; t < W; ++t) {
-          const float ph = es_tap(fmaf((float)t, -2.0f / (float)W, kp.z0), dm.cbeta);
-          if (g0) atomicAdd(g0 + t, pack_fix(ph * s0.x, ph * s0.y));
-          if (g1) atomicAdd(g1 + t, pack_fix(ph * s1.x, ph * s1.y));
-        }
-      }
-      const bool more = nxt.step < nsteps;
-      if (more) store_tables(stg(sb ^ 1), tr, nxt.cnt);
-      __syncthreads();
-      if (more) load_dv(dr, dhat, stg(sb ^ 1), f0, nxt.cnt, dm, ftl);
-      if (nxt.step != step && !finished) {
-        // the slice completed by this step is transformed while the next data values arrive
-        finish_slot<W>(lo, scratch, mb + (size_t)(step - 1) * slice_stride, f0, inv_s, tb, dm, fpg, p1, ftl);
-        finished = true;
-      }
-      if (more) store_dv(stg(sb ^ 1), dr, nxt.cnt, ft);
-      __syncthreads();
-      sb ^= 1;
-      cur = nxt;
-    }
-    if (!finished)  // a step without traces still completes its slice
-      finish_slot<W>(lo, scratch, mb + (size_t)(step - 1) * slice_stride, f0, inv_s, tb, dm, fpg, p1, ftl);
+  const int last = dm.ntheta - 1;
+
+  // step 0: upper part of the wrap bin into slice 0; step s = 1..last: bin s-1 into slices
+  // s-1 and s, then slice s-1 is complete; step last+1: lower part of the wrap bin into slice last
+  for (int step = 0; step <= last + 1; ++step) {
+    const int bin = (step == 0 || step == last + 1) ? last : step - 1;
+    unsigned long long* lo = step == 0 ? nullptr : (((step - 1) & 1) ? slot1 : slot0);
+    unsigned long long* hi = step == last + 1 ? nullptr : ((step & 1) ? slot1 : slot0);
+    spread_bin<W>(lo, hi, bp[bin], bp[bin + 1], dhat, st, f0, S, tb, dm, ftl);
+    if (step >= 1)
+      finish_slot<W>(lo, scratch, mb + (size_t)(step - 1) * slice_stride, f0, inv_s, twl, dm, fpg, ftl);
   }
 }
 
@@ -824,15 +711,15 @@ __global__ void k_objective(const float* __restrict__ rss, const int64_t* __rest
 }
 
 // ------------------------------------------------------------------ launchers
-static size_t row_lds_bytes(const Dims& dm) { return 2 * (size_t)dm.nh * sizeof(float2); }
+static size_t row_lds_bytes(const Dims& dm) { return 2 * (size_t)dm.nhp * sizeof(float2); }
 
 static size_t interp_lds_bytes(const Dims& dm) {
   const int nslot = (dm.ntheta >= 3 ? 3 : dm.ntheta) + 1;
-  return ((size_t)nslot * dm.ft * dm.ldr + (size_t)stage_elems(dm.ft)) * sizeof(float2);
+  return ((size_t)nslot * dm.ft * dm.ldr + (size_t)kStageTraces * (3 + dm.ft) + dm.mg) * sizeof(float2);
 }
 
 static size_t spread_lds_bytes(const Dims& dm) {
-  return (3 * (size_t)dm.ft * dm.ldr + 2 * (size_t)stage_elems(dm.ft)) * sizeof(float2);
+  return (3 * (size_t)dm.ft * dm.ldr + (size_t)kStageTraces * (3 + dm.ft) + dm.mg) * sizeof(float2);
 }
 
 static int ilog2(int v) {

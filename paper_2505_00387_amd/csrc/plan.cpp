@@ -12,7 +12,6 @@
 #include <vector>
 
 #include "aahrt_internal.hpp"
-#include "fft_lds.hpp"
 
 namespace aahrt {
 hipError_t launch_objective(const Plan& p, const float* rss, const int64_t* trace_ptr_dev,
@@ -216,11 +215,11 @@ int validate_params(const aahrt_params& q) {
 // LDS of a GFST workgroup (rows of ldr cells): interpolation uses up to three
 // azimuth-slice slots + one FFT scratch slot, spreading two fixed-point slots + scratch;
 // both stage per-trace tables.  The larger of the two.
-size_t grid_lds(int ft, int ldr, int ntheta) {
+size_t grid_lds(int ft, int ldr, int ntheta, int mg) {
   const int nslot = (ntheta >= 3 ? 3 : ntheta) + 1;
-  const size_t stage = 2 * (size_t)(kStageTraces * 3 + kStageTraces * ft) * sizeof(float2);
-  const size_t interp = (size_t)nslot * ft * ldr * sizeof(float2) + stage;
-  const size_t spread = 3 * (size_t)ft * ldr * sizeof(float2) + stage;
+  const size_t extra = ((size_t)kStageTraces * (3 + ft) + mg) * sizeof(float2);  // stage + twiddles
+  const size_t interp = (size_t)nslot * ft * ldr * sizeof(float2) + extra;
+  const size_t spread = 3 * (size_t)ft * ldr * sizeof(float2) + extra;
   return interp > spread ? interp : spread;
 }
 
@@ -258,6 +257,7 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
   }
   dm.nh = dm.nfft / 2;
   dm.nf = dm.nh;
+  dm.nhp = (dm.nh - 1) + ((dm.nh - 1) >> 4) + 1;
   if (!make_fft_plan(dm.nh, P.fft_half))
     return fail(AAHRT_E_UNSUPPORTED, "FFT length N/2 = " + std::to_string(dm.nh) + " exceeds the LDS FFT limits");
 
@@ -279,23 +279,19 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
   const double beta = 0.98 * M_PI * (1.0 - 1.0 / (2.0 * P.sigma)) * w;
   dm.beta = (float)beta;
   dm.cbeta = (float)(beta / std::log(2.0));
-  dm.ldr = mg + w - 1;
+  // row length of a q-grid slot: the ghost cells, and room for the padded first FFT pass
+  dm.ldr = std::max(mg + w - 1, (mg - 1) + ((mg - 1) >> 4) + 1);
   if (dm.ldr % 2 == 0) dm.ldr += 1;
   dm.qhalf = dm.nq / 2;
 
   // frequency tile
   if (!make_fft_plan(mg, P.fft_grid)) return fail(AAHRT_E_UNSUPPORTED, "q-grid length not 5-smooth");
   int ft = prm.freq_tile == 0 ? 16 : prm.freq_tile;
-  while (ft > 1 && (grid_lds(ft, dm.ldr, dm.ntheta) > 160 * 1024 || ft > kMaxFreqTile ||
-                    dm.nq * ft > kPrefetchCells))
-    ft /= 2;
-  if (dm.nq > kPrefetchCells) return fail(AAHRT_E_UNSUPPORTED, "nq too large for the GFST prefetch");
-  if (grid_lds(ft, dm.ldr, dm.ntheta) > 160 * 1024) return fail(AAHRT_E_UNSUPPORTED, "q-grid too large for LDS");
+  while (ft > 1 && grid_lds(ft, dm.ldr, dm.ntheta, mg) > 160 * 1024) ft /= 2;
+  if (grid_lds(ft, dm.ldr, dm.ntheta, mg) > 160 * 1024) return fail(AAHRT_E_UNSUPPORTED, "q-grid too large for LDS");
   dm.ft = ft;
   dm.nftile = (dm.nf + ft - 1) / ft;
-  dm.grid1 = fits_1bpt(P.fft_grid, ft, kBlockG) ? 1 : 0;
-  dm.row1 = fits_1bpt(P.fft_half, 1, kBlock) ? 1 : 0;
-  if (2 * (size_t)dm.nh * sizeof(float2) > 160 * 1024 || std::max(dm.nt, dm.ntau) > 2 * dm.nh)
+  if (2 * (size_t)dm.nhp * sizeof(float2) > 160 * 1024 || std::max(dm.nt, dm.ntau) > 2 * dm.nh)
     return fail(AAHRT_E_UNSUPPORTED, "row FFT too large for LDS");
 
   // anti-alias rule of Section 3.5 (informational)
