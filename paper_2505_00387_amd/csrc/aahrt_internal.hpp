@@ -15,6 +15,7 @@ constexpr int kMaxPasses = 12;
 constexpr int kBlock = 256;     // threads per workgroup of the row kernels and small kernels
 constexpr int kBlockG = 512;    // threads per workgroup of the GFST (nonuniform FFT) kernels
 constexpr int kStageTraces = 64;  // traces staged in LDS per chunk in the GFST kernels
+constexpr int kPrefetchCells = 4 * 512;  // q-coefficients (nq * ft) a GFST workgroup holds in registers
 
 // x / d = (umulhi(x, m) + x) >> s for 0 <= x < 2^31 (d = 1: x).
 struct FastDiv {

@@ -385,24 +385,45 @@ __device__ __forceinline__ void stage_tables(const Stage& st, const Tables& tb, 
   }
 }
 
-// Forward q-grid of slice s: g[f][m] = sum_k c_k exp(-2 pi i k m/mg), c_k = Mh[b][s][k + nq/2][f0+f],
+// q-coefficients of one slice for the tile, c[l][fl] = Mh[b][s][l][f0 + fl], held in
+// registers (kCoefRegs per thread) so their loads overlap the preceding work.
+constexpr int kCoefRegs = 4;
+static_assert(kCoefRegs * kBlockG >= kPrefetchCells, "coefficient prefetch capacity");
+
+__device__ __forceinline__ void load_coefs(float2* cr, const float2* __restrict__ mhat_slice, int f0,
+                                           const Dims& dm, int ftl) {
+#pragma unroll
+  for (int k = 0; k < kCoefRegs; ++k) {
+    const int it = threadIdx.x + k * kBlockG;
+    cr[k] = make_float2(0.f, 0.f);
+    if (it < dm.nq * dm.ft) {
+      const int f = f0 + (it & (dm.ft - 1));
+      if (f < dm.nf) cr[k] = mhat_slice[(size_t)(it >> ftl) * dm.nf + f];
+    }
+  }
+}
+
+// Forward q-grid of one slice from its coefficients: g[f][m] = sum_k c_k exp(-2 pi i k m/mg),
 // then the ghost cells g[f][mg + t] = g[f][t], t < W - 1.
 template <int W>
-__device__ __forceinline__ void build_grid(float2* G, float2* scratch, const float2* __restrict__ mhat_slice, int f0,
-                           const float2* twl, const Dims& dm, const FftPlan& fpg, int ftl) {
+__device__ __forceinline__ void build_grid(float2* G, float2* scratch, const float2* cr, const float2* twl,
+                                           const Dims& dm, const FftPlan& fpg, int ftl) {
   const int ldr = dm.ldr;
   const int ft = dm.ft;
-  for (int i = threadIdx.x; i < ft * ldr; i += kBlockG) G[i] = make_float2(0.f, 0.f);
-  __syncthreads();
-  for (int it = threadIdx.x; it < dm.nq * ft; it += kBlockG) {
-    const int l = it >> ftl;
-    const int fl = it & (ft - 1);
-    const int f = f0 + fl;
-    float2 c = make_float2(0.f, 0.f);
-    if (f < dm.nf) c = mhat_slice[(size_t)l * dm.nf + f];
-    int m = l - dm.qhalf;
-    if (m < 0) m += dm.mg;
-    G[fl * ldr + m] = c;
+  const int nz = dm.mg - dm.nq;  // zero-padded cells [nq - qhalf, mg - qhalf) of each row
+  for (int i = threadIdx.x; i < ft * nz; i += kBlockG) {
+    const int fl = i / nz;
+    G[fl * ldr + dm.nq - dm.qhalf + (i - fl * nz)] = make_float2(0.f, 0.f);
+  }
+#pragma unroll
+  for (int k = 0; k < kCoefRegs; ++k) {
+    const int it = threadIdx.x + k * kBlockG;
+    if (it < dm.nq * ft) {
+      const int l = it >> ftl;
+      int m = l - dm.qhalf;
+      if (m < 0) m += dm.mg;
+      G[(it & (ft - 1)) * ldr + m] = cr[k];
+    }
   }
   __syncthreads();
   const float2* R = fft_lds<false, kBlockG>(G, scratch, fpg, ft, ldr, twl);
@@ -440,8 +461,12 @@ __global__ __launch_bounds__(kBlockG) void k_nufft_interp(const float2* __restri
   // slice 0 stays in slot 0 (the last bin wraps onto it); slice s >= 1 uses slot 1 + ((s-1) & 1)
   auto slot_of = [](int s) { return s == 0 ? 0 : 1 + ((s - 1) & 1); };
 
-  // step -2 and -1 build slices 0 and 1; step j >= 0 interpolates bin j, then builds slice j + 2
+  // step -2 and -1 build slices 0 and 1; step j >= 0 interpolates bin j, then builds slice j + 2.
+  // The coefficients of the slice built at the end of a step are loaded at its start.
+  float2 cr[kCoefRegs];
   for (int j = -2; j < dm.ntheta; ++j) {
+    const int sb = j + 2;
+    if (sb < dm.ntheta) load_coefs(cr, mb + (size_t)sb * slice_stride, f0, dm, ftl);
     if (j >= 0) {
       const int j1 = (j + 1 == dm.ntheta) ? 0 : j + 1;
       const float2* G0 = lds + slot_of(j) * slot_sz;
@@ -475,9 +500,7 @@ __global__ __launch_bounds__(kBlockG) void k_nufft_interp(const float2* __restri
         __syncthreads();
       }
     }
-    const int sb = j + 2;
-    if (sb < dm.ntheta)
-      build_grid<W>(lds + slot_of(sb) * slot_sz, scratch, mb + (size_t)sb * slice_stride, f0, twl, dm, fpg, ftl);
+    if (sb < dm.ntheta) build_grid<W>(lds + slot_of(sb) * slot_sz, scratch, cr, twl, dm, fpg, ftl);
   }
 }
 

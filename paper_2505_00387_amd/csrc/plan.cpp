@@ -287,7 +287,8 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
   // frequency tile
   if (!make_fft_plan(mg, P.fft_grid)) return fail(AAHRT_E_UNSUPPORTED, "q-grid length not 5-smooth");
   int ft = prm.freq_tile == 0 ? 16 : prm.freq_tile;
-  while (ft > 1 && grid_lds(ft, dm.ldr, dm.ntheta, mg) > 160 * 1024) ft /= 2;
+  while (ft > 1 && (grid_lds(ft, dm.ldr, dm.ntheta, mg) > 160 * 1024 || dm.nq * ft > kPrefetchCells)) ft /= 2;
+  if (dm.nq > kPrefetchCells) return fail(AAHRT_E_UNSUPPORTED, "nq too large for the q-coefficient prefetch");
   if (grid_lds(ft, dm.ldr, dm.ntheta, mg) > 160 * 1024) return fail(AAHRT_E_UNSUPPORTED, "q-grid too large for LDS");
   dm.ft = ft;
   dm.nftile = (dm.nf + ft - 1) / ft;
