@@ -5,5 +5,6 @@ this package only marshals arguments.  Importing it does not load the library;
 the first Plan() does, and raises if the library has not been built.
 """
 from .api import Axes, Plan, plan_from_workload
+from .autograd import AAHRTFunction, aahrt
 
-__all__ = ['Axes', 'Plan', 'plan_from_workload']
+__all__ = ['Axes', 'Plan', 'plan_from_workload', 'AAHRTFunction', 'aahrt']

@@ -128,6 +128,7 @@ struct Plan {
   // cached graph of the solver
   hipGraphExec_t graph_exec = nullptr;
   hipGraph_t graph = nullptr;
+  hipStream_t cap_stream = nullptr;
   std::string graph_key;
 };
 

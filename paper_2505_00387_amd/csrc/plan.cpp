@@ -182,6 +182,7 @@ void free_plan(Plan* p) {
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
   if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   for (void* a : p->allocations) (void)hipFree(a);
   delete p;
 }
@@ -682,7 +683,31 @@ int aahrt_sparse_solve(aahrt_plan* plan, const float* d, float* m, const float* 
     HIP_TRY(launch_gather_scalar(P, GS_LAMBDA, P.tmpb, P.lam, 0.05f, s));
   }
   HIP_TRY(launch_copy(P.ybuf, m, model, s));
-  return enqueue_iterations(P, d, m, n_iter, ista, objective, s);
+  if ((flags & AAHRT_SOLVE_NO_GRAPH) || P.prof || n_iter == 0)
+    return enqueue_iterations(P, d, m, n_iter, ista, objective, s);
+  // The iterations are captured once into a hipGraph (on the plan's capture stream) and
+  // replayed on the caller's stream; the capture is reused while the arguments match.
+  char key[160];
+  snprintf(key, sizeof(key), "%p/%p/%d/%d/%p", (const void*)d, (void*)m, n_iter, (int)ista, (void*)objective);
+  if (!P.graph_exec || P.graph_key != key) {
+    if (P.graph_exec) { (void)hipGraphExecDestroy(P.graph_exec); P.graph_exec = nullptr; }
+    if (P.graph) { (void)hipGraphDestroy(P.graph); P.graph = nullptr; }
+    if (!P.cap_stream) HIP_TRY(hipStreamCreateWithFlags(&P.cap_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(P.cap_stream, hipStreamCaptureModeThreadLocal));
+    const int rc = enqueue_iterations(P, d, m, n_iter, ista, objective, P.cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(P.cap_stream, &g);
+    if (rc != AAHRT_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (ec != hipSuccess) return fail(AAHRT_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+    P.graph = g;
+    HIP_TRY(hipGraphInstantiate(&P.graph_exec, P.graph, nullptr, nullptr, 0));
+    P.graph_key = key;
+  }
+  HIP_TRY(hipGraphLaunch(P.graph_exec, s));
+  return AAHRT_OK;
 }
 
 int aahrt_profile_enable(aahrt_plan* plan, int32_t enable) {

@@ -240,3 +240,23 @@ def test_operators_are_bitwise_deterministic():
     x2, _ = plan.sparse_solve(d, 5)
     assert torch.equal(x1, x2)
     plan.close()
+
+
+def test_graph_replay_equals_eager():
+    """The captured hipGraph of the solve reproduces the eager launches bit for bit, on every replay."""
+    import torch
+    w = wl.config3(with_data=True)
+    plan = make_plan(w)
+    d = to_dev(w.data_all())
+    lam = plan.lambda_max(d) * 0.05
+    step = 1.0 / (1.05 * plan.operator_norm2(30))
+    ref, _ = plan.sparse_solve(d, 7, lam=lam, step=step, graph=False)
+    ref = ref.clone()
+    m = torch.zeros_like(ref)
+    for rep in range(3):
+        m.zero_()
+        plan.sparse_solve(d, 7, m=m, lam=lam, step=step, graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(m, ref), rep
+        _ = plan.forward(m)  # eager work between replays
+    plan.close()
