@@ -101,6 +101,118 @@ def cpu_baseline(w, sample_gather: int):
                       f'scaled to {w.n_iter} iterations + lambda rule per gather'}
 
 
+class PlainOperator:
+    """Plain per-gather FP32 operator on the GPU with torch ops, for the speed-up comparison.
+
+    The same discrete L and L^T as the library (linear stretch, real FFT of length N,
+    GFST map, inverse FFT, unstretch), but the map is the direct nonuniform DFT over
+    q (phases reduced modulo 1 in FP64, exponentials and sums in FP32) and every
+    gather is processed on its own.
+    """
+
+    def __init__(self, w, nfft, dev):
+        import numpy as np
+        import torch
+        a = w.axes
+        self.a, self.N, self.F, self.dev = a, nfft, nfft // 2, dev
+        self.nts = a.stretch * a.nt
+        T = (a.nt - 1) * a.dt
+        self.dts = T * T / (self.nts - 1)
+        S = np.zeros((self.nts, a.ntau))
+        for r in range(self.nts):
+            pos = np.sqrt(r * self.dts) / a.dtau
+            i = int(np.floor(pos))
+            f = pos - i
+            if i < a.ntau:
+                S[r, i] += 1 - f
+            if i + 1 < a.ntau:
+                S[r, i + 1] += f
+        U = np.zeros((a.nt, self.nts))
+        for t in range(a.nt):
+            pos = (t * a.dt) ** 2 / self.dts
+            i = int(np.floor(pos))
+            f = pos - i
+            if i < self.nts:
+                U[t, i] += 1 - f
+            if i + 1 < self.nts:
+                U[t, i + 1] += f
+        self.S = torch.tensor(S, dtype=torch.float32, device=dev)
+        self.U = torch.tensor(U, dtype=torch.float32, device=dev)
+        self.q = torch.tensor(a.q_min + a.dq * np.arange(a.nq), dtype=torch.float64, device=dev)
+        self.f = torch.arange(self.F, dtype=torch.float64, device=dev) / (nfft * self.dts)
+
+    def gather(self, g):
+        import numpy as np
+        import torch
+        th = np.mod(np.arctan2(g.y, g.x), np.pi)
+        u = th / (np.pi / self.a.ntheta)
+        j = np.floor(u).astype(np.int64) % self.a.ntheta
+        fr = u - np.floor(u)
+        W = np.zeros((g.x.size, self.a.ntheta))
+        W[np.arange(g.x.size), j] += 1 - fr
+        W[np.arange(g.x.size), (j + 1) % self.a.ntheta] += fr
+        h2 = torch.tensor(g.x ** 2 + g.y ** 2, dtype=torch.float64, device=self.dev)
+        return torch.tensor(W, dtype=torch.complex64, device=self.dev), h2
+
+    def _phase(self, h2, f0, f1):
+        import torch
+        ph = torch.frac(self.f[f0:f1, None, None] * h2[None, :, None] * self.q[None, None, :])
+        return torch.exp((-2j * torch.pi) * ph.to(torch.float32))          # [fc, n, nq]
+
+    def forward(self, m, W, h2, fc=64):
+        import torch
+        mh = torch.fft.rfft(m @ self.S.T, n=self.N)[..., :self.F]            # [ntheta, nq, F]
+        dh = torch.empty((h2.numel(), self.F), dtype=torch.complex64, device=self.dev)
+        for f0 in range(0, self.F, fc):
+            f1 = min(f0 + fc, self.F)
+            A = torch.einsum('nj,jlf->fnl', W, mh[:, :, f0:f1])
+            dh[:, f0:f1] = torch.sum(A * self._phase(h2, f0, f1), dim=2).T
+        pad = torch.zeros((h2.numel(), self.F + 1), dtype=torch.complex64, device=self.dev)
+        pad[:, :self.F] = dh
+        return torch.fft.irfft(pad, n=self.N)[:, :self.nts] @ self.U.T
+
+    def adjoint(self, d, W, h2, fc=64):
+        import torch
+        c = torch.full((self.F,), 2.0 / self.N, device=self.dev)
+        c[0] = 1.0 / self.N
+        gh = torch.fft.rfft(d @ self.U, n=self.N)[:, :self.F] * c
+        hh = torch.empty((self.a.ntheta, self.a.nq, self.F), dtype=torch.complex64, device=self.dev)
+        for f0 in range(0, self.F, fc):
+            f1 = min(f0 + fc, self.F)
+            B = torch.conj(self._phase(h2, f0, f1)) * gh[:, f0:f1].T[:, :, None]
+            hh[:, :, f0:f1] = torch.einsum('nj,fnl->jlf', torch.conj(W), B)
+        pad = torch.zeros((self.a.ntheta, self.a.nq, self.N), dtype=torch.complex64, device=self.dev)
+        pad[..., :self.F] = hh
+        return (torch.fft.ifft(pad).real * self.N)[..., :self.nts] @ self.S
+
+
+def plain_comparison(w, plan, lib_pair_s, n_sample, dev):
+    """Time the plain per-gather operator pair on n_sample gathers and scale to the batch."""
+    import torch
+    op = PlainOperator(w, plan.info['nfft'], dev)
+    gs = [op.gather(g) for g in w.gathers[:n_sample]]
+    ms = [torch.randn((w.axes.ntheta, w.axes.nq, w.axes.ntau), device=dev) for _ in range(n_sample)]
+    op.adjoint(op.forward(ms[0], *gs[0]), *gs[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b in range(n_sample):
+        op.adjoint(op.forward(ms[b], *gs[b]), *gs[b])
+    torch.cuda.synchronize()
+    t_sample = time.perf_counter() - t0
+    folds = [g.x.size for g in w.gathers]
+    scale = sum(folds) / sum(folds[:n_sample])
+    t_batch = t_sample * scale
+    # the plain operator and the library compute the same L: compare on gather 0
+    mb = torch.zeros(plan.model_shape, device=dev)
+    mb[0] = ms[0]
+    d_lib = plan.forward(mb)[: w.gathers[0].x.size]
+    d_pl = op.forward(ms[0], *gs[0])
+    diff = (torch.linalg.norm(d_lib - d_pl) / torch.linalg.norm(d_pl)).item()
+    return {'plain_pair_s_batch': round(t_batch, 3), 'plain_sample_gathers': n_sample,
+            'plain_pair_ms_per_gather': round(1e3 * t_sample / n_sample, 3),
+            'speedup_vs_plain': round(t_batch / lib_pair_s, 1), 'plain_vs_library_rel_diff': diff}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument('--gpus', type=int, default=1)
@@ -109,6 +221,7 @@ def main():
     ap.add_argument('--iters', type=int, default=0, help='FISTA iterations per solve (0: workload default, 100)')
     ap.add_argument('--no-cpu', action='store_true', help='skip the oracle CPU-baseline leg')
     ap.add_argument('--pairs', type=int, default=5, help='timed fwd+adj pairs')
+    ap.add_argument('--plain-sample', type=int, default=16, help='gathers of the plain-operator comparison (0: skip)')
     args = ap.parse_args()
     if args.gpus != 1:
         print('bench.py runs on one GPU only: the batched solve shards by gather, and this build '
@@ -184,6 +297,11 @@ def main():
     bop = 4 * rows * a.ntau + 16 * rows * nf + 16 * plan.ntraces * nf + 4 * plan.ntraces * a.nt
     pair_gbs = 2 * bop / t_pair / 1e9
 
+    plain = None
+    if args.plain_sample > 0:
+        print('# timing the plain per-gather FP32 operator', file=sys.stderr, flush=True)
+        plain = plain_comparison(w, plan, t_pair, args.plain_sample, dev)
+
     kernels = {}
     for name, (ms, n) in prof.items():
         if n == 0:
@@ -220,7 +338,7 @@ def main():
         'cpu_baseline': cpu,
         'secondary': {'fwd_adj_pairs_per_s': round(pairs_per_s, 1), 'fwd_adj_pair_ms': round(1e3 * t_pair, 3),
                       'fwd_adj_alg_GBs': round(pair_gbs, 1), 'setup_plan_s': round(t_plan, 3),
-                      'setup_power_iteration_s': round(t_power, 3)},
+                      'setup_power_iteration_s': round(t_power, 3), 'plain_per_gather_fp32': plain},
         'kernels': kernels,
     }
     print(json.dumps(out), flush=True)
