@@ -333,11 +333,13 @@ def main():
         'config': {'workload': w.name, 'gathers': w.batch, 'traces': plan.ntraces, 'nt': a.nt,
                    'nq': a.nq, 'ntheta': a.ntheta, 'fista_iters': n_iter, 'nfft': plan.info['nfft'],
                    'kernel_width': plan.info['kernel_width'], 'grid': plan.info['grid_size'],
-                   'freq_tile': plan.info['freq_tile']},
+                   'sigma': plan.info['sigma'], 'freq_tile': plan.info['freq_tile']},
         'roofline': roofline,
         'cpu_baseline': cpu,
         'secondary': {'fwd_adj_pairs_per_s': round(pairs_per_s, 1), 'fwd_adj_pair_ms': round(1e3 * t_pair, 3),
                       'fwd_adj_alg_GBs': round(pair_gbs, 1), 'setup_plan_s': round(t_plan, 3),
+                      'setup_autotune_s': round(plan.info['autotune_seconds'], 3),
+                      'autotune_candidates': plan.info['autotune_candidates'],
                       'setup_power_iteration_s': round(t_power, 3), 'plain_per_gather_fp32': plain},
         'kernels': kernels,
     }

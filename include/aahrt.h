@@ -78,8 +78,8 @@ typedef struct aahrt_params {
                             >= nt' + ceil(max(q_max,0) h2max/dt') + ceil(max(-q_min,0) h2max/dt');
                             otherwise it must be even, 2^a3^b5^c and >= nt' */
   double nufft_tol;      /* target relative error of the q nonuniform FFT; 0 -> 1e-6 */
-  double sigma;          /* q-grid oversampling; 0 -> chosen with the kernel width from nufft_tol */
-  int32_t kernel_width;  /* spreading kernel width w (3..12); 0 -> chosen from nufft_tol */
+  double sigma;          /* q-grid oversampling in [1.25, 4]; 0 -> autotune between 2 and 1.5 */
+  int32_t kernel_width;  /* spreading kernel width w (3..12); 0 -> chosen from nufft_tol and sigma */
   int32_t freq_tile;     /* frequencies per work item of the GFST stage (power of 2, 1..64); 0 -> autotune */
   int32_t grid_dtype;    /* aahrt_grid_dtype */
 } aahrt_params;
@@ -101,6 +101,8 @@ typedef struct aahrt_plan_info {
   int32_t freq_tile;     /* frequencies per GFST work item */
   int64_t workspace_bytes;
   int32_t q_alias_ok;    /* 1 if nq >= 2 q_max f'_max h2max (Section 3.5 anti-alias rule), else 0 (informational) */
+  int32_t autotune_candidates; /* GFST settings timed at plan creation (0: none, the setting was fixed) */
+  double autotune_seconds;     /* wall time of that autotuning */
 } aahrt_plan_info;
 
 /* Version string of the library. */
@@ -119,7 +121,12 @@ const char* aahrt_last_error(void);
  *   device     : HIP device ordinal the plan lives on
  * Computes the FP64 tables (stretch taps, azimuth weights, 64-bit fixed-point
  * phase increments, kernel deapodisation), allocates the device tables and the
- * workspace (hipMalloc), and autotunes the GFST tile when freq_tile is 0.
+ * workspace (hipMalloc).  When sigma or freq_tile is 0 it then autotunes the
+ * GFST stage: every admissible (sigma in {2, 1.5}, freq_tile in {4, 8, 16, 32})
+ * setting, with the kernel width that meets nufft_tol at that sigma, is timed
+ * on one interpolation + one spreading launch over the batch (on zeroed
+ * spectra, in a stream of its own, synchronously) and the fastest is kept.
+ * The tile changes no result; sigma changes results within the tolerance.
  */
 int aahrt_plan_create(aahrt_plan** out, const aahrt_params* p, int32_t batch,
                       const int64_t* trace_ptr, const double* x_km, const double* y_km,

@@ -41,7 +41,8 @@ class PlanInfo(ctypes.Structure):
                 ('nfft', ctypes.c_int32), ('nfreq', ctypes.c_int32), ('grid_size', ctypes.c_int32),
                 ('kernel_width', ctypes.c_int32), ('sigma', ctypes.c_double), ('beta', ctypes.c_double),
                 ('freq_tile', ctypes.c_int32), ('workspace_bytes', ctypes.c_int64),
-                ('q_alias_ok', ctypes.c_int32)]
+                ('q_alias_ok', ctypes.c_int32), ('autotune_candidates', ctypes.c_int32),
+                ('autotune_seconds', ctypes.c_double)]
 
 
 class AahrtError(RuntimeError):

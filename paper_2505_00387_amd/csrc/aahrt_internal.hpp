@@ -112,6 +112,11 @@ struct Plan {
   float* l1row = nullptr;   // [rows] per-row l1 norms (objective)
   float* rss = nullptr;     // [ntr] per-trace residual sums of squares (objective)
   float* tr_bound = nullptr; // [ntr] max_f |Re Dh| + |Im Dh| of each trace (spreading scale bound)
+  float* deapod_dev = nullptr;   // [nq] deapodisation of the current q-grid setting
+  float2* twgrid_dev = nullptr;  // [mg] q-grid twiddles of the current setting
+  std::vector<float> tune_ms;    // GFST stage time of each autotune candidate
+  int tune_choice = 0;
+  double autotune_s = 0.0;
   const int64_t* trace_ptr_dev = nullptr;
   int red_blocks_model = 0; // partial blocks per gather (model-sized reductions)
   size_t workspace_bytes = 0;

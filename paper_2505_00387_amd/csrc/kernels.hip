@@ -508,9 +508,11 @@ __global__ __launch_bounds__(kBlockG) void k_nufft_interp(const float2* __restri
 // is added as one 64-bit integer round(S Re c) + 2^32 round(S Im c).  Integer
 // addition is exact and order independent (deterministic results), and the
 // two 32-bit fields can be read back exactly while each partial sum stays
-// below 2^31 in magnitude, which the scale guarantees: S = 0.99 (2^31 - 1)/B_b
-// with B_b = sum over the gather's traces of max_f (|Re Dh| + |Im Dh|), an
-// upper bound of every cell sum (the kernel and the azimuth weights are <= 1).
+// below 2^31 in magnitude, which the scale guarantees.  Each azimuth slice s
+// has its own scale S_s = 0.99 (2^31 - 1)/B_s, where B_s sums, over the only
+// traces that reach the slice (bin s with weight 1 - alpha, bin s-1 mod ntheta
+// with weight alpha), the weight times max_f (|Re Dh| + |Im Dh|) of the trace:
+// an upper bound of every cell sum of the slice, the kernel being <= 1.
 __device__ __forceinline__ unsigned long long pack_fix(float x, float y) {
   const int a = __float2int_rn(x), b = __float2int_rn(y);
   return (unsigned long long)(long long)a + ((unsigned long long)(unsigned)b << 32);
@@ -522,11 +524,26 @@ __device__ __forceinline__ float2 unpack_fix(unsigned long long v, float inv_s) 
   return make_float2((float)lo * inv_s, (float)hi * inv_s);
 }
 
-// One azimuth bin into the slots lo (weight 1 - alpha, slice j) and hi (weight
-// alpha, slice j+1); a null slot is skipped.
+// Scale S_s of slice s (all threads of the block receive it).
+__device__ __forceinline__ float slice_scale(int s, const int* bp, const float* __restrict__ tr_bound,
+                                             const Tables& tb, int ntheta, float* red, float* scale_sh) {
+  const int sb = s == 0 ? ntheta - 1 : s - 1;
+  float part = 0.f;
+  for (int pos = bp[s] + threadIdx.x; pos < bp[s + 1]; pos += kBlockG)
+    part += (1.0f - tb.tr_alpha[pos]) * tr_bound[tb.tr_row[pos]];
+  for (int pos = bp[sb] + threadIdx.x; pos < bp[sb + 1]; pos += kBlockG)
+    part += tb.tr_alpha[pos] * tr_bound[tb.tr_row[pos]];
+  const float sum = block_sum<kBlockG>(part, red);
+  if (threadIdx.x == 0) *scale_sh = sum > 0.f ? 0.99f * 2147483647.0f / sum : 1.0f;
+  __syncthreads();
+  return *scale_sh;
+}
+
+// One azimuth bin into the slots lo (weight 1 - alpha, slice j, scale S_lo) and hi
+// (weight alpha, slice j+1, scale S_hi); a null slot is skipped.
 template <int W>
 __device__ __forceinline__ void spread_bin(unsigned long long* lo, unsigned long long* hi, int c_begin, int c_end,
-                           const float2* __restrict__ dhat, const Stage& st, int f0, float S,
+                           const float2* __restrict__ dhat, const Stage& st, int f0, float S_lo, float S_hi,
                            const Tables& tb, const Dims& dm, int ftl) {
   const int ldr = dm.ldr;
   const int ft = dm.ft;
@@ -548,8 +565,8 @@ __device__ __forceinline__ void spread_bin(unsigned long long* lo, unsigned long
       const float2 s = cmul(st.dv[it], pre_phase<1>(f, st.a[ti]));
       const KernelPoint kp = kernel_point<W>(f, st.b[ti], dm.mg);
       const float alpha = st.alpha[ti];
-      const float2 s1 = cscale(s, alpha * S);
-      const float2 s0 = cscale(s, (1.0f - alpha) * S);
+      const float2 s1 = cscale(s, alpha * S_hi);
+      const float2 s0 = cscale(s, (1.0f - alpha) * S_lo);
       unsigned long long* g0 = lo ? lo + fl * ldr + kp.base : nullptr;
       unsigned long long* g1 = hi ? hi + fl * ldr + kp.base : nullptr;
 #pragma unroll
@@ -601,7 +618,6 @@ __device__ __forceinline__ void finish_slot(unsigned long long* slot, float2* sc
 template <int W>
 __global__ __launch_bounds__(kBlockG) void k_nufft_spread(const float2* __restrict__ dhat,
                                                           const float* __restrict__ tr_bound,
-                                                          const int64_t* __restrict__ trace_ptr,
                                                           float2* __restrict__ mhat, Tables tb,
                                                           Dims dm, FftPlan fpg, int ftl) {
   extern __shared__ float2 lds[];
@@ -621,16 +637,10 @@ __global__ __launch_bounds__(kBlockG) void k_nufft_spread(const float2* __restri
   const size_t slice_stride = (size_t)dm.nq * dm.nf;
   float2* mb = mhat + (size_t)b * dm.ntheta * slice_stride;
 
-  float part = 0.f;
-  for (int64_t n = trace_ptr[b] + threadIdx.x; n < trace_ptr[b + 1]; n += kBlockG) part += tr_bound[n];
-  const float bsum = block_sum<kBlockG>(part, red);
-  if (threadIdx.x == 0) scale_sh = bsum > 0.f ? 0.99f * 2147483647.0f / bsum : 1.0f;
   for (int i = threadIdx.x; i < 2 * slot_sz; i += kBlockG) slot0[i] = 0ull;
   for (int i = threadIdx.x; i < dm.mg; i += kBlockG) twl[i] = tb.tw_grid[i];
-  __syncthreads();
-  const float S = scale_sh;
-  const float inv_s = 1.0f / S;
   const int last = dm.ntheta - 1;
+  float S_prev = 1.0f;  // scale of the slice finished at this step
 
   // step 0: upper part of the wrap bin into slice 0; step s = 1..last: bin s-1 into slices
   // s-1 and s, then slice s-1 is complete; step last+1: lower part of the wrap bin into slice last
@@ -638,9 +648,11 @@ __global__ __launch_bounds__(kBlockG) void k_nufft_spread(const float2* __restri
     const int bin = (step == 0 || step == last + 1) ? last : step - 1;
     unsigned long long* lo = step == 0 ? nullptr : (((step - 1) & 1) ? slot1 : slot0);
     unsigned long long* hi = step == last + 1 ? nullptr : ((step & 1) ? slot1 : slot0);
-    spread_bin<W>(lo, hi, bp[bin], bp[bin + 1], dhat, st, f0, S, tb, dm, ftl);
+    const float S_hi = step <= last ? slice_scale(step, bp, tr_bound, tb, dm.ntheta, red, &scale_sh) : 1.0f;
+    spread_bin<W>(lo, hi, bp[bin], bp[bin + 1], dhat, st, f0, S_prev, S_hi, tb, dm, ftl);
     if (step >= 1)
-      finish_slot<W>(lo, scratch, mb + (size_t)(step - 1) * slice_stride, f0, inv_s, twl, dm, fpg, ftl);
+      finish_slot<W>(lo, scratch, mb + (size_t)(step - 1) * slice_stride, f0, 1.0f / S_prev, twl, dm, fpg, ftl);
+    S_prev = S_hi;
   }
 }
 
@@ -857,7 +869,7 @@ hipError_t launch_nufft_spread(const Plan& p, const float2* dhat, float2* mhat, 
   case WW: {                                                                                 \
     hipError_t e = set_lds(k_nufft_spread<WW>, lds);                                         \
     if (e != hipSuccess) return e;                                                           \
-    hipLaunchKernelGGL(k_nufft_spread<WW>, grid, block, lds, s, dhat, p.tr_bound, p.trace_ptr_dev, mhat, \
+    hipLaunchKernelGGL(k_nufft_spread<WW>, grid, block, lds, s, dhat, p.tr_bound, mhat, \
                        p.tb, dm, p.fft_grid, ftl);                                           \
     break;                                                                                   \
   }

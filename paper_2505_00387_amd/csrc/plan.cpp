@@ -224,6 +224,162 @@ size_t grid_lds(int ft, int ldr, int ntheta, int mg) {
   return interp > spread ? interp : spread;
 }
 
+// One setting of the q nonuniform FFT: oversampled grid length mg (sigma = mg/nq),
+// kernel width w, frequencies per GFST workgroup ft.
+struct NufftChoice {
+  int mg, w, ft;
+};
+
+// Kernel width for a target relative error: measured error of the exponential-of-
+// semicircle kernel is about 0.9 * 10^-(w-1) at sigma = 2; narrower grids need
+// wider kernels (about two more cells at sigma = 1.5, three at 1.25).
+int width_for(double tol, double sigma) {
+  int w = (int)std::ceil(-std::log10(tol / 0.9)) + 1;
+  if (sigma < 1.5 - 1e-9) w += 3;
+  else if (sigma < 2.0 - 1e-9) w += 2;
+  return std::min(12, std::max(3, w));
+}
+
+// Row length of a q-grid slot: the ghost cells, and room for the padded first FFT pass.
+int slot_row(int mg, int w) {
+  int ldr = std::max(mg + w - 1, (mg - 1) + ((mg - 1) >> 4) + 1);
+  return ldr % 2 == 0 ? ldr + 1 : ldr;
+}
+
+bool choice_fits(const Dims& dm, int mg, int w, int ft) {
+  return grid_lds(ft, slot_row(mg, w), dm.ntheta, mg) <= 160 * 1024 && dm.nq * ft <= kPrefetchCells;
+}
+
+// Candidates: the requested sigma (or 2 and 1.5 when it is free) with the width from
+// the tolerance (or the requested width), and the requested tile (or 4..32 when
+// free).  The first candidate is the default setting.
+int nufft_candidates(const aahrt_params& prm, const Dims& dm, std::vector<NufftChoice>& out) {
+  const double tol = prm.nufft_tol == 0.0 ? 1e-6 : prm.nufft_tol;
+  if (dm.nq > kPrefetchCells) return fail(AAHRT_E_UNSUPPORTED, "nq too large for the q-coefficient prefetch");
+  std::vector<double> sig;
+  if (prm.sigma != 0.0) sig.push_back(prm.sigma);
+  else sig = {2.0, 1.5};
+  std::vector<int> fts;
+  if (prm.freq_tile != 0) fts.push_back(prm.freq_tile);
+  else fts = {16, 8, 32, 4};
+  out.clear();
+  std::vector<int> seen_mg;
+  for (double sg : sig) {
+    int w = prm.kernel_width != 0 ? prm.kernel_width : width_for(tol, sg);
+    int mg = next_smooth_even((long)std::ceil(sg * dm.nq));
+    if (mg < 2 * w) mg = next_smooth_even(2 * w);
+    if (std::find(seen_mg.begin(), seen_mg.end(), mg) != seen_mg.end()) continue;
+    seen_mg.push_back(mg);
+    FftPlan fp;
+    if (!make_fft_plan(mg, fp)) continue;
+    if (prm.freq_tile != 0) {
+      // a requested tile is halved until it fits
+      int ft = prm.freq_tile;
+      while (ft > 1 && !choice_fits(dm, mg, w, ft)) ft /= 2;
+      if (choice_fits(dm, mg, w, ft)) out.push_back({mg, w, ft});
+    } else {
+      for (int ft : fts)
+        if (choice_fits(dm, mg, w, ft)) out.push_back({mg, w, ft});
+      if (out.empty() || out.back().mg != mg) {
+        int ft = 16;
+        while (ft > 1 && !choice_fits(dm, mg, w, ft)) ft /= 2;
+        if (choice_fits(dm, mg, w, ft)) out.push_back({mg, w, ft});
+      }
+    }
+  }
+  if (out.empty()) return fail(AAHRT_E_UNSUPPORTED, "q-grid too large for LDS");
+  return AAHRT_OK;
+}
+
+// Make one candidate current: grid dimensions, kernel shape, q-grid FFT plan, and
+// the device deapodisation and q-grid twiddle tables.
+int set_nufft(Plan& P, const NufftChoice& c) {
+  Dims& dm = P.dm;
+  if (!make_fft_plan(c.mg, P.fft_grid)) return fail(AAHRT_E_UNSUPPORTED, "q-grid length not 5-smooth");
+  dm.mg = c.mg;
+  dm.w = c.w;
+  P.sigma = (double)c.mg / dm.nq;
+  const double beta = 0.98 * M_PI * (1.0 - 1.0 / (2.0 * P.sigma)) * c.w;
+  dm.beta = (float)beta;
+  dm.cbeta = (float)(beta / std::log(2.0));
+  dm.ldr = slot_row(c.mg, c.w);
+  dm.qhalf = dm.nq / 2;
+  dm.ft = c.ft;
+  dm.nftile = (dm.nf + c.ft - 1) / c.ft;
+  // deapodisation 1/Phi(2 pi k/mg) of mode k = l - nq/2
+  std::vector<float> deapod(dm.nq);
+  for (int l = 0; l < dm.nq; ++l) {
+    const int k = l - dm.qhalf;
+    deapod[l] = (float)(1.0 / es_transform(2.0 * M_PI * k / c.mg, c.w, beta));
+  }
+  std::vector<float2> tw_grid(c.mg);
+  for (int t = 0; t < c.mg; ++t) {
+    const double a = -2.0 * M_PI * t / c.mg;
+    tw_grid[t] = make_float2((float)std::cos(a), (float)std::sin(a));
+  }
+  HIP_TRY(hipMemcpy(P.deapod_dev, deapod.data(), deapod.size() * sizeof(float), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(P.twgrid_dev, tw_grid.data(), tw_grid.size() * sizeof(float2), hipMemcpyHostToDevice));
+  return AAHRT_OK;
+}
+
+// Time the GFST stage (one interpolation and one spreading launch over the whole
+// batch, on zeroed spectra) for every candidate and keep the fastest.  The
+// candidates give the same result to within the tolerance; the tile alone does not
+// change any result.
+int autotune_nufft(Plan& P, const std::vector<NufftChoice>& cands) {
+  const auto t_start = std::chrono::steady_clock::now();
+  hipStream_t s = nullptr;
+  HIP_TRY(hipStreamCreate(&s));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = AAHRT_OK;
+  size_t best = 0;
+  float best_ms = 0.f;
+  auto run = [&](int reps, float* ms) -> int {
+    HIP_TRY(hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r) {
+      HIP_TRY(launch_nufft_interp(P, P.mhat, P.dhat, s));
+      HIP_TRY(launch_nufft_spread(P, P.dhat, P.mhat, s));
+    }
+    HIP_TRY(hipEventRecord(e1, s));
+    HIP_TRY(hipEventSynchronize(e1));
+    HIP_TRY(hipEventElapsedTime(ms, e0, e1));
+    *ms /= reps;
+    return AAHRT_OK;
+  };
+  do {
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+      rc = fail(AAHRT_E_HIP, "hipEventCreate failed");
+      break;
+    }
+    const size_t rows = (size_t)P.dm.batch * P.dm.ntheta * P.dm.nq;
+    if (launch_fill(reinterpret_cast<float*>(P.mhat), 0.f, 2 * rows * P.dm.nf, s) != hipSuccess ||
+        launch_fill(reinterpret_cast<float*>(P.dhat), 0.f, 2 * (size_t)P.dm.ntr * P.dm.nf, s) != hipSuccess ||
+        launch_fill(P.tr_bound, 1.f, (size_t)P.dm.ntr, s) != hipSuccess) {
+      rc = fail(AAHRT_E_HIP, "autotune fill failed");
+      break;
+    }
+    for (size_t i = 0; i < cands.size() && rc == AAHRT_OK; ++i) {
+      if ((rc = set_nufft(P, cands[i])) != AAHRT_OK) break;
+      float ms = 0.f;
+      if ((rc = run(1, &ms)) != AAHRT_OK) break;           // warm-up (and a first estimate)
+      if ((rc = run(ms > 50.f ? 1 : 3, &ms)) != AAHRT_OK) break;
+      P.tune_ms.push_back(ms);
+      if (i == 0 || ms < best_ms) {
+        best = i;
+        best_ms = ms;
+      }
+    }
+  } while (false);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamDestroy(s);
+  if (rc != AAHRT_OK) return rc;
+  P.tune_choice = (int)best;
+  TRY(set_nufft(P, cands[best]));
+  P.autotune_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  return AAHRT_OK;
+}
+
 int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* trace_ptr,
                const double* x, const double* y) {
   P.prm = prm;
@@ -262,37 +418,11 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
   if (!make_fft_plan(dm.nh, P.fft_half))
     return fail(AAHRT_E_UNSUPPORTED, "FFT length N/2 = " + std::to_string(dm.nh) + " exceeds the LDS FFT limits");
 
-  // nonuniform FFT parameters
-  const double tol = prm.nufft_tol == 0.0 ? 1e-6 : prm.nufft_tol;
-  double sigma = prm.sigma == 0.0 ? 2.0 : prm.sigma;
-  int w = prm.kernel_width;
-  if (w == 0) {
-    // measured error of the exponential-of-semicircle kernel at sigma = 2: about 0.9 * 10^-(w-1)
-    w = (int)std::ceil(-std::log10(tol / 0.9)) + 1;
-    if (sigma < 2.0) w += 2;
-    w = std::min(12, std::max(3, w));
-  }
-  int mg = next_smooth_even((long)std::ceil(sigma * dm.nq));
-  if (mg < 2 * w) mg = next_smooth_even(2 * w);
-  dm.mg = mg;
-  dm.w = w;
-  P.sigma = (double)mg / dm.nq;
-  const double beta = 0.98 * M_PI * (1.0 - 1.0 / (2.0 * P.sigma)) * w;
-  dm.beta = (float)beta;
-  dm.cbeta = (float)(beta / std::log(2.0));
-  // row length of a q-grid slot: the ghost cells, and room for the padded first FFT pass
-  dm.ldr = std::max(mg + w - 1, (mg - 1) + ((mg - 1) >> 4) + 1);
-  if (dm.ldr % 2 == 0) dm.ldr += 1;
+  // nonuniform FFT parameters: the candidate (sigma, w, ft) list; the first one
+  // is built now, the others are timed by the autotuner once the plan is complete
   dm.qhalf = dm.nq / 2;
-
-  // frequency tile
-  if (!make_fft_plan(mg, P.fft_grid)) return fail(AAHRT_E_UNSUPPORTED, "q-grid length not 5-smooth");
-  int ft = prm.freq_tile == 0 ? 16 : prm.freq_tile;
-  while (ft > 1 && (grid_lds(ft, dm.ldr, dm.ntheta, mg) > 160 * 1024 || dm.nq * ft > kPrefetchCells)) ft /= 2;
-  if (dm.nq > kPrefetchCells) return fail(AAHRT_E_UNSUPPORTED, "nq too large for the q-coefficient prefetch");
-  if (grid_lds(ft, dm.ldr, dm.ntheta, mg) > 160 * 1024) return fail(AAHRT_E_UNSUPPORTED, "q-grid too large for LDS");
-  dm.ft = ft;
-  dm.nftile = (dm.nf + ft - 1) / ft;
+  std::vector<NufftChoice> cands;
+  TRY(nufft_candidates(prm, dm, cands));
   if (2 * (size_t)dm.nhp * sizeof(float2) > 160 * 1024 || std::max(dm.nt, dm.ntau) > 2 * dm.nh)
     return fail(AAHRT_E_UNSUPPORTED, "row FFT too large for LDS");
 
@@ -339,24 +469,13 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
     ut_ptr[r + 1] = (int)ut_idx.size();
   }
 
-  // ---- deapodisation
-  std::vector<float> deapod(dm.nq);
-  for (int l = 0; l < dm.nq; ++l) {
-    const int k = l - dm.qhalf;
-    deapod[l] = (float)(1.0 / es_transform(2.0 * M_PI * k / mg, w, beta));
-  }
-
-  // ---- twiddles
-  std::vector<float2> tw_half(dm.nh), tw_real(dm.nh), tw_grid(mg);
+  // ---- twiddles of the row transforms
+  std::vector<float2> tw_half(dm.nh), tw_real(dm.nh);
   for (int t = 0; t < dm.nh; ++t) {
     const double a = -2.0 * M_PI * t / dm.nh;
     tw_half[t] = make_float2((float)std::cos(a), (float)std::sin(a));
     const double b = -2.0 * M_PI * t / dm.nfft;
     tw_real[t] = make_float2((float)std::cos(b), (float)std::sin(b));
-  }
-  for (int t = 0; t < mg; ++t) {
-    const double a = -2.0 * M_PI * t / mg;
-    tw_grid[t] = make_float2((float)std::cos(a), (float)std::sin(a));
   }
 
   // ---- per-trace tables in bin order
@@ -407,8 +526,15 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
   TRY(upload(P, st_ptr, &tb.st_ptr)); TRY(upload(P, st_idx, &tb.st_idx)); TRY(upload(P, st_w, &tb.st_w));
   TRY(upload(P, u_tap, &tb.u_tap));
   TRY(upload(P, ut_ptr, &tb.ut_ptr)); TRY(upload(P, ut_idx, &tb.ut_idx)); TRY(upload(P, ut_w, &tb.ut_w));
-  TRY(upload(P, deapod, &tb.deapod));
-  TRY(upload(P, tw_half, &tb.tw_half)); TRY(upload(P, tw_real, &tb.tw_real)); TRY(upload(P, tw_grid, &tb.tw_grid));
+  TRY(upload(P, tw_half, &tb.tw_half)); TRY(upload(P, tw_real, &tb.tw_real));
+  {
+    int mg_cap = 0;
+    for (const NufftChoice& c : cands) mg_cap = std::max(mg_cap, c.mg);
+    TRY(alloc(P, (size_t)dm.nq, &P.deapod_dev));
+    TRY(alloc(P, (size_t)mg_cap, &P.twgrid_dev));
+    tb.deapod = P.deapod_dev;
+    tb.tw_grid = P.twgrid_dev;
+  }
   TRY(upload(P, tr_row, &tb.tr_row)); TRY(upload(P, tr_b, &tb.tr_b)); TRY(upload(P, tr_a, &tb.tr_a));
   TRY(upload(P, tr_alpha, &tb.tr_alpha)); TRY(upload(P, bin_ptr, &tb.bin_ptr));
   TRY(upload(P, gather_of_row, &tb.gather_of_row));
@@ -434,6 +560,9 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
   TRY(alloc(P, rows, &P.l1row));
   TRY(alloc(P, (size_t)dm.ntr, &P.rss));
   TRY(alloc(P, (size_t)dm.ntr, &P.tr_bound));
+
+  TRY(set_nufft(P, cands[0]));
+  if (cands.size() > 1) TRY(autotune_nufft(P, cands));
   return AAHRT_OK;
 }
 
@@ -619,6 +748,8 @@ int aahrt_plan_query(const aahrt_plan* plan, aahrt_plan_info* info) {
   info->freq_tile = P.dm.ft;
   info->workspace_bytes = (int64_t)P.workspace_bytes;
   info->q_alias_ok = P.q_alias_ok;
+  info->autotune_candidates = (int32_t)P.tune_ms.size();
+  info->autotune_seconds = P.autotune_s;
   return AAHRT_OK;
 }
 

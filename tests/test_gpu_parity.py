@@ -142,6 +142,83 @@ def test_operator_parity_config4_full_size_sampled():
     plan.close()
 
 
+def test_operator_parity_config5_large_sampled():
+    """32 gathers x 4096 traces, nt = 2048, nq = 128, ntheta = 36 (N = 12000): four seeded
+    gathers carry a random model (forward) or random data (adjoint), the others zeros;
+    sampled traces and model rows of those four are checked by the oracle."""
+    import torch
+    w = wl.config5(with_data=False)
+    plan = make_plan(w)
+    gsall = geoms(w)
+    assert plan.info['nfft'] == gsall[0].nfft == 12000
+    print('config5 plan', {k: plan.info[k] for k in ('grid_size', 'kernel_width', 'freq_tile', 'sigma')})
+    tp = w.trace_ptr
+    rng = np.random.default_rng(5)
+    picks = sorted(rng.choice(w.batch, 4, replace=False).tolist())
+    m = torch.zeros(plan.model_shape, dtype=torch.float32, device='cuda:0')
+    d = torch.zeros(plan.data_shape, dtype=torch.float32, device='cuda:0')
+    mh, dh = {}, {}
+    for b in picks:
+        mh[b] = wl.random_model(w.axes, 1, 50 + b)[0]
+        dh[b] = wl.random_data(int(tp[b + 1] - tp[b]), w.axes.nt, 50 + b)
+        m[b] = to_dev(mh[b])
+        d[tp[b]:tp[b + 1]] = to_dev(dh[b])
+    got_d = plan.forward(m)
+    got_m = plan.adjoint(d)
+    for b in picks:
+        g = gsall[b]
+        idx = sorted(rng.choice(g.x.size, 6, replace=False))
+        ref = gfst.forward_traces(mh[b], g, idx)
+        ef = rel(to_host(got_d[tp[b] + np.array(idx)]), ref)
+        rows = [(int(rng.integers(g.ntheta)), int(rng.integers(g.nq))) for _ in range(4)]
+        refm = gfst.adjoint(dh[b], g, rows=rows)
+        ea = rel(np.stack([to_host(got_m[b, j, l]) for j, l in rows]), refm)
+        print(f'config5 gather {b}: forward {ef:.2e} adjoint {ea:.2e}')
+        assert ef < TOL and ea < TOL
+    # gathers with zero input give exactly zero output
+    zb = [b for b in range(w.batch) if b not in picks][:3]
+    for b in zb:
+        assert float(got_m[b].abs().max()) == 0.0
+        assert float(got_d[tp[b]:tp[b + 1]].abs().max()) == 0.0
+    plan.close()
+
+
+@pytest.mark.parametrize('sigma,freq_tile', [(1.5, 4), (1.25, 32), (3.0, 1), (2.0, 64)])
+def test_operator_parity_grid_settings(sigma, freq_tile):
+    """Every oversampling and tile the autotuner may pick (and the extremes) meets the bound."""
+    errs = _op_parity(wl.config3(with_data=False), seed=4, sigma=sigma, freq_tile=freq_tile)
+    print(f'sigma {sigma} tile {freq_tile}', [f'{a:.1e}/{b:.1e}' for a, b in errs])
+    for ef, ea in errs:
+        assert ef < TOL and ea < TOL
+
+
+def test_frequency_tile_changes_no_result():
+    """The tile only regroups frequencies: forward and adjoint are bitwise equal across tiles."""
+    w = wl.config3(with_data=False)
+    m = to_dev(wl.random_model(w.axes, w.batch, 9))
+    d = to_dev(wl.random_data(int(w.trace_ptr[-1]), w.axes.nt, 9))
+    outs = []
+    for ft in (4, 16, 32):
+        plan = make_plan(w, sigma=2.0, freq_tile=ft)
+        assert plan.info['freq_tile'] == ft and plan.info['autotune_candidates'] == 0
+        outs.append((to_host(plan.forward(m)), to_host(plan.adjoint(d))))
+        plan.close()
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
+
+
+def test_autotuner_times_the_candidates():
+    w = wl.config3(with_data=False)
+    plan = make_plan(w)
+    info = plan.info
+    print('autotuned', {k: info[k] for k in ('sigma', 'kernel_width', 'freq_tile', 'autotune_candidates',
+                                             'autotune_seconds')})
+    assert info['autotune_candidates'] >= 6          # two oversamplings x several tiles
+    assert info['sigma'] in (2.0, 1.5) and info['freq_tile'] in (4, 8, 16, 32)
+    assert info['kernel_width'] == (7 if info['sigma'] == 2.0 else 9)
+    plan.close()
+
+
 # ------------------------------------------------------------------ solver
 def test_lambda_max_matches_oracle_config1():
     w = wl.config1(with_data=True)
