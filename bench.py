@@ -333,7 +333,8 @@ def main():
         'config': {'workload': w.name, 'gathers': w.batch, 'traces': plan.ntraces, 'nt': a.nt,
                    'nq': a.nq, 'ntheta': a.ntheta, 'fista_iters': n_iter, 'nfft': plan.info['nfft'],
                    'kernel_width': plan.info['kernel_width'], 'grid': plan.info['grid_size'],
-                   'sigma': plan.info['sigma'], 'freq_tile': plan.info['freq_tile']},
+                   'sigma': plan.info['sigma'], 'freq_tile': plan.info['freq_tile'],
+                   'freq_tile_adjoint': plan.info['freq_tile_adjoint']},
         'roofline': roofline,
         'cpu_baseline': cpu,
         'secondary': {'fwd_adj_pairs_per_s': round(pairs_per_s, 1), 'fwd_adj_pair_ms': round(1e3 * t_pair, 3),

@@ -98,11 +98,12 @@ typedef struct aahrt_plan_info {
   int32_t kernel_width;  /* w */
   double sigma;          /* grid_size / nq */
   double beta;           /* kernel shape parameter */
-  int32_t freq_tile;     /* frequencies per GFST work item */
+  int32_t freq_tile;     /* frequencies per work item of the forward GFST kernel (interpolation) */
   int64_t workspace_bytes;
   int32_t q_alias_ok;    /* 1 if nq >= 2 q_max f'_max h2max (Section 3.5 anti-alias rule), else 0 (informational) */
   int32_t autotune_candidates; /* GFST settings timed at plan creation (0: none, the setting was fixed) */
   double autotune_seconds;     /* wall time of that autotuning */
+  int32_t freq_tile_adjoint;   /* frequencies per work item of the adjoint GFST kernel (spreading) */
 } aahrt_plan_info;
 
 /* Version string of the library. */
@@ -124,9 +125,10 @@ const char* aahrt_last_error(void);
  * workspace (hipMalloc).  When sigma or freq_tile is 0 it then autotunes the
  * GFST stage: every admissible (sigma in {2, 1.5}, freq_tile in {4, 8, 16, 32})
  * setting, with the kernel width that meets nufft_tol at that sigma, is timed
- * on one interpolation + one spreading launch over the batch (on zeroed
- * spectra, in a stream of its own, synchronously) and the fastest is kept.
- * The tile changes no result; sigma changes results within the tolerance.
+ * on the interpolation and on the spreading launch over the batch (on zeroed
+ * spectra, in a stream of its own, synchronously); each kernel keeps its fastest
+ * tile and the sigma with the smallest sum is kept.  The tiles change no
+ * result; sigma changes results within the tolerance.
  */
 int aahrt_plan_create(aahrt_plan** out, const aahrt_params* p, int32_t batch,
                       const int64_t* trace_ptr, const double* x_km, const double* y_km,

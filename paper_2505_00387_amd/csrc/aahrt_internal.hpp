@@ -78,12 +78,13 @@ struct Dims {
   int nts;      // nt'
   int nfft, nh, nf;  // N, N/2, bins carried (= N/2)
   int nhp;      // LDS cells of one row FFT buffer: room for the padded first pass
+  int row_ip;   // 1: every pass of the row FFT has at most kBlock butterflies (in-place row kernels)
   int mg;       // q-grid length
   int ldr;      // LDS row length of a q-grid slot: mg + w - 1 ghost cells, padded to odd
   int w;        // kernel width
   float beta;
   float cbeta;  // beta * log2(e)
-  int ft;       // frequencies per GFST tile
+  int ft;       // frequencies per GFST tile (set per launch: interpolation and spreading tile separately)
   int nftile;   // ceil(nf/ft)
   int qhalf;    // nq/2 (mode offset)
 };
@@ -112,8 +113,11 @@ struct Plan {
   float* l1row = nullptr;   // [rows] per-row l1 norms (objective)
   float* rss = nullptr;     // [ntr] per-trace residual sums of squares (objective)
   float* tr_bound = nullptr; // [ntr] max_f |Re Dh| + |Im Dh| of each trace (spreading scale bound)
+  float* slice_scale = nullptr; // [batch][ntheta] fixed-point scale of each azimuth slice (spreading)
   float* deapod_dev = nullptr;   // [nq] deapodisation of the current q-grid setting
   float2* twgrid_dev = nullptr;  // [mg] q-grid twiddles of the current setting
+  int ft_interp = 16;            // frequency tile of the interpolation kernel
+  int ft_spread = 16;            // frequency tile of the spreading kernel
   std::vector<float> tune_ms;    // GFST stage time of each autotune candidate
   int tune_choice = 0;
   double autotune_s = 0.0;

@@ -110,11 +110,24 @@ __device__ __forceinline__ float pack_from_csr(float2* buf, const float* g, cons
 }
 
 // ------------------------------------------------------------------ model side
-// Row kernels use two LDS buffers of N/2 complex values (FFT ping-pong); the
-// staged input row aliases the second buffer before the first pass.
+// Row kernels transform one row (or trace) per workgroup in LDS.  IP = true:
+// one buffer of N/2 (padded) complex values, transformed in place, plus a
+// staging area after it for a real input row; IP = false (long rows whose FFT
+// passes have more butterflies than threads): two ping-pong buffers, the staged
+// input row aliasing the second one before the first pass.
+template <bool INV, bool IP>
+__device__ __forceinline__ float2* row_fft(float2* A, float2* B, const FftPlan& fp, const Tables& tb,
+                                           const Dims& dm) {
+  if (IP) {
+    fft_lds_ip<INV, kBlock>(A, fp, tb.tw_half);
+    return A;
+  }
+  return fft_lds<INV, kBlock>(A, B, fp, 1, dm.nh, tb.tw_half);
+}
 
 // Steps 1-2 of L: M'(tau') = S M, times the deapodisation of its curvature
 // index, real DFT of length N, bins 0..N/2-1 stored as mhat[row][f].
+template <bool IP>
 __global__ __launch_bounds__(kBlock) void k_model_r2c(const float* __restrict__ m,
                                                       float2* __restrict__ mhat, Tables tb, Dims dm,
                                                       FftPlan fp) {
@@ -143,27 +156,29 @@ __global__ __launch_bounds__(kBlock) void k_model_r2c(const float* __restrict__ 
     A[p] = make_float2(a, b);
   }
   __syncthreads();
-  const float2* X = fft_lds<false, kBlock>(A, B, fp, 1, dm.nh, tb.tw_half);
+  const float2* X = row_fft<false, IP>(A, B, fp, tb, dm);
   store_real_spectrum(X, mhat + rid * dm.nf, tb, dm);
 }
 
 // Transpose of steps 1-2: inverse real DFT (1/N, doubled positive bins), first
 // nt' samples, times the deapodisation, then S^T.
+template <bool IP>
 __device__ __forceinline__ const float* model_c2r_core(const float2* __restrict__ mhat, float2* A,
                                                        float2* B, const Tables& tb, const Dims& dm,
                                                        const FftPlan& fp, size_t rid) {
   load_packed_c2r(A, mhat + rid * dm.nf, tb, dm);
   __syncthreads();
-  return reinterpret_cast<const float*>(fft_lds<true, kBlock>(A, B, fp, 1, dm.nh, tb.tw_half));
+  return reinterpret_cast<const float*>(row_fft<true, IP>(A, B, fp, tb, dm));
 }
 
+template <bool IP>
 __global__ __launch_bounds__(kBlock) void k_model_c2r(const float2* __restrict__ mhat,
                                                       float* __restrict__ m, Tables tb, Dims dm,
                                                       FftPlan fp) {
   extern __shared__ float2 lds[];
   const size_t rid = blockIdx.x;
   const int l = (int)(rid % dm.nq);
-  const float* xs = model_c2r_core(mhat, lds, lds + dm.nhp, tb, dm, fp, rid);
+  const float* xs = model_c2r_core<IP>(mhat, lds, lds + dm.nhp, tb, dm, fp, rid);
   const float sc = tb.deapod[l] / (float)dm.nfft;
   float* dst = m + rid * dm.ntau;
   for (int i = threadIdx.x; i < dm.ntau; i += kBlock) {
@@ -176,6 +191,7 @@ __global__ __launch_bounds__(kBlock) void k_model_c2r(const float2* __restrict__
 // Same transpose, fused with one forward-backward step on the row:
 //   x_new = soft(y + gamma g, gamma lambda); y <- x_new + beta (x_new - x_old); x <- x_new
 // (ISTA: y <- x_new).  l1[row] receives sum |x_new| when l1 is not null.
+template <bool IP>
 __global__ __launch_bounds__(kBlock) void k_model_c2r_update(const float2* __restrict__ mhat,
                                                              float* __restrict__ y,
                                                              float* __restrict__ x, Tables tb,
@@ -189,7 +205,7 @@ __global__ __launch_bounds__(kBlock) void k_model_c2r_update(const float2* __res
   const size_t rid = blockIdx.x;
   const int l = (int)(rid % dm.nq);
   const int b = (int)(rid / ((size_t)dm.nq * dm.ntheta));
-  const float* xs = model_c2r_core(mhat, lds, lds + dm.nhp, tb, dm, fp, rid);
+  const float* xs = model_c2r_core<IP>(mhat, lds, lds + dm.nhp, tb, dm, fp, rid);
   const float sc = tb.deapod[l] / (float)dm.nfft;
   const float g = gam[b];
   const float thr = g * lam[b];
@@ -215,6 +231,7 @@ __global__ __launch_bounds__(kBlock) void k_model_c2r_update(const float2* __res
 
 // ------------------------------------------------------------------ data side
 // Steps 4-5 of L: inverse real DFT of Dh[n][0..N/2-1], unstretch.
+template <bool IP>
 __global__ __launch_bounds__(kBlock) void k_data_c2r(const float2* __restrict__ dhat,
                                                      float* __restrict__ d, Tables tb, Dims dm,
                                                      FftPlan fp) {
@@ -224,7 +241,7 @@ __global__ __launch_bounds__(kBlock) void k_data_c2r(const float2* __restrict__ 
   const size_t n = blockIdx.x;
   load_packed_c2r(A, dhat + n * dm.nf, tb, dm);
   __syncthreads();
-  const float* xs = reinterpret_cast<const float*>(fft_lds<true, kBlock>(A, B, fp, 1, dm.nh, tb.tw_half));
+  const float* xs = reinterpret_cast<const float*>(row_fft<true, IP>(A, B, fp, tb, dm));
   const float invN = 1.0f / (float)dm.nfft;
   float* dst = d + n * dm.nt;
 #pragma unroll 4
@@ -236,6 +253,7 @@ __global__ __launch_bounds__(kBlock) void k_data_c2r(const float2* __restrict__ 
 
 // Transpose of step 5 then the forward real DFT (the data side of L^T).
 // tr_bound[n] = max_f (|Re Dh[n,f]| + |Im Dh[n,f]|) (the spreading scale bound).
+template <bool IP>
 __global__ __launch_bounds__(kBlock) void k_data_r2c(const float* __restrict__ d,
                                                      float2* __restrict__ dhat,
                                                      float* __restrict__ tr_bound, Tables tb, Dims dm,
@@ -251,13 +269,14 @@ __global__ __launch_bounds__(kBlock) void k_data_r2c(const float* __restrict__ d
   __syncthreads();
   pack_from_csr(A, g, tb.ut_ptr, tb.ut_idx, tb.ut_w, dm.nts, dm.nh);
   __syncthreads();
-  const float2* X = fft_lds<false, kBlock>(A, B, fp, 1, dm.nh, tb.tw_half);
+  const float2* X = row_fft<false, IP>(A, B, fp, tb, dm);
   const float mx = block_max<kBlock>(store_real_spectrum(X, dhat + n * dm.nf, tb, dm), red);
   if (threadIdx.x == 0) tr_bound[n] = mx;
 }
 
 // Solver data side, in place on dhat[n]: r = d_obs - S^-1 F1^-1 Dh (steps 4-5),
 // then the data side of L^T applied to r.  rss[n] = sum r^2 when not null.
+template <bool IP>
 __global__ __launch_bounds__(kBlock) void k_residual_r2c(float2* __restrict__ dhat,
                                                          const float* __restrict__ dobs,
                                                          float* __restrict__ rss,
@@ -270,8 +289,8 @@ __global__ __launch_bounds__(kBlock) void k_residual_r2c(float2* __restrict__ dh
   const size_t n = blockIdx.x;
   load_packed_c2r(A, dhat + n * dm.nf, tb, dm);
   __syncthreads();
-  float2* X = fft_lds<true, kBlock>(A, B, fp, 1, dm.nh, tb.tw_half);
-  float2* Y = (X == A) ? B : A;
+  float2* X = row_fft<true, IP>(A, B, fp, tb, dm);
+  float2* Y = (X == A) ? B : A;      // IP: the staging area after A
   const float* xs = reinterpret_cast<const float*>(X);
   float* g = reinterpret_cast<float*>(Y);
   const float invN = 1.0f / (float)dm.nfft;
@@ -288,7 +307,7 @@ __global__ __launch_bounds__(kBlock) void k_residual_r2c(float2* __restrict__ dh
   __syncthreads();
   pack_from_csr(X, g, tb.ut_ptr, tb.ut_idx, tb.ut_w, dm.nts, dm.nh);
   __syncthreads();
-  const float2* Z = fft_lds<false, kBlock>(X, Y, fp, 1, dm.nh, tb.tw_half);
+  const float2* Z = row_fft<false, IP>(X, Y, fp, tb, dm);
   const float mx = block_max<kBlock>(store_real_spectrum(Z, dhat + n * dm.nf, tb, dm), red);
   if (threadIdx.x == 0) tr_bound[n] = mx;
   if (rss) {
@@ -524,19 +543,21 @@ __device__ __forceinline__ float2 unpack_fix(unsigned long long v, float inv_s) 
   return make_float2((float)lo * inv_s, (float)hi * inv_s);
 }
 
-// Scale S_s of slice s (all threads of the block receive it).
-__device__ __forceinline__ float slice_scale(int s, const int* bp, const float* __restrict__ tr_bound,
-                                             const Tables& tb, int ntheta, float* red, float* scale_sh) {
+// Scale S_s of every (gather, slice): one block per pair, fixed summation order.
+__global__ __launch_bounds__(kBlock) void k_slice_scales(const float* __restrict__ tr_bound, Tables tb,
+                                                         int ntheta, float* __restrict__ scale) {
+  __shared__ float red[kBlock / 64];
+  const int b = blockIdx.x / ntheta;
+  const int s = blockIdx.x - b * ntheta;
+  const int* bp = tb.bin_ptr + (size_t)b * (ntheta + 1);
   const int sb = s == 0 ? ntheta - 1 : s - 1;
   float part = 0.f;
-  for (int pos = bp[s] + threadIdx.x; pos < bp[s + 1]; pos += kBlockG)
+  for (int pos = bp[s] + threadIdx.x; pos < bp[s + 1]; pos += kBlock)
     part += (1.0f - tb.tr_alpha[pos]) * tr_bound[tb.tr_row[pos]];
-  for (int pos = bp[sb] + threadIdx.x; pos < bp[sb + 1]; pos += kBlockG)
+  for (int pos = bp[sb] + threadIdx.x; pos < bp[sb + 1]; pos += kBlock)
     part += tb.tr_alpha[pos] * tr_bound[tb.tr_row[pos]];
-  const float sum = block_sum<kBlockG>(part, red);
-  if (threadIdx.x == 0) *scale_sh = sum > 0.f ? 0.99f * 2147483647.0f / sum : 1.0f;
-  __syncthreads();
-  return *scale_sh;
+  const float sum = block_sum<kBlock>(part, red);
+  if (threadIdx.x == 0) scale[blockIdx.x] = sum > 0.f ? 0.99f * 2147483647.0f / sum : 1.0f;
 }
 
 // One azimuth bin into the slots lo (weight 1 - alpha, slice j, scale S_lo) and hi
@@ -617,12 +638,10 @@ __device__ __forceinline__ void finish_slot(unsigned long long* slot, float2* sc
 // slice has to stay resident across the whole sweep.
 template <int W>
 __global__ __launch_bounds__(kBlockG) void k_nufft_spread(const float2* __restrict__ dhat,
-                                                          const float* __restrict__ tr_bound,
+                                                          const float* __restrict__ slice_scale,
                                                           float2* __restrict__ mhat, Tables tb,
                                                           Dims dm, FftPlan fpg, int ftl) {
   extern __shared__ float2 lds[];
-  __shared__ float red[kBlockG / 64];
-  __shared__ float scale_sh;
   const int ft = dm.ft;
   const int slot_sz = ft * dm.ldr;
   unsigned long long* slot0 = reinterpret_cast<unsigned long long*>(lds);
@@ -639,6 +658,7 @@ __global__ __launch_bounds__(kBlockG) void k_nufft_spread(const float2* __restri
 
   for (int i = threadIdx.x; i < 2 * slot_sz; i += kBlockG) slot0[i] = 0ull;
   for (int i = threadIdx.x; i < dm.mg; i += kBlockG) twl[i] = tb.tw_grid[i];
+  __syncthreads();
   const int last = dm.ntheta - 1;
   float S_prev = 1.0f;  // scale of the slice finished at this step
 
@@ -648,7 +668,7 @@ __global__ __launch_bounds__(kBlockG) void k_nufft_spread(const float2* __restri
     const int bin = (step == 0 || step == last + 1) ? last : step - 1;
     unsigned long long* lo = step == 0 ? nullptr : (((step - 1) & 1) ? slot1 : slot0);
     unsigned long long* hi = step == last + 1 ? nullptr : ((step & 1) ? slot1 : slot0);
-    const float S_hi = step <= last ? slice_scale(step, bp, tr_bound, tb, dm.ntheta, red, &scale_sh) : 1.0f;
+    const float S_hi = step <= last ? slice_scale[(size_t)b * dm.ntheta + step] : 1.0f;
     spread_bin<W>(lo, hi, bp[bin], bp[bin + 1], dhat, st, f0, S_prev, S_hi, tb, dm, ftl);
     if (step >= 1)
       finish_slot<W>(lo, scratch, mb + (size_t)(step - 1) * slice_stride, f0, 1.0f / S_prev, twl, dm, fpg, ftl);
@@ -746,7 +766,6 @@ __global__ void k_objective(const float* __restrict__ rss, const int64_t* __rest
 }
 
 // ------------------------------------------------------------------ launchers
-static size_t row_lds_bytes(const Dims& dm) { return 2 * (size_t)dm.nhp * sizeof(float2); }
 
 static size_t interp_lds_bytes(const Dims& dm) {
   const int nslot = (dm.ntheta >= 3 ? 3 : dm.ntheta) + 1;
@@ -769,77 +788,80 @@ static hipError_t set_lds(K kernel, size_t bytes) {
   return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+// Launch one row kernel: in place (every FFT pass fits the block) with `stage`
+// real samples of staging after the buffer, else the two-buffer form.
+template <typename KIP, typename KPP, typename... Args>
+static hipError_t launch_row(KIP kip, KPP kpp, const Dims& dm, int stage, unsigned grid, hipStream_t s,
+                             Args... args) {
+  if (grid == 0) return hipSuccess;
+  if (dm.row_ip) {
+    const size_t lds = ((size_t)dm.nhp + (size_t)(stage + 1) / 2) * sizeof(float2);
+    hipError_t e = set_lds(kip, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kip, dim3(grid), dim3(kBlock), lds, s, args...);
+  } else {
+    const size_t lds = 2 * (size_t)dm.nhp * sizeof(float2);
+    hipError_t e = set_lds(kpp, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kpp, dim3(grid), dim3(kBlock), lds, s, args...);
+  }
+  return hipGetLastError();
+}
+
+static unsigned model_rows(const Dims& dm) { return (unsigned)((size_t)dm.batch * dm.ntheta * dm.nq); }
+
 hipError_t launch_model_r2c(const Plan& p, const float* m, float2* mhat, hipStream_t s) {
   const Dims& dm = p.dm;
-  const unsigned rows = (unsigned)((size_t)dm.batch * dm.ntheta * dm.nq);
-  const size_t lds = row_lds_bytes(dm);
-  hipError_t e = set_lds(k_model_r2c, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_model_r2c, dim3(rows), dim3(kBlock), lds, s, m, mhat, p.tb, dm, p.fft_half);
-  return hipGetLastError();
+  return launch_row(k_model_r2c<true>, k_model_r2c<false>, dm, dm.ntau, model_rows(dm), s, m, mhat, p.tb, dm,
+                    p.fft_half);
 }
 
 hipError_t launch_model_c2r(const Plan& p, const float2* mhat, float* m, hipStream_t s) {
   const Dims& dm = p.dm;
-  const unsigned rows = (unsigned)((size_t)dm.batch * dm.ntheta * dm.nq);
-  const size_t lds = row_lds_bytes(dm);
-  hipError_t e = set_lds(k_model_c2r, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_model_c2r, dim3(rows), dim3(kBlock), lds, s, mhat, m, p.tb, dm, p.fft_half);
-  return hipGetLastError();
+  return launch_row(k_model_c2r<true>, k_model_c2r<false>, dm, 0, model_rows(dm), s, mhat, m, p.tb, dm,
+                    p.fft_half);
 }
 
 hipError_t launch_model_c2r_update(const Plan& p, const float2* mhat, float* y, float* x,
                                    const float* gam, const float* lam, float beta, int ista,
                                    float* l1, hipStream_t s) {
   const Dims& dm = p.dm;
-  const unsigned rows = (unsigned)((size_t)dm.batch * dm.ntheta * dm.nq);
-  const size_t lds = row_lds_bytes(dm);
-  hipError_t e = set_lds(k_model_c2r_update, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_model_c2r_update, dim3(rows), dim3(kBlock), lds, s, mhat, y, x, p.tb, dm,
-                     p.fft_half, gam, lam, beta, ista, l1);
-  return hipGetLastError();
+  return launch_row(k_model_c2r_update<true>, k_model_c2r_update<false>, dm, 0, model_rows(dm), s, mhat, y,
+                    x, p.tb, dm, p.fft_half, gam, lam, beta, ista, l1);
 }
 
 hipError_t launch_data_c2r(const Plan& p, const float2* dhat, float* d, hipStream_t s) {
   const Dims& dm = p.dm;
-  if (dm.ntr == 0) return hipSuccess;
-  const size_t lds = row_lds_bytes(dm);
-  hipError_t e = set_lds(k_data_c2r, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_data_c2r, dim3(dm.ntr), dim3(kBlock), lds, s, dhat, d, p.tb, dm, p.fft_half);
-  return hipGetLastError();
+  return launch_row(k_data_c2r<true>, k_data_c2r<false>, dm, 0, (unsigned)dm.ntr, s, dhat, d, p.tb, dm,
+                    p.fft_half);
 }
 
 hipError_t launch_data_r2c(const Plan& p, const float* d, float2* dhat, hipStream_t s) {
   const Dims& dm = p.dm;
-  if (dm.ntr == 0) return hipSuccess;
-  const size_t lds = row_lds_bytes(dm);
-  hipError_t e = set_lds(k_data_r2c, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_data_r2c, dim3(dm.ntr), dim3(kBlock), lds, s, d, dhat, p.tr_bound, p.tb, dm,
-                     p.fft_half);
-  return hipGetLastError();
+  return launch_row(k_data_r2c<true>, k_data_r2c<false>, dm, dm.nt, (unsigned)dm.ntr, s, d, dhat, p.tr_bound,
+                    p.tb, dm, p.fft_half);
 }
 
 hipError_t launch_residual_r2c(const Plan& p, float2* dhat, const float* dobs, float* rss,
                                hipStream_t s) {
   const Dims& dm = p.dm;
-  if (dm.ntr == 0) return hipSuccess;
-  const size_t lds = row_lds_bytes(dm);
-  hipError_t e = set_lds(k_residual_r2c, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_residual_r2c, dim3(dm.ntr), dim3(kBlock), lds, s, dhat, dobs, rss, p.tr_bound,
-                     p.tb, dm, p.fft_half);
-  return hipGetLastError();
+  return launch_row(k_residual_r2c<true>, k_residual_r2c<false>, dm, dm.nt, (unsigned)dm.ntr, s, dhat, dobs,
+                    rss, p.tr_bound, p.tb, dm, p.fft_half);
 }
 
 #define AAHRT_W_CASES(MACRO) \
   MACRO(3) MACRO(4) MACRO(5) MACRO(6) MACRO(7) MACRO(8) MACRO(9) MACRO(10) MACRO(11) MACRO(12)
 
+// Dims of a GFST launch with the kernel's own frequency tile.
+static Dims tile_dims(const Dims& d0, int ft) {
+  Dims dm = d0;
+  dm.ft = ft;
+  dm.nftile = (dm.nf + ft - 1) / ft;
+  return dm;
+}
+
 hipError_t launch_nufft_interp(const Plan& p, const float2* mhat, float2* dhat, hipStream_t s) {
-  const Dims& dm = p.dm;
+  const Dims dm = tile_dims(p.dm, p.ft_interp);
   if (dm.ntr == 0) return hipSuccess;
   const size_t lds = interp_lds_bytes(dm);
   const dim3 grid((unsigned)dm.batch * dm.nftile), block(kBlockG);
@@ -860,16 +882,18 @@ hipError_t launch_nufft_interp(const Plan& p, const float2* mhat, float2* dhat, 
 }
 
 hipError_t launch_nufft_spread(const Plan& p, const float2* dhat, float2* mhat, hipStream_t s) {
-  const Dims& dm = p.dm;
+  const Dims dm = tile_dims(p.dm, p.ft_spread);
   const size_t lds = spread_lds_bytes(dm);
   const dim3 grid((unsigned)dm.batch * dm.nftile), block(kBlockG);
   const int ftl = ilog2(dm.ft);
+  hipLaunchKernelGGL(k_slice_scales, dim3((unsigned)dm.batch * dm.ntheta), dim3(kBlock), 0, s, p.tr_bound, p.tb,
+                     dm.ntheta, p.slice_scale);
   switch (dm.w) {
 #define AAHRT_CASE(WW)                                                                       \
   case WW: {                                                                                 \
     hipError_t e = set_lds(k_nufft_spread<WW>, lds);                                         \
     if (e != hipSuccess) return e;                                                           \
-    hipLaunchKernelGGL(k_nufft_spread<WW>, grid, block, lds, s, dhat, p.tr_bound, mhat, \
+    hipLaunchKernelGGL(k_nufft_spread<WW>, grid, block, lds, s, dhat, p.slice_scale, mhat, \
                        p.tb, dm, p.fft_grid, ftl);                                           \
     break;                                                                                   \
   }

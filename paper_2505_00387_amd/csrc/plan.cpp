@@ -306,6 +306,8 @@ int set_nufft(Plan& P, const NufftChoice& c) {
   dm.qhalf = dm.nq / 2;
   dm.ft = c.ft;
   dm.nftile = (dm.nf + c.ft - 1) / c.ft;
+  P.ft_interp = c.ft;
+  P.ft_spread = c.ft;
   // deapodisation 1/Phi(2 pi k/mg) of mode k = l - nq/2
   std::vector<float> deapod(dm.nq);
   for (int l = 0; l < dm.nq; ++l) {
@@ -322,30 +324,36 @@ int set_nufft(Plan& P, const NufftChoice& c) {
   return AAHRT_OK;
 }
 
-// Time the GFST stage (one interpolation and one spreading launch over the whole
-// batch, on zeroed spectra) for every candidate and keep the fastest.  The
-// candidates give the same result to within the tolerance; the tile alone does not
-// change any result.
+// Time the GFST stage for every candidate, on zeroed spectra: the interpolation
+// and the spreading kernels are timed separately, each keeps its fastest tile for
+// a given oversampling, and the oversampling with the smallest sum is kept.  The
+// oversamplings give the same result to within the tolerance; the tiles change no
+// result.
 int autotune_nufft(Plan& P, const std::vector<NufftChoice>& cands) {
   const auto t_start = std::chrono::steady_clock::now();
   hipStream_t s = nullptr;
   HIP_TRY(hipStreamCreate(&s));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   int rc = AAHRT_OK;
-  size_t best = 0;
-  float best_ms = 0.f;
-  auto run = [&](int reps, float* ms) -> int {
-    HIP_TRY(hipEventRecord(e0, s));
-    for (int r = 0; r < reps; ++r) {
-      HIP_TRY(launch_nufft_interp(P, P.mhat, P.dhat, s));
-      HIP_TRY(launch_nufft_spread(P, P.dhat, P.mhat, s));
+  // time one kernel (0: interpolation, 1: spreading): a warm-up launch, then 1 or 3 timed
+  auto run = [&](int which, float* ms) -> int {
+    for (int pass = 0; pass < 2; ++pass) {
+      const int reps = pass == 0 ? 1 : (*ms > 25.f ? 1 : 3);
+      HIP_TRY(hipEventRecord(e0, s));
+      for (int r = 0; r < reps; ++r) {
+        if (which == 0) HIP_TRY(launch_nufft_interp(P, P.mhat, P.dhat, s));
+        else HIP_TRY(launch_nufft_spread(P, P.dhat, P.mhat, s));
+      }
+      HIP_TRY(hipEventRecord(e1, s));
+      HIP_TRY(hipEventSynchronize(e1));
+      HIP_TRY(hipEventElapsedTime(ms, e0, e1));
+      *ms /= reps;
     }
-    HIP_TRY(hipEventRecord(e1, s));
-    HIP_TRY(hipEventSynchronize(e1));
-    HIP_TRY(hipEventElapsedTime(ms, e0, e1));
-    *ms /= reps;
     return AAHRT_OK;
   };
+  NufftChoice best{0, 0, 0};
+  int best_fi = 0, best_fs = 0;
+  float best_total = 0.f;
   do {
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
       rc = fail(AAHRT_E_HIP, "hipEventCreate failed");
@@ -358,24 +366,37 @@ int autotune_nufft(Plan& P, const std::vector<NufftChoice>& cands) {
       rc = fail(AAHRT_E_HIP, "autotune fill failed");
       break;
     }
-    for (size_t i = 0; i < cands.size() && rc == AAHRT_OK; ++i) {
-      if ((rc = set_nufft(P, cands[i])) != AAHRT_OK) break;
-      float ms = 0.f;
-      if ((rc = run(1, &ms)) != AAHRT_OK) break;           // warm-up (and a first estimate)
-      if ((rc = run(ms > 50.f ? 1 : 3, &ms)) != AAHRT_OK) break;
-      P.tune_ms.push_back(ms);
-      if (i == 0 || ms < best_ms) {
-        best = i;
-        best_ms = ms;
+    for (size_t i = 0; i < cands.size() && rc == AAHRT_OK;) {
+      // candidates of one oversampling are consecutive
+      size_t j = i;
+      float bi = 0.f, bs = 0.f;
+      int fi = 0, fs = 0;
+      for (; j < cands.size() && cands[j].mg == cands[i].mg && rc == AAHRT_OK; ++j) {
+        if ((rc = set_nufft(P, cands[j])) != AAHRT_OK) break;
+        float ti = 0.f, ts = 0.f;
+        if ((rc = run(0, &ti)) != AAHRT_OK || (rc = run(1, &ts)) != AAHRT_OK) break;
+        P.tune_ms.push_back(ti);
+        P.tune_ms.push_back(ts);
+        if (j == i || ti < bi) { bi = ti; fi = cands[j].ft; }
+        if (j == i || ts < bs) { bs = ts; fs = cands[j].ft; }
       }
+      if (rc != AAHRT_OK) break;
+      if (best.mg == 0 || bi + bs < best_total) {
+        best = cands[i];
+        best_fi = fi;
+        best_fs = fs;
+        best_total = bi + bs;
+      }
+      i = j;
     }
   } while (false);
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   (void)hipStreamDestroy(s);
   if (rc != AAHRT_OK) return rc;
-  P.tune_choice = (int)best;
-  TRY(set_nufft(P, cands[best]));
+  TRY(set_nufft(P, best));
+  P.ft_interp = best_fi;
+  P.ft_spread = best_fs;
   P.autotune_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   return AAHRT_OK;
 }
@@ -417,6 +438,9 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
   dm.nhp = (dm.nh - 1) + ((dm.nh - 1) >> 4) + 1;
   if (!make_fft_plan(dm.nh, P.fft_half))
     return fail(AAHRT_E_UNSUPPORTED, "FFT length N/2 = " + std::to_string(dm.nh) + " exceeds the LDS FFT limits");
+  dm.row_ip = 1;
+  for (int i = 0; i < P.fft_half.npass; ++i)
+    if (P.fft_half.pass[i].nb > kBlock) dm.row_ip = 0;
 
   // nonuniform FFT parameters: the candidate (sigma, w, ft) list; the first one
   // is built now, the others are timed by the autotuner once the plan is complete
@@ -560,6 +584,7 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
   TRY(alloc(P, rows, &P.l1row));
   TRY(alloc(P, (size_t)dm.ntr, &P.rss));
   TRY(alloc(P, (size_t)dm.ntr, &P.tr_bound));
+  TRY(alloc(P, (size_t)batch * dm.ntheta, &P.slice_scale));
 
   TRY(set_nufft(P, cands[0]));
   if (cands.size() > 1) TRY(autotune_nufft(P, cands));
@@ -745,7 +770,8 @@ int aahrt_plan_query(const aahrt_plan* plan, aahrt_plan_info* info) {
   info->kernel_width = P.dm.w;
   info->sigma = P.sigma;
   info->beta = P.dm.beta;
-  info->freq_tile = P.dm.ft;
+  info->freq_tile = P.ft_interp;
+  info->freq_tile_adjoint = P.ft_spread;
   info->workspace_bytes = (int64_t)P.workspace_bytes;
   info->q_alias_ok = P.q_alias_ok;
   info->autotune_candidates = (int32_t)P.tune_ms.size();
