@@ -87,6 +87,7 @@ struct Dims {
   int ft;       // frequencies per GFST tile (set per launch: interpolation and spreading tile separately)
   int nftile;   // ceil(nf/ft)
   int qhalf;    // nq/2 (mode offset)
+  int gdt;      // storage of the forward q-grid (aahrt_grid_dtype)
 };
 
 struct Plan {
@@ -140,6 +141,26 @@ struct Plan {
   hipStream_t cap_stream = nullptr;
   std::string graph_key;
 };
+
+// LDS of the GFST kernels in float2 units.  Interpolation: the slots (3, or
+// ntheta if fewer; 16-bit grids pack a cell in 4 bytes), the FP32 work buffers
+// of the grid transform (one for an FP32 grid, transformed in its slot; two for a
+// 16-bit grid), the trace stage and the q-grid twiddles.  Spreading: two
+// fixed-point slots, one FP32 work buffer, the stage (with the data values) and
+// the twiddles.
+__host__ __device__ inline size_t interp_slots_f2(int ft, int ldr, int ntheta, int gdt) {
+  const int nslot = ntheta >= 3 ? 3 : ntheta;
+  const size_t cells = (size_t)nslot * ft * ldr;
+  return gdt == AAHRT_GRID_F32 ? cells : (cells + 1) / 2;
+}
+__host__ __device__ inline size_t interp_lds_f2(int ft, int ldr, int ntheta, int mg, int gdt) {
+  const size_t slot = (size_t)ft * ldr;
+  return interp_slots_f2(ft, ldr, ntheta, gdt) + (gdt == AAHRT_GRID_F32 ? 1 : 2) * slot +
+         (size_t)kStageTraces * (3 + ft) + mg;
+}
+__host__ __device__ inline size_t spread_lds_f2(int ft, int ldr, int mg) {
+  return 3 * (size_t)ft * ldr + (size_t)kStageTraces * (3 + ft) + mg;
+}
 
 // ---- kernels (kernels.hip) ----
 hipError_t launch_model_r2c(const Plan& p, const float* m, float2* mhat, hipStream_t s);

@@ -457,16 +457,59 @@ __device__ __forceinline__ void build_grid(float2* G, float2* scratch, const flo
   __syncthreads();
 }
 
-template <int W>
+// Storage of the forward q-grid.  GD = AAHRT_GRID_F32: the FP32 grid itself;
+// GD = AAHRT_GRID_F16 / AAHRT_GRID_BF16: one 32-bit cell holds (Re, Im) as two
+// 16-bit floats (rounded to nearest even), built by an FP32 transform and read
+// back into FP32 for the interpolation, which accumulates in FP32.
+template <int GD>
+struct GridCell {
+  using T = unsigned;
+};
+template <>
+struct GridCell<AAHRT_GRID_F32> {
+  using T = float2;
+};
+
+template <int GD>
+__device__ __forceinline__ typename GridCell<GD>::T enc_cell(float2 v) {
+  if constexpr (GD == AAHRT_GRID_F32) {
+    return v;
+  } else if constexpr (GD == AAHRT_GRID_F16) {
+    const _Float16 a = (_Float16)v.x, b = (_Float16)v.y;
+    return (unsigned)__builtin_bit_cast(unsigned short, a) | ((unsigned)__builtin_bit_cast(unsigned short, b) << 16);
+  } else {
+    unsigned a = __float_as_uint(v.x), b = __float_as_uint(v.y);
+    a = (a + 0x7FFFu + ((a >> 16) & 1u)) >> 16;
+    b = (b + 0x7FFFu + ((b >> 16) & 1u)) >> 16;
+    return a | (b << 16);
+  }
+}
+
+template <int GD>
+__device__ __forceinline__ float2 dec_cell(typename GridCell<GD>::T c) {
+  if constexpr (GD == AAHRT_GRID_F32) {
+    return c;
+  } else if constexpr (GD == AAHRT_GRID_F16) {
+    const _Float16 a = __builtin_bit_cast(_Float16, (unsigned short)(c & 0xFFFFu));
+    const _Float16 b = __builtin_bit_cast(_Float16, (unsigned short)(c >> 16));
+    return make_float2((float)a, (float)b);
+  } else {
+    return make_float2(__uint_as_float(c << 16), __uint_as_float(c & 0xFFFF0000u));
+  }
+}
+
+template <int W, int GD>
 __global__ __launch_bounds__(kBlockG) void k_nufft_interp(const float2* __restrict__ mhat,
                                                           float2* __restrict__ dhat, Tables tb,
                                                           Dims dm, FftPlan fpg, int ftl) {
+  using Cell = typename GridCell<GD>::T;
   extern __shared__ float2 lds[];
   const int ldr = dm.ldr;
   const int ft = dm.ft;
   const int slot_sz = ft * ldr;
-  const int nslot = dm.ntheta >= 3 ? 3 : dm.ntheta;
-  float2* scratch = lds + nslot * slot_sz;
+  Cell* slots = reinterpret_cast<Cell*>(lds);
+  float2* work = lds + interp_slots_f2(ft, ldr, dm.ntheta, GD);   // 16-bit grids: FP32 transform buffer
+  float2* scratch = GD == AAHRT_GRID_F32 ? work : work + slot_sz;  // FFT ping-pong partner
   const Stage st = stage_at(scratch + slot_sz);
   float2* twl = scratch + slot_sz + kStageTraces * (3 + ft);  // q-grid twiddles
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -488,8 +531,8 @@ __global__ __launch_bounds__(kBlockG) void k_nufft_interp(const float2* __restri
     if (sb < dm.ntheta) load_coefs(cr, mb + (size_t)sb * slice_stride, f0, dm, ftl);
     if (j >= 0) {
       const int j1 = (j + 1 == dm.ntheta) ? 0 : j + 1;
-      const float2* G0 = lds + slot_of(j) * slot_sz;
-      const float2* G1 = lds + slot_of(j1) * slot_sz;
+      const Cell* G0 = slots + slot_of(j) * slot_sz;
+      const Cell* G1 = slots + slot_of(j1) * slot_sz;
       for (int c0 = bp[j]; c0 < bp[j + 1]; c0 += kStageTraces) {
         const int cnt = min(kStageTraces, bp[j + 1] - c0);
         stage_tables(st, tb, c0, cnt);
@@ -500,13 +543,13 @@ __global__ __launch_bounds__(kBlockG) void k_nufft_interp(const float2* __restri
           const unsigned f = (unsigned)(f0 + fl);
           if (f >= (unsigned)dm.nf) continue;
           const KernelPoint kp = kernel_point<W>(f, st.b[ti], dm.mg);
-          const float2* g0 = G0 + fl * ldr + kp.base;
-          const float2* g1 = G1 + fl * ldr + kp.base;
+          const Cell* g0 = G0 + fl * ldr + kp.base;
+          const Cell* g1 = G1 + fl * ldr + kp.base;
           float2 a0 = make_float2(0.f, 0.f), a1 = make_float2(0.f, 0.f);
 #pragma unroll
           for (int t = 0; t < W; ++t) {
             const float ph = es_tap(fmaf((float)t, -2.0f / (float)W, kp.z0), dm.cbeta);
-            const float2 v0 = g0[t], v1 = g1[t];
+            const float2 v0 = dec_cell<GD>(g0[t]), v1 = dec_cell<GD>(g1[t]);
             a0.x = fmaf(ph, v0.x, a0.x);
             a0.y = fmaf(ph, v0.y, a0.y);
             a1.x = fmaf(ph, v1.x, a1.x);
@@ -519,7 +562,16 @@ __global__ __launch_bounds__(kBlockG) void k_nufft_interp(const float2* __restri
         __syncthreads();
       }
     }
-    if (sb < dm.ntheta) build_grid<W>(lds + slot_of(sb) * slot_sz, scratch, cr, twl, dm, fpg, ftl);
+    if (sb < dm.ntheta) {
+      if constexpr (GD == AAHRT_GRID_F32) {
+        build_grid<W>(slots + slot_of(sb) * slot_sz, scratch, cr, twl, dm, fpg, ftl);
+      } else {
+        build_grid<W>(work, scratch, cr, twl, dm, fpg, ftl);
+        Cell* G = slots + slot_of(sb) * slot_sz;
+        for (int i = threadIdx.x; i < slot_sz; i += kBlockG) G[i] = enc_cell<GD>(work[i]);
+        __syncthreads();
+      }
+    }
   }
 }
 
@@ -768,13 +820,10 @@ __global__ void k_objective(const float* __restrict__ rss, const int64_t* __rest
 // ------------------------------------------------------------------ launchers
 
 static size_t interp_lds_bytes(const Dims& dm) {
-  const int nslot = (dm.ntheta >= 3 ? 3 : dm.ntheta) + 1;
-  return ((size_t)nslot * dm.ft * dm.ldr + (size_t)kStageTraces * (3 + dm.ft) + dm.mg) * sizeof(float2);
+  return interp_lds_f2(dm.ft, dm.ldr, dm.ntheta, dm.mg, dm.gdt) * sizeof(float2);
 }
 
-static size_t spread_lds_bytes(const Dims& dm) {
-  return (3 * (size_t)dm.ft * dm.ldr + (size_t)kStageTraces * (3 + dm.ft) + dm.mg) * sizeof(float2);
-}
+static size_t spread_lds_bytes(const Dims& dm) { return spread_lds_f2(dm.ft, dm.ldr, dm.mg) * sizeof(float2); }
 
 static int ilog2(int v) {
   int l = 0;
@@ -867,15 +916,22 @@ hipError_t launch_nufft_interp(const Plan& p, const float2* mhat, float2* dhat, 
   const dim3 grid((unsigned)dm.batch * dm.nftile), block(kBlockG);
   const int ftl = ilog2(dm.ft);
   switch (dm.w) {
+#define AAHRT_LAUNCH_INTERP(WW, GG)                                                               \
+  {                                                                                               \
+    hipError_t e = set_lds(k_nufft_interp<WW, GG>, lds);                                          \
+    if (e != hipSuccess) return e;                                                                \
+    hipLaunchKernelGGL((k_nufft_interp<WW, GG>), grid, block, lds, s, mhat, dhat, p.tb, dm, p.fft_grid, ftl); \
+  }
 #define AAHRT_CASE(WW)                                                                       \
   case WW: {                                                                                 \
-    hipError_t e = set_lds(k_nufft_interp<WW>, lds);                                         \
-    if (e != hipSuccess) return e;                                                           \
-    hipLaunchKernelGGL(k_nufft_interp<WW>, grid, block, lds, s, mhat, dhat, p.tb, dm, p.fft_grid, ftl); \
+    if (dm.gdt == AAHRT_GRID_F16) AAHRT_LAUNCH_INTERP(WW, AAHRT_GRID_F16)                    \
+    else if (dm.gdt == AAHRT_GRID_BF16) AAHRT_LAUNCH_INTERP(WW, AAHRT_GRID_BF16)             \
+    else AAHRT_LAUNCH_INTERP(WW, AAHRT_GRID_F32)                                             \
     break;                                                                                   \
   }
     AAHRT_W_CASES(AAHRT_CASE)
 #undef AAHRT_CASE
+#undef AAHRT_LAUNCH_INTERP
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

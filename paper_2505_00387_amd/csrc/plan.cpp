@@ -209,19 +209,13 @@ int validate_params(const aahrt_params& q) {
     return bad("freq_tile must be 0 or a power of two in 1..64");
   if (q.grid_dtype != AAHRT_GRID_F32 && q.grid_dtype != AAHRT_GRID_F16 && q.grid_dtype != AAHRT_GRID_BF16)
     return bad("grid_dtype must be 0, 1 or 2");
-  if (q.grid_dtype != AAHRT_GRID_F32) return fail(AAHRT_E_UNSUPPORTED, "only the FP32 q-grid is built");
   return AAHRT_OK;
 }
 
-// LDS of a GFST workgroup (rows of ldr cells): interpolation uses up to three
-// azimuth-slice slots + one FFT scratch slot, spreading two fixed-point slots + scratch;
-// both stage per-trace tables.  The larger of the two.
-size_t grid_lds(int ft, int ldr, int ntheta, int mg) {
-  const int nslot = (ntheta >= 3 ? 3 : ntheta) + 1;
-  const size_t extra = ((size_t)kStageTraces * (3 + ft) + mg) * sizeof(float2);  // stage + twiddles
-  const size_t interp = (size_t)nslot * ft * ldr * sizeof(float2) + extra;
-  const size_t spread = 3 * (size_t)ft * ldr * sizeof(float2) + extra;
-  return interp > spread ? interp : spread;
+// LDS bytes of the larger of the two GFST kernels for a tile of ft frequencies.
+size_t grid_lds(int ft, int ldr, int ntheta, int mg, int gdt) {
+  const size_t a = interp_lds_f2(ft, ldr, ntheta, mg, gdt), b = spread_lds_f2(ft, ldr, mg);
+  return (a > b ? a : b) * sizeof(float2);
 }
 
 // One setting of the q nonuniform FFT: oversampled grid length mg (sigma = mg/nq),
@@ -247,7 +241,7 @@ int slot_row(int mg, int w) {
 }
 
 bool choice_fits(const Dims& dm, int mg, int w, int ft) {
-  return grid_lds(ft, slot_row(mg, w), dm.ntheta, mg) <= 160 * 1024 && dm.nq * ft <= kPrefetchCells;
+  return grid_lds(ft, slot_row(mg, w), dm.ntheta, mg, dm.gdt) <= 160 * 1024 && dm.nq * ft <= kPrefetchCells;
 }
 
 // Candidates: the requested sigma (or 2 and 1.5 when it is free) with the width from
@@ -445,6 +439,7 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
   // nonuniform FFT parameters: the candidate (sigma, w, ft) list; the first one
   // is built now, the others are timed by the autotuner once the plan is complete
   dm.qhalf = dm.nq / 2;
+  dm.gdt = prm.grid_dtype;
   std::vector<NufftChoice> cands;
   TRY(nufft_candidates(prm, dm, cands));
   if (2 * (size_t)dm.nhp * sizeof(float2) > 160 * 1024 || std::max(dm.nt, dm.ntau) > 2 * dm.nh)

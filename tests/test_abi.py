@@ -87,9 +87,11 @@ def test_invalid_geometry_is_rejected():
     assert _create(p, batch=0)[0] == -1
 
 
-def test_reduced_precision_grid_is_reported_unsupported():
-    rc, msg = _create(_params(grid_dtype=1))
-    assert rc == -4
+def test_reduced_precision_grids_pass_validation():
+    # FP16 / BF16 q-grid storage is accepted; without a GPU creation stops at the device
+    for gd in (1, 2):
+        rc, msg = _create(_params(grid_dtype=gd))
+        assert rc != -4 and 'grid_dtype' not in msg
 
 
 def test_null_arguments_are_rejected():

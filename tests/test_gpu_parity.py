@@ -183,6 +183,43 @@ def test_operator_parity_config5_large_sampled():
     plan.close()
 
 
+def test_grid_precision_sweep_large():
+    """Precision of the forward q-grid storage (FP32 / FP16 / BF16, FP32 accumulation) on four
+    seeded gathers of the 4096-trace, N = 12000 workload: relative data error of L m against
+    the oracle on sampled traces, per storage type.  FP32 is held to the bound; the 16-bit
+    grids are reported, with loose sanity limits.  The adjoint does not use the 16-bit grid
+    and is bitwise the same for every storage type."""
+    import torch
+    w5 = wl.config5(with_data=False)
+    rng = np.random.default_rng(55)
+    picks = sorted(rng.choice(w5.batch, 4, replace=False).tolist())
+    w = wl.Workload('cmp_batch32_nt2048_subset', w5.axes, [w5.gathers[b] for b in picks], 1, 'subset')
+    gs = [g for g in geoms(w5)]
+    gs = [gs[b] for b in picks]
+    nfft = gs[0].nfft
+    m = wl.random_model(w.axes, w.batch, 77)
+    d = wl.random_data(int(w.trace_ptr[-1]), w.axes.nt, 77)
+    idx = [sorted(rng.choice(g.x.size, 4, replace=False)) for g in gs]
+    refs = [gfst.forward_traces(m[b], g, idx[b]) for b, g in enumerate(gs)]
+    rows = [(int(rng.integers(g.ntheta)), int(rng.integers(g.nq))) for g in gs]
+    tp = w.trace_ptr
+    errs, adj = {}, {}
+    for gd, name in ((0, 'fp32'), (1, 'fp16'), (2, 'bf16')):
+        plan = make_plan(w, nfft=nfft, sigma=2.0, freq_tile=8, grid_dtype=gd)
+        got = to_host(plan.forward(to_dev(m)))
+        adj[name] = to_host(plan.adjoint(to_dev(d)))
+        errs[name] = max(rel(got[tp[b] + np.array(idx[b])], refs[b]) for b in range(w.batch))
+        plan.close()
+    print('forward relative error by q-grid storage:', {k: f'{v:.2e}' for k, v in errs.items()})
+    assert errs['fp32'] < TOL
+    assert errs['fp16'] < 2e-3 and errs['bf16'] < 2e-2
+    assert errs['fp16'] > errs['fp32'] and errs['bf16'] > errs['fp16']
+    assert np.array_equal(adj['fp16'], adj['fp32']) and np.array_equal(adj['bf16'], adj['fp32'])
+    b = 0
+    refm = gfst.adjoint(d[tp[b]:tp[b + 1]], gs[b], rows=[rows[b]])
+    assert rel(adj['fp32'][b, rows[b][0], rows[b][1]][None], refm) < TOL
+
+
 @pytest.mark.parametrize('sigma,freq_tile', [(1.5, 4), (1.25, 32), (3.0, 1), (2.0, 64)])
 def test_operator_parity_grid_settings(sigma, freq_tile):
     """Every oversampling and tile the autotuner may pick (and the extremes) meets the bound."""
