@@ -142,24 +142,22 @@ struct Plan {
   std::string graph_key;
 };
 
-// LDS of the GFST kernels in float2 units.  Interpolation: the slots (3, or
-// ntheta if fewer; 16-bit grids pack a cell in 4 bytes), the FP32 work buffers
-// of the grid transform (one for an FP32 grid, transformed in its slot; two for a
-// 16-bit grid), the trace stage and the q-grid twiddles.  Spreading: two
-// fixed-point slots, one FP32 work buffer, the stage (with the data values) and
+// LDS of the GFST kernels in float2 units (q-grid transforms run in place).
+// Interpolation: two slots (one if ntheta = 1; 16-bit grids pack a cell in 4
+// bytes, plus one FP32 transform buffer), the trace stage and the q-grid
+// twiddles.  Spreading: two fixed-point slots, the stage with the data values and
 // the twiddles.
 __host__ __device__ inline size_t interp_slots_f2(int ft, int ldr, int ntheta, int gdt) {
-  const int nslot = ntheta >= 3 ? 3 : ntheta;
+  const int nslot = ntheta >= 2 ? 2 : 1;
   const size_t cells = (size_t)nslot * ft * ldr;
   return gdt == AAHRT_GRID_F32 ? cells : (cells + 1) / 2;
 }
 __host__ __device__ inline size_t interp_lds_f2(int ft, int ldr, int ntheta, int mg, int gdt) {
-  const size_t slot = (size_t)ft * ldr;
-  return interp_slots_f2(ft, ldr, ntheta, gdt) + (gdt == AAHRT_GRID_F32 ? 1 : 2) * slot +
-         (size_t)kStageTraces * (3 + ft) + mg;
+  return interp_slots_f2(ft, ldr, ntheta, gdt) + (gdt == AAHRT_GRID_F32 ? 0 : (size_t)ft * ldr) +
+         3 * (size_t)kStageTraces + mg;
 }
 __host__ __device__ inline size_t spread_lds_f2(int ft, int ldr, int mg) {
-  return 3 * (size_t)ft * ldr + (size_t)kStageTraces * (3 + ft) + mg;
+  return 2 * (size_t)ft * ldr + (size_t)kStageTraces * (3 + ft) + mg;
 }
 
 // ---- kernels (kernels.hip) ----

@@ -311,22 +311,30 @@ __device__ __forceinline__ float2* fft_lds(float2* a, float2* b, const FftPlan& 
   return src;
 }
 
-// In-place pass for one sequence whose passes each have at most NT butterflies:
-// every thread reads its butterfly, the block synchronises, then writes it back
-// to its Stockham output positions.  Halves the LDS of the ping-pong form.
+// In-place pass over nbatch sequences (stride bstride) whose butterflies, over all
+// sequences, number at most NT: every thread reads its butterfly, the block
+// synchronises, then writes it back to its Stockham output positions.  Needs half
+// the LDS of the ping-pong form.
 template <int R, bool INV, int NT, bool PIN, bool POUT>
-__device__ __forceinline__ void fft_pass_ip(float2* buf, const FftPass& ps, const float2* __restrict__ tw) {
-  const int j = threadIdx.x;
-  const bool act = j < ps.nb;
+__device__ __forceinline__ void fft_pass_ip(float2* buf, const FftPass& ps, int nbatch, int bstride,
+                                            const float2* __restrict__ tw) {
+  const int bt = threadIdx.x;
+  const bool act = bt < ps.nb * nbatch;
   float2 v[R];
-  int o = 0;
+  int o = 0, fb = 0;
   if (act) {
+    int j = bt;
+    if (nbatch > 1) {
+      fb = (int)fdiv((unsigned)bt, ps.dnb);
+      j = bt - fb * ps.nb;
+    }
     const int jq = (int)fdiv((unsigned)j, ps.dns);
     const int k = j - jq * ps.ns;
+    const float2* x = buf + fb * bstride;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int i = j + r * ps.nb;
-      v[r] = buf[PIN ? pad16(i) : i];
+      v[r] = x[PIN ? pad16(i) : i];
     }
     if (ps.ns > 1) apply_twiddles<R, INV>(v, tw, k * ps.stride);
     Dft<R, INV>::run(v);
@@ -334,39 +342,42 @@ __device__ __forceinline__ void fft_pass_ip(float2* buf, const FftPass& ps, cons
   }
   __syncthreads();
   if (act) {
+    float2* y = buf + fb * bstride;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int i = o + r * ps.ns;
-      buf[POUT ? pad16(i) : i] = v[r];
+      y[POUT ? pad16(i) : i] = v[r];
     }
   }
   __syncthreads();
 }
 
 template <int R, bool INV, int NT>
-__device__ __forceinline__ void fft_pass_ip_sel(float2* buf, const FftPass& ps, const float2* tw, int mode) {
-  if (mode == 1) fft_pass_ip<R, INV, NT, false, true>(buf, ps, tw);
-  else if (mode == 2) fft_pass_ip<R, INV, NT, true, false>(buf, ps, tw);
-  else fft_pass_ip<R, INV, NT, false, false>(buf, ps, tw);
+__device__ __forceinline__ void fft_pass_ip_sel(float2* buf, const FftPass& ps, int nbatch, int bstride,
+                                                const float2* tw, int mode) {
+  if (mode == 1) fft_pass_ip<R, INV, NT, false, true>(buf, ps, nbatch, bstride, tw);
+  else if (mode == 2) fft_pass_ip<R, INV, NT, true, false>(buf, ps, nbatch, bstride, tw);
+  else fft_pass_ip<R, INV, NT, false, false>(buf, ps, nbatch, bstride, tw);
 }
 
-// In-place transform of one sequence (every pass with at most NT butterflies;
-// the caller synchronises before calling).  buf holds pad16(n - 1) + 1 cells;
-// input and result are unpadded.
+// In-place transform of nbatch sequences at buf + b*bstride (every pass with at
+// most NT butterflies in total; the caller synchronises before calling).  Each
+// sequence holds pad16(n - 1) + 1 cells; input and result are unpadded.
 template <bool INV, int NT>
-__device__ __forceinline__ void fft_lds_ip(float2* buf, const FftPlan& pl, const float2* __restrict__ tw) {
+__device__ __forceinline__ void fft_lds_ip(float2* buf, const FftPlan& pl, int nbatch, int bstride,
+                                           const float2* __restrict__ tw) {
   for (int s = 0; s < pl.npass; ++s) {
     const FftPass& ps = pl.pass[s];
     const int mode = pl.npass < 2 ? 0 : (s == 0 ? 1 : (s == 1 ? 2 : 0));
     switch (ps.r) {
-      case 2: fft_pass_ip_sel<2, INV, NT>(buf, ps, tw, mode); break;
-      case 3: fft_pass_ip_sel<3, INV, NT>(buf, ps, tw, mode); break;
-      case 4: fft_pass_ip_sel<4, INV, NT>(buf, ps, tw, mode); break;
-      case 5: fft_pass_ip_sel<5, INV, NT>(buf, ps, tw, mode); break;
-      case 8: fft_pass_ip_sel<8, INV, NT>(buf, ps, tw, mode); break;
-      case 9: fft_pass_ip_sel<9, INV, NT>(buf, ps, tw, mode); break;
-      case 15: fft_pass_ip_sel<15, INV, NT>(buf, ps, tw, mode); break;
-      default: fft_pass_ip_sel<16, INV, NT>(buf, ps, tw, mode); break;
+      case 2: fft_pass_ip_sel<2, INV, NT>(buf, ps, nbatch, bstride, tw, mode); break;
+      case 3: fft_pass_ip_sel<3, INV, NT>(buf, ps, nbatch, bstride, tw, mode); break;
+      case 4: fft_pass_ip_sel<4, INV, NT>(buf, ps, nbatch, bstride, tw, mode); break;
+      case 5: fft_pass_ip_sel<5, INV, NT>(buf, ps, nbatch, bstride, tw, mode); break;
+      case 8: fft_pass_ip_sel<8, INV, NT>(buf, ps, nbatch, bstride, tw, mode); break;
+      case 9: fft_pass_ip_sel<9, INV, NT>(buf, ps, nbatch, bstride, tw, mode); break;
+      case 15: fft_pass_ip_sel<15, INV, NT>(buf, ps, nbatch, bstride, tw, mode); break;
+      default: fft_pass_ip_sel<16, INV, NT>(buf, ps, nbatch, bstride, tw, mode); break;
     }
   }
 }

@@ -119,7 +119,7 @@ template <bool INV, bool IP>
 __device__ __forceinline__ float2* row_fft(float2* A, float2* B, const FftPlan& fp, const Tables& tb,
                                            const Dims& dm) {
   if (IP) {
-    fft_lds_ip<INV, kBlock>(A, fp, tb.tw_half);
+    fft_lds_ip<INV, kBlock>(A, fp, 1, 0, tb.tw_half);
     return A;
   }
   return fft_lds<INV, kBlock>(A, B, fp, 1, dm.nh, tb.tw_half);
@@ -423,10 +423,10 @@ __device__ __forceinline__ void load_coefs(float2* cr, const float2* __restrict_
 }
 
 // Forward q-grid of one slice from its coefficients: g[f][m] = sum_k c_k exp(-2 pi i k m/mg),
-// then the ghost cells g[f][mg + t] = g[f][t], t < W - 1.
+// transformed in place, then the ghost cells g[f][mg + t] = g[f][t], t < W - 1.
 template <int W>
-__device__ __forceinline__ void build_grid(float2* G, float2* scratch, const float2* cr, const float2* twl,
-                                           const Dims& dm, const FftPlan& fpg, int ftl) {
+__device__ __forceinline__ void build_grid(float2* G, const float2* cr, const float2* twl, const Dims& dm,
+                                           const FftPlan& fpg, int ftl) {
   const int ldr = dm.ldr;
   const int ft = dm.ft;
   const int nz = dm.mg - dm.nq;  // zero-padded cells [nq - qhalf, mg - qhalf) of each row
@@ -445,11 +445,7 @@ __device__ __forceinline__ void build_grid(float2* G, float2* scratch, const flo
     }
   }
   __syncthreads();
-  const float2* R = fft_lds<false, kBlockG>(G, scratch, fpg, ft, ldr, twl);
-  if (R != G) {
-    for (int i = threadIdx.x; i < ft * ldr; i += kBlockG) G[i] = R[i];
-    __syncthreads();
-  }
+  fft_lds_ip<false, kBlockG>(G, fpg, ft, ldr, twl);
   for (int i = threadIdx.x; i < ft * (W - 1); i += kBlockG) {
     const int fl = i / (W - 1), t = i - fl * (W - 1);
     G[fl * ldr + dm.mg + t] = G[fl * ldr + t];
@@ -498,6 +494,10 @@ __device__ __forceinline__ float2 dec_cell(typename GridCell<GD>::T c) {
   }
 }
 
+// Forward GFST map (type-2 nonuniform FFT in q plus the azimuth weights) for one
+// gather and a tile of ft frequencies.  Two slots hold the q-grids of slices j
+// and j+1 while bin j is interpolated; slice j+2 (mod ntheta, so slice 0 is
+// built again for the last bin) then replaces slice j.
 template <int W, int GD>
 __global__ __launch_bounds__(kBlockG) void k_nufft_interp(const float2* __restrict__ mhat,
                                                           float2* __restrict__ dhat, Tables tb,
@@ -508,10 +508,9 @@ __global__ __launch_bounds__(kBlockG) void k_nufft_interp(const float2* __restri
   const int ft = dm.ft;
   const int slot_sz = ft * ldr;
   Cell* slots = reinterpret_cast<Cell*>(lds);
-  float2* work = lds + interp_slots_f2(ft, ldr, dm.ntheta, GD);   // 16-bit grids: FP32 transform buffer
-  float2* scratch = GD == AAHRT_GRID_F32 ? work : work + slot_sz;  // FFT ping-pong partner
-  const Stage st = stage_at(scratch + slot_sz);
-  float2* twl = scratch + slot_sz + kStageTraces * (3 + ft);  // q-grid twiddles
+  float2* work = lds + interp_slots_f2(ft, ldr, dm.ntheta, GD);  // 16-bit grids: FP32 transform buffer
+  const Stage st = stage_at(GD == AAHRT_GRID_F32 ? work : work + slot_sz);
+  float2* twl = reinterpret_cast<float2*>(st.row + kStageTraces);  // q-grid twiddles
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int b = tile / dm.nftile;
   const int f0 = (tile - b * dm.nftile) * ft;
@@ -520,19 +519,20 @@ __global__ __launch_bounds__(kBlockG) void k_nufft_interp(const float2* __restri
   const float2* mb = mhat + (size_t)b * dm.ntheta * slice_stride;
   if (bp[dm.ntheta] == bp[0]) return;  // empty gather: nothing to write
   for (int i = threadIdx.x; i < dm.mg; i += kBlockG) twl[i] = tb.tw_grid[i];
-  // slice 0 stays in slot 0 (the last bin wraps onto it); slice s >= 1 uses slot 1 + ((s-1) & 1)
-  auto slot_of = [](int s) { return s == 0 ? 0 : 1 + ((s - 1) & 1); };
+  const int nt = dm.ntheta;
 
-  // step -2 and -1 build slices 0 and 1; step j >= 0 interpolates bin j, then builds slice j + 2.
-  // The coefficients of the slice built at the end of a step are loaded at its start.
+  // step -2 and -1 build slices 0 and 1; step j >= 0 interpolates bin j, then builds
+  // slice (j + 2) mod ntheta into the slot of slice j (while j + 2 <= ntheta).  The
+  // coefficients of the slice built at the end of a step are loaded at its start.
   float2 cr[kCoefRegs];
-  for (int j = -2; j < dm.ntheta; ++j) {
+  for (int j = -2; j < nt; ++j) {
     const int sb = j + 2;
-    if (sb < dm.ntheta) load_coefs(cr, mb + (size_t)sb * slice_stride, f0, dm, ftl);
+    const bool build = sb < 2 ? sb < nt : sb <= nt;
+    const int sbm = sb >= nt ? sb - nt : sb;
+    if (build) load_coefs(cr, mb + (size_t)sbm * slice_stride, f0, dm, ftl);
     if (j >= 0) {
-      const int j1 = (j + 1 == dm.ntheta) ? 0 : j + 1;
-      const Cell* G0 = slots + slot_of(j) * slot_sz;
-      const Cell* G1 = slots + slot_of(j1) * slot_sz;
+      const Cell* G0 = slots + (nt == 1 ? 0 : (j & 1)) * slot_sz;
+      const Cell* G1 = slots + (nt == 1 ? 0 : ((j + 1) & 1)) * slot_sz;
       for (int c0 = bp[j]; c0 < bp[j + 1]; c0 += kStageTraces) {
         const int cnt = min(kStageTraces, bp[j + 1] - c0);
         stage_tables(st, tb, c0, cnt);
@@ -562,12 +562,14 @@ __global__ __launch_bounds__(kBlockG) void k_nufft_interp(const float2* __restri
         __syncthreads();
       }
     }
-    if (sb < dm.ntheta) {
-      if constexpr (GD == AAHRT_GRID_F32) {
-        build_grid<W>(slots + slot_of(sb) * slot_sz, scratch, cr, twl, dm, fpg, ftl);
+    if (build) {
+      if (sb >= 2 && nt == 2 && sbm == 0) {
+        // two slices: slice 0 is still in its slot
+      } else if constexpr (GD == AAHRT_GRID_F32) {
+        build_grid<W>(slots + (sb & 1) * slot_sz, cr, twl, dm, fpg, ftl);
       } else {
-        build_grid<W>(work, scratch, cr, twl, dm, fpg, ftl);
-        Cell* G = slots + slot_of(sb) * slot_sz;
+        build_grid<W>(work, cr, twl, dm, fpg, ftl);
+        Cell* G = slots + (sb & 1) * slot_sz;
         for (int i = threadIdx.x; i < slot_sz; i += kBlockG) G[i] = enc_cell<GD>(work[i]);
         __syncthreads();
       }
@@ -654,12 +656,12 @@ __device__ __forceinline__ void spread_bin(unsigned long long* lo, unsigned long
 }
 
 // Fold the ghost cells back, decode the slot in place to FP32, inverse q-grid
-// FFT: H[k] = sum_m G[m] exp(+2 pi i k m/mg) for the nq modes, written to
+// FFT in place: H[k] = sum_m G[m] exp(+2 pi i k m/mg) for the nq modes, written to
 // Mh[b][s][k + nq/2][f0 + f]; the slot is cleared afterwards.
 template <int W>
-__device__ __forceinline__ void finish_slot(unsigned long long* slot, float2* scratch, float2* __restrict__ out_slice,
-                            int f0, float inv_s, const float2* twl, const Dims& dm, const FftPlan& fpg,
-                            int ftl) {
+__device__ __forceinline__ void finish_slot(unsigned long long* slot, float2* __restrict__ out_slice, int f0,
+                                            float inv_s, const float2* twl, const Dims& dm, const FftPlan& fpg,
+                                            int ftl) {
   const int ldr = dm.ldr;
   const int ft = dm.ft;
   for (int i = threadIdx.x; i < ft * (W - 1); i += kBlockG) {
@@ -670,14 +672,14 @@ __device__ __forceinline__ void finish_slot(unsigned long long* slot, float2* sc
   float2* P = reinterpret_cast<float2*>(slot);
   for (int i = threadIdx.x; i < ft * ldr; i += kBlockG) P[i] = unpack_fix(slot[i], inv_s);
   __syncthreads();
-  const float2* R = fft_lds<true, kBlockG>(P, scratch, fpg, ft, ldr, twl);
+  fft_lds_ip<true, kBlockG>(P, fpg, ft, ldr, twl);
   for (int it = threadIdx.x; it < dm.nq * ft; it += kBlockG) {
     const int l = it >> ftl;
     const int fl = it & (ft - 1);
     const int f = f0 + fl;
     int m = l - dm.qhalf;
     if (m < 0) m += dm.mg;
-    if (f < dm.nf) out_slice[(size_t)l * dm.nf + f] = R[fl * ldr + m];
+    if (f < dm.nf) out_slice[(size_t)l * dm.nf + f] = P[fl * ldr + m];
   }
   __syncthreads();
   for (int i = threadIdx.x; i < ft * ldr; i += kBlockG) slot[i] = 0ull;
@@ -698,9 +700,8 @@ __global__ __launch_bounds__(kBlockG) void k_nufft_spread(const float2* __restri
   const int slot_sz = ft * dm.ldr;
   unsigned long long* slot0 = reinterpret_cast<unsigned long long*>(lds);
   unsigned long long* slot1 = slot0 + slot_sz;
-  float2* scratch = lds + 2 * slot_sz;
-  const Stage st = stage_at(scratch + slot_sz);
-  float2* twl = scratch + slot_sz + kStageTraces * (3 + ft);  // q-grid twiddles
+  const Stage st = stage_at(lds + 2 * slot_sz);
+  float2* twl = lds + 2 * slot_sz + kStageTraces * (3 + ft);  // q-grid twiddles
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int b = tile / dm.nftile;
   const int f0 = (tile - b * dm.nftile) * ft;
@@ -723,7 +724,7 @@ __global__ __launch_bounds__(kBlockG) void k_nufft_spread(const float2* __restri
     const float S_hi = step <= last ? slice_scale[(size_t)b * dm.ntheta + step] : 1.0f;
     spread_bin<W>(lo, hi, bp[bin], bp[bin + 1], dhat, st, f0, S_prev, S_hi, tb, dm, ftl);
     if (step >= 1)
-      finish_slot<W>(lo, scratch, mb + (size_t)(step - 1) * slice_stride, f0, 1.0f / S_prev, twl, dm, fpg, ftl);
+      finish_slot<W>(lo, mb + (size_t)(step - 1) * slice_stride, f0, 1.0f / S_prev, twl, dm, fpg, ftl);
     S_prev = S_hi;
   }
 }

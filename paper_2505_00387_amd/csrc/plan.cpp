@@ -240,7 +240,13 @@ int slot_row(int mg, int w) {
   return ldr % 2 == 0 ? ldr + 1 : ldr;
 }
 
+// A setting fits when its LDS fits a CU, its coefficients fit the register prefetch, and
+// every pass of the in-place q-grid transform has at most one butterfly per thread.
 bool choice_fits(const Dims& dm, int mg, int w, int ft) {
+  FftPlan fp;
+  if (!make_fft_plan(mg, fp)) return false;
+  for (int i = 0; i < fp.npass; ++i)
+    if ((long)fp.pass[i].nb * ft > kBlockG) return false;
   return grid_lds(ft, slot_row(mg, w), dm.ntheta, mg, dm.gdt) <= 160 * 1024 && dm.nq * ft <= kPrefetchCells;
 }
 
