@@ -46,16 +46,16 @@ struct __attribute__((aligned(16))) Tap {
 struct Tables {
   // stretch S (model side): for r < nt', M'(r) = interpolation s_tap[r] of M
   const Tap* s_tap;
-  // S^T as CSR over tau samples
-  const int* st_ptr;
-  const int* st_idx;
-  const float* st_w;
+  // S^T: weights (w0, w1) of every stretched sample (4 zero entries of padding) and
+  // s_start[i] = first stretched sample whose lower tap is >= i (i <= ntau)
+  const int* s_start;
+  const float2* s_w;
   // unstretch U (data side): d(s) = interpolation u_tap[s] of D'
   const Tap* u_tap;
-  // U^T as CSR over stretched samples
-  const int* ut_ptr;
-  const int* ut_idx;
-  const float* ut_w;
+  // U^T: weights of every time sample (4 zero entries of padding) and u_start[r] =
+  // first time sample whose lower tap is >= r (r <= nt')
+  const int* u_start;
+  const float2* u_w;
   // deapodisation 1/Phi(2 pi k/Mg), k = l - nq/2, per curvature sample l
   const float* deapod;
   // twiddles

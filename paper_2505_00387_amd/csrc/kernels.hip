@@ -86,27 +86,39 @@ __device__ __forceinline__ void load_packed_c2r(float2* buf, const float2* __res
   }
 }
 
-// Pack x[r] = sum_{e in CSR row r} w[e] g[idx[e]] (r < nts, zero beyond) as z[p] = x[2p] + i x[2p+1].
-// Returns this thread's share of sum |x[r]|.
-__device__ __forceinline__ float pack_from_csr(float2* buf, const float* g, const int* __restrict__ ptr,
-                                              const int* __restrict__ idx, const float* __restrict__ w,
-                                              int nts, int nh) {
-  float l1 = 0.f;
-  for (int p = threadIdx.x; p < nh; p += kBlock) {
-    float v[2] = {0.f, 0.f};
+// Transpose of a monotone two-tap interpolator at output i (inputs r with lower tap
+// lo(r), non-decreasing in r, weights w[r] = (w0, w1) on lo and lo + 1):
+//   y[i] = sum_{lo(r) = i-1} w1[r] x[r] + sum_{lo(r) = i} w0[r] x[r],
+// where start[i] is the first input whose lower tap is >= i, so both sums run over
+// one contiguous range of inputs.  Loads are issued four at a time.
+__device__ __forceinline__ float lerp_transpose(int i, const int* __restrict__ start, const float2* __restrict__ w,
+                                                const float* x) {
+  const int b = start[i], c = start[i + 1];
+  const int a = i > 0 ? start[i - 1] : b;
+  float acc = 0.f;
+  for (int r0 = a; r0 < c; r0 += 4) {
+    float2 wv[4];
+    float xv[4];
 #pragma unroll
-    for (int e2 = 0; e2 < 2; ++e2) {
-      const int r = 2 * p + e2;
-      if (r < nts) {
-        float acc = 0.f;
-        for (int e = ptr[r]; e < ptr[r + 1]; ++e) acc += w[e] * g[idx[e]];
-        v[e2] = acc;
-      }
+    for (int k = 0; k < 4; ++k) {
+      const int r = r0 + k;
+      wv[k] = r < c ? w[r] : make_float2(0.f, 0.f);
+      xv[k] = r < c ? x[r] : 0.f;
     }
-    buf[p] = make_float2(v[0], v[1]);
-    l1 += fabsf(v[0]) + fabsf(v[1]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc = fmaf(r0 + k < b ? wv[k].y : wv[k].x, xv[k], acc);
   }
-  return l1;
+  return acc;
+}
+
+// Pack x[r] = (U^T g)[r] (r < nts, zero beyond) as z[p] = x[2p] + i x[2p+1].
+__device__ __forceinline__ void pack_transpose(float2* buf, const float* g, const Tables& tb, int nts, int nh) {
+  for (int p = threadIdx.x; p < nh; p += kBlock) {
+    const int r0 = 2 * p, r1 = 2 * p + 1;
+    const float v0 = r0 < nts ? lerp_transpose(r0, tb.u_start, tb.u_w, g) : 0.f;
+    const float v1 = r1 < nts ? lerp_transpose(r1, tb.u_start, tb.u_w, g) : 0.f;
+    buf[p] = make_float2(v0, v1);
+  }
 }
 
 // ------------------------------------------------------------------ model side
@@ -182,9 +194,7 @@ __global__ __launch_bounds__(kBlock) void k_model_c2r(const float2* __restrict__
   const float sc = tb.deapod[l] / (float)dm.nfft;
   float* dst = m + rid * dm.ntau;
   for (int i = threadIdx.x; i < dm.ntau; i += kBlock) {
-    float acc = 0.f;
-    for (int e = tb.st_ptr[i]; e < tb.st_ptr[i + 1]; ++e) acc += tb.st_w[e] * xs[tb.st_idx[e]];
-    dst[i] = sc * acc;
+    dst[i] = sc * lerp_transpose(i, tb.s_start, tb.s_w, xs);
   }
 }
 
@@ -213,9 +223,7 @@ __global__ __launch_bounds__(kBlock) void k_model_c2r_update(const float2* __res
   float* xr = x + rid * dm.ntau;
   float s1 = 0.f;
   for (int i = threadIdx.x; i < dm.ntau; i += kBlock) {
-    float acc = 0.f;
-    for (int e = tb.st_ptr[i]; e < tb.st_ptr[i + 1]; ++e) acc += tb.st_w[e] * xs[tb.st_idx[e]];
-    const float v = yr[i] + g * (sc * acc);
+    const float v = yr[i] + g * (sc * lerp_transpose(i, tb.s_start, tb.s_w, xs));
     const float a = fabsf(v) - thr;
     const float xn = a > 0.f ? copysignf(a, v) : 0.f;
     const float xo = xr[i];
@@ -267,7 +275,7 @@ __global__ __launch_bounds__(kBlock) void k_data_r2c(const float* __restrict__ d
   const float* src = d + n * dm.nt;
   for (int s = threadIdx.x; s < dm.nt; s += kBlock) g[s] = src[s];
   __syncthreads();
-  pack_from_csr(A, g, tb.ut_ptr, tb.ut_idx, tb.ut_w, dm.nts, dm.nh);
+  pack_transpose(A, g, tb, dm.nts, dm.nh);
   __syncthreads();
   const float2* X = row_fft<false, IP>(A, B, fp, tb, dm);
   const float mx = block_max<kBlock>(store_real_spectrum(X, dhat + n * dm.nf, tb, dm), red);
@@ -305,7 +313,7 @@ __global__ __launch_bounds__(kBlock) void k_residual_r2c(float2* __restrict__ dh
     ss += r * r;
   }
   __syncthreads();
-  pack_from_csr(X, g, tb.ut_ptr, tb.ut_idx, tb.ut_w, dm.nts, dm.nh);
+  pack_transpose(X, g, tb, dm.nts, dm.nh);
   __syncthreads();
   const float2* Z = row_fft<false, IP>(X, Y, fp, tb, dm);
   const float mx = block_max<kBlock>(store_real_spectrum(Z, dhat + n * dm.nf, tb, dm), red);
@@ -845,7 +853,7 @@ static hipError_t launch_row(KIP kip, KPP kpp, const Dims& dm, int stage, unsign
                              Args... args) {
   if (grid == 0) return hipSuccess;
   if (dm.row_ip) {
-    const size_t lds = ((size_t)dm.nhp + (size_t)(stage + 1) / 2) * sizeof(float2);
+    const size_t lds = ((size_t)dm.nhp + (size_t)(stage + 5) / 2) * sizeof(float2);  // staging + 4 spare
     hipError_t e = set_lds(kip, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kip, dim3(grid), dim3(kBlock), lds, s, args...);

@@ -455,43 +455,45 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
   const double fmax = (dm.nf - 1) / (dm.nfft * dts);
   P.q_alias_ok = dm.nq >= 2.0 * std::max(std::fabs(prm.q_max), std::fabs(prm.q_min)) * fmax * h2max ? 1 : 0;
 
-  // ---- stretch tables (FP64 positions)
+  // ---- stretch tables (FP64 positions).  Forward: two taps per output.  Transpose:
+  // the inputs of each output form contiguous ranges (positions are monotone), so it
+  // keeps per-input weights (w0, w1) and the first input whose lower tap is >= i.
   std::vector<Tap> s_tap(dm.nts);
-  std::vector<std::vector<std::pair<int, double>>> st(dm.ntau);
-  for (int r = 0; r < dm.nts; ++r) {
-    const double pos = std::sqrt(r * dts) / prm.dtau;
-    const long i = (long)std::floor(pos);
-    const double a = pos - (double)i;
-    int i0 = 0, i1 = 0;
-    double w0 = 0.0, w1 = 0.0;
-    if (i >= 0 && i < dm.ntau) { i0 = (int)i; w0 = 1.0 - a; st[i0].push_back({r, w0}); }
-    if (i + 1 >= 0 && i + 1 < dm.ntau) { i1 = (int)(i + 1); w1 = a; st[i1].push_back({r, w1}); }
-    s_tap[r] = Tap{i0, i1, (float)w0, (float)w1};
-  }
-  std::vector<int> st_ptr(dm.ntau + 1, 0), st_idx;
-  std::vector<float> st_w;
-  for (int i = 0; i < dm.ntau; ++i) {
-    for (auto& e : st[i]) { st_idx.push_back(e.first); st_w.push_back((float)e.second); }
-    st_ptr[i + 1] = (int)st_idx.size();
+  std::vector<float2> s_w(dm.nts + 4, make_float2(0.f, 0.f));
+  std::vector<int> s_start(dm.ntau + 1, dm.nts);
+  {
+    long next = 0;  // next output index whose start is not yet set
+    for (int r = 0; r < dm.nts; ++r) {
+      const double pos = std::sqrt(r * dts) / prm.dtau;
+      const long i = (long)std::floor(pos);
+      const double a = pos - (double)i;
+      int i0 = 0, i1 = 0;
+      double w0 = 0.0, w1 = 0.0;
+      if (i >= 0 && i < dm.ntau) { i0 = (int)i; w0 = 1.0 - a; }
+      if (i + 1 >= 0 && i + 1 < dm.ntau) { i1 = (int)(i + 1); w1 = a; }
+      s_tap[r] = Tap{i0, i1, (float)w0, (float)w1};
+      s_w[r] = make_float2((float)w0, (float)w1);
+      for (; next <= std::min<long>(i, dm.ntau); ++next) s_start[next] = r;
+    }
   }
   std::vector<Tap> u_tap(dm.nt);
-  std::vector<std::vector<std::pair<int, double>>> ut(dm.nts);
-  for (int s = 0; s < dm.nt; ++s) {
-    const double ts = s * prm.dt;
-    const double pos = ts * ts / dts;
-    const long r = (long)std::floor(pos);
-    const double b = pos - (double)r;
-    int r0 = 0, r1 = 0;
-    double w0 = 0.0, w1 = 0.0;
-    if (r >= 0 && r < dm.nts) { r0 = (int)r; w0 = 1.0 - b; ut[r0].push_back({s, w0}); }
-    if (r + 1 >= 0 && r + 1 < dm.nts) { r1 = (int)(r + 1); w1 = b; ut[r1].push_back({s, w1}); }
-    u_tap[s] = Tap{r0, r1, (float)w0, (float)w1};
-  }
-  std::vector<int> ut_ptr(dm.nts + 1, 0), ut_idx;
-  std::vector<float> ut_w;
-  for (int r = 0; r < dm.nts; ++r) {
-    for (auto& e : ut[r]) { ut_idx.push_back(e.first); ut_w.push_back((float)e.second); }
-    ut_ptr[r + 1] = (int)ut_idx.size();
+  std::vector<float2> u_w(dm.nt + 4, make_float2(0.f, 0.f));
+  std::vector<int> u_start(dm.nts + 1, dm.nt);
+  {
+    long next = 0;
+    for (int t = 0; t < dm.nt; ++t) {
+      const double ts = t * prm.dt;
+      const double pos = ts * ts / dts;
+      const long r = (long)std::floor(pos);
+      const double b = pos - (double)r;
+      int r0 = 0, r1 = 0;
+      double w0 = 0.0, w1 = 0.0;
+      if (r >= 0 && r < dm.nts) { r0 = (int)r; w0 = 1.0 - b; }
+      if (r + 1 >= 0 && r + 1 < dm.nts) { r1 = (int)(r + 1); w1 = b; }
+      u_tap[t] = Tap{r0, r1, (float)w0, (float)w1};
+      u_w[t] = make_float2((float)w0, (float)w1);
+      for (; next <= std::min<long>(r, dm.nts); ++next) u_start[next] = t;
+    }
   }
 
   // ---- twiddles of the row transforms
@@ -548,9 +550,9 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
   // ---- upload
   Tables& tb = P.tb;
   TRY(upload(P, s_tap, &tb.s_tap));
-  TRY(upload(P, st_ptr, &tb.st_ptr)); TRY(upload(P, st_idx, &tb.st_idx)); TRY(upload(P, st_w, &tb.st_w));
+  TRY(upload(P, s_start, &tb.s_start)); TRY(upload(P, s_w, &tb.s_w));
   TRY(upload(P, u_tap, &tb.u_tap));
-  TRY(upload(P, ut_ptr, &tb.ut_ptr)); TRY(upload(P, ut_idx, &tb.ut_idx)); TRY(upload(P, ut_w, &tb.ut_w));
+  TRY(upload(P, u_start, &tb.u_start)); TRY(upload(P, u_w, &tb.u_w));
   TRY(upload(P, tw_half, &tb.tw_half)); TRY(upload(P, tw_real, &tb.tw_real));
   {
     int mg_cap = 0;
