@@ -14,7 +14,6 @@ namespace aahrt {
 constexpr int kMaxPasses = 12;
 constexpr int kBlock = 256;     // threads per workgroup of the row kernels and small kernels
 constexpr int kBlockG = 512;    // threads per workgroup of the GFST (nonuniform FFT) kernels
-constexpr int kStageTraces = 64;  // traces staged in LDS per chunk in the GFST kernels
 constexpr int kPrefetchCells = 4 * 512;  // q-coefficients (nq * ft) a GFST workgroup holds in registers
 
 // x / d = (umulhi(x, m) + x) >> s for 0 <= x < 2^31 (d = 1: x).
@@ -145,19 +144,17 @@ struct Plan {
 // LDS of the GFST kernels in float2 units (q-grid transforms run in place).
 // Interpolation: two slots (one if ntheta = 1; 16-bit grids pack a cell in 4
 // bytes, plus one FP32 transform buffer), the trace stage and the q-grid
-// twiddles.  Spreading: two fixed-point slots, the stage with the data values and
-// the twiddles.
+// twiddles.  Spreading: two fixed-point slots, the trace stage and the twiddles.
 __host__ __device__ inline size_t interp_slots_f2(int ft, int ldr, int ntheta, int gdt) {
   const int nslot = ntheta >= 2 ? 2 : 1;
   const size_t cells = (size_t)nslot * ft * ldr;
   return gdt == AAHRT_GRID_F32 ? cells : (cells + 1) / 2;
 }
 __host__ __device__ inline size_t interp_lds_f2(int ft, int ldr, int ntheta, int mg, int gdt) {
-  return interp_slots_f2(ft, ldr, ntheta, gdt) + (gdt == AAHRT_GRID_F32 ? 0 : (size_t)ft * ldr) +
-         3 * (size_t)kStageTraces + mg;
+  return interp_slots_f2(ft, ldr, ntheta, gdt) + (gdt == AAHRT_GRID_F32 ? 0 : (size_t)ft * ldr) + mg;
 }
 __host__ __device__ inline size_t spread_lds_f2(int ft, int ldr, int mg) {
-  return 2 * (size_t)ft * ldr + (size_t)kStageTraces * (3 + ft) + mg;
+  return 2 * (size_t)ft * ldr + mg;
 }
 
 // ---- kernels (kernels.hip) ----

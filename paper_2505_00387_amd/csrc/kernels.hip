@@ -332,7 +332,9 @@ __global__ __launch_bounds__(kBlock) void k_residual_r2c(float2* __restrict__ dh
 // wraps), then padding to an odd row length (rows of one access fall in
 // distinct LDS banks).  Slices are visited in azimuth order; traces are grouped
 // by their lower azimuth bin j_n, so bin j needs slices j and j+1 (mod ntheta).
-// Per-trace tables of a bin are staged in LDS in chunks of kStageTraces traces.
+// The (trace, frequency) items of a bin run with the frequency fastest across
+// threads; the per-trace tables are read straight from memory (the lanes of one
+// trace share the cache line), so a bin needs no barrier of its own.
 //
 // Phases use 0.64 fixed point: frac(f b) for an integer frequency index f is the
 // wrapped 64-bit product, of which only the top 32 bits are formed
@@ -383,33 +385,6 @@ __device__ __forceinline__ int xcd_tile(int id, int n) {
   const int q = n >> 3, r = n & 7;
   const int x = id & 7, loc = id >> 3;
   return x < r ? x * (q + 1) + loc : r * (q + 1) + (x - r) * q + loc;
-}
-
-struct Stage {
-  unsigned long long* b;
-  unsigned long long* a;
-  float* alpha;
-  int* row;
-  float2* dv;  // spreading only: [kStageTraces][ft]
-};
-
-__device__ __forceinline__ Stage stage_at(float2* base) {
-  Stage st;
-  st.b = reinterpret_cast<unsigned long long*>(base);
-  st.a = st.b + kStageTraces;
-  st.alpha = reinterpret_cast<float*>(st.a + kStageTraces);
-  st.row = reinterpret_cast<int*>(st.alpha + kStageTraces);
-  st.dv = reinterpret_cast<float2*>(st.row + kStageTraces);
-  return st;
-}
-
-__device__ __forceinline__ void stage_tables(const Stage& st, const Tables& tb, int c0, int cnt) {
-  for (int t = threadIdx.x; t < cnt; t += kBlockG) {
-    st.b[t] = tb.tr_b[c0 + t];
-    st.a[t] = tb.tr_a[c0 + t];
-    st.alpha[t] = tb.tr_alpha[c0 + t];
-    st.row[t] = tb.tr_row[c0 + t];
-  }
 }
 
 // q-coefficients of one slice for the tile, c[l][fl] = Mh[b][s][l][f0 + fl], held in
@@ -517,8 +492,7 @@ __global__ __launch_bounds__(kBlockG) void k_nufft_interp(const float2* __restri
   const int slot_sz = ft * ldr;
   Cell* slots = reinterpret_cast<Cell*>(lds);
   float2* work = lds + interp_slots_f2(ft, ldr, dm.ntheta, GD);  // 16-bit grids: FP32 transform buffer
-  const Stage st = stage_at(GD == AAHRT_GRID_F32 ? work : work + slot_sz);
-  float2* twl = reinterpret_cast<float2*>(st.row + kStageTraces);  // q-grid twiddles
+  float2* twl = GD == AAHRT_GRID_F32 ? work : work + slot_sz;  // q-grid twiddles
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int b = tile / dm.nftile;
   const int f0 = (tile - b * dm.nftile) * ft;
@@ -541,34 +515,31 @@ __global__ __launch_bounds__(kBlockG) void k_nufft_interp(const float2* __restri
     if (j >= 0) {
       const Cell* G0 = slots + (nt == 1 ? 0 : (j & 1)) * slot_sz;
       const Cell* G1 = slots + (nt == 1 ? 0 : ((j + 1) & 1)) * slot_sz;
-      for (int c0 = bp[j]; c0 < bp[j + 1]; c0 += kStageTraces) {
-        const int cnt = min(kStageTraces, bp[j + 1] - c0);
-        stage_tables(st, tb, c0, cnt);
-        __syncthreads();
-        for (int it = threadIdx.x; it < cnt * ft; it += kBlockG) {
-          const int ti = it >> ftl;
-          const int fl = it & (ft - 1);
-          const unsigned f = (unsigned)(f0 + fl);
-          if (f >= (unsigned)dm.nf) continue;
-          const KernelPoint kp = kernel_point<W>(f, st.b[ti], dm.mg);
-          const Cell* g0 = G0 + fl * ldr + kp.base;
-          const Cell* g1 = G1 + fl * ldr + kp.base;
-          float2 a0 = make_float2(0.f, 0.f), a1 = make_float2(0.f, 0.f);
+      const int c0 = bp[j];
+      const int cnt = bp[j + 1] - c0;
+      for (int it = threadIdx.x; it < cnt * ft; it += kBlockG) {
+        const int n = c0 + (it >> ftl);
+        const int fl = it & (ft - 1);
+        const unsigned f = (unsigned)(f0 + fl);
+        if (f >= (unsigned)dm.nf) continue;
+        const KernelPoint kp = kernel_point<W>(f, tb.tr_b[n], dm.mg);
+        const Cell* g0 = G0 + fl * ldr + kp.base;
+        const Cell* g1 = G1 + fl * ldr + kp.base;
+        float2 a0 = make_float2(0.f, 0.f), a1 = make_float2(0.f, 0.f);
 #pragma unroll
-          for (int t = 0; t < W; ++t) {
-            const float ph = es_tap(fmaf((float)t, -2.0f / (float)W, kp.z0), dm.cbeta);
-            const float2 v0 = dec_cell<GD>(g0[t]), v1 = dec_cell<GD>(g1[t]);
-            a0.x = fmaf(ph, v0.x, a0.x);
-            a0.y = fmaf(ph, v0.y, a0.y);
-            a1.x = fmaf(ph, v1.x, a1.x);
-            a1.y = fmaf(ph, v1.y, a1.y);
-          }
-          const float alpha = st.alpha[ti];
-          const float2 v = make_float2(fmaf(alpha, a1.x - a0.x, a0.x), fmaf(alpha, a1.y - a0.y, a0.y));
-          dhat[(size_t)st.row[ti] * dm.nf + f] = cmul(v, pre_phase<-1>(f, st.a[ti]));
+        for (int t = 0; t < W; ++t) {
+          const float ph = es_tap(fmaf((float)t, -2.0f / (float)W, kp.z0), dm.cbeta);
+          const float2 v0 = dec_cell<GD>(g0[t]), v1 = dec_cell<GD>(g1[t]);
+          a0.x = fmaf(ph, v0.x, a0.x);
+          a0.y = fmaf(ph, v0.y, a0.y);
+          a1.x = fmaf(ph, v1.x, a1.x);
+          a1.y = fmaf(ph, v1.y, a1.y);
         }
-        __syncthreads();
+        const float alpha = tb.tr_alpha[n];
+        const float2 v = make_float2(fmaf(alpha, a1.x - a0.x, a0.x), fmaf(alpha, a1.y - a0.y, a0.y));
+        dhat[(size_t)tb.tr_row[n] * dm.nf + f] = cmul(v, pre_phase<-1>(f, tb.tr_a[n]));
       }
+      __syncthreads();
     }
     if (build) {
       if (sb >= 2 && nt == 2 && sbm == 0) {
@@ -623,44 +594,35 @@ __global__ __launch_bounds__(kBlock) void k_slice_scales(const float* __restrict
 }
 
 // One azimuth bin into the slots lo (weight 1 - alpha, slice j, scale S_lo) and hi
-// (weight alpha, slice j+1, scale S_hi); a null slot is skipped.
-template <int W>
+// (weight alpha, slice j+1, scale S_hi); HAS_LO / HAS_HI say which slots take part.
+template <int W, bool HAS_LO, bool HAS_HI>
 __device__ __forceinline__ void spread_bin(unsigned long long* lo, unsigned long long* hi, int c_begin, int c_end,
-                           const float2* __restrict__ dhat, const Stage& st, int f0, float S_lo, float S_hi,
-                           const Tables& tb, const Dims& dm, int ftl) {
+                                           const float2* __restrict__ dhat, int f0, float S_lo,
+                                           float S_hi, const Tables& tb, const Dims& dm, int ftl) {
   const int ldr = dm.ldr;
   const int ft = dm.ft;
-  for (int c0 = c_begin; c0 < c_end; c0 += kStageTraces) {
-    const int cnt = min(kStageTraces, c_end - c0);
-    stage_tables(st, tb, c0, cnt);
-    __syncthreads();
-    for (int it = threadIdx.x; it < cnt * ft; it += kBlockG) {
-      const int ti = it >> ftl;
-      const int f = f0 + (it & (ft - 1));
-      st.dv[it] = f < dm.nf ? dhat[(size_t)st.row[ti] * dm.nf + f] : make_float2(0.f, 0.f);
-    }
-    __syncthreads();
-    for (int it = threadIdx.x; it < cnt * ft; it += kBlockG) {
-      const int ti = it >> ftl;
-      const int fl = it & (ft - 1);
-      const unsigned f = (unsigned)(f0 + fl);
-      if (f >= (unsigned)dm.nf) continue;
-      const float2 s = cmul(st.dv[it], pre_phase<1>(f, st.a[ti]));
-      const KernelPoint kp = kernel_point<W>(f, st.b[ti], dm.mg);
-      const float alpha = st.alpha[ti];
-      const float2 s1 = cscale(s, alpha * S_hi);
-      const float2 s0 = cscale(s, (1.0f - alpha) * S_lo);
-      unsigned long long* g0 = lo ? lo + fl * ldr + kp.base : nullptr;
-      unsigned long long* g1 = hi ? hi + fl * ldr + kp.base : nullptr;
+  const int cnt = c_end - c_begin;
+  for (int it = threadIdx.x; it < cnt * ft; it += kBlockG) {
+    const int n = c_begin + (it >> ftl);
+    const int fl = it & (ft - 1);
+    const unsigned f = (unsigned)(f0 + fl);
+    if (f >= (unsigned)dm.nf) continue;
+    const float2 dv = dhat[(size_t)tb.tr_row[n] * dm.nf + f];
+    const float2 s = cmul(dv, pre_phase<1>(f, tb.tr_a[n]));
+    const KernelPoint kp = kernel_point<W>(f, tb.tr_b[n], dm.mg);
+    const float alpha = tb.tr_alpha[n];
+    const float2 s1 = cscale(s, alpha * S_hi);
+    const float2 s0 = cscale(s, (1.0f - alpha) * S_lo);
+    unsigned long long* g0 = HAS_LO ? lo + fl * ldr + kp.base : nullptr;
+    unsigned long long* g1 = HAS_HI ? hi + fl * ldr + kp.base : nullptr;
 #pragma unroll
-      for (int t = 0; t < W; ++t) {
-        const float ph = es_tap(fmaf((float)t, -2.0f / (float)W, kp.z0), dm.cbeta);
-        if (g0) atomicAdd(g0 + t, pack_fix(ph * s0.x, ph * s0.y));
-        if (g1) atomicAdd(g1 + t, pack_fix(ph * s1.x, ph * s1.y));
-      }
+    for (int t = 0; t < W; ++t) {
+      const float ph = es_tap(fmaf((float)t, -2.0f / (float)W, kp.z0), dm.cbeta);
+      if (HAS_LO) atomicAdd(g0 + t, pack_fix(ph * s0.x, ph * s0.y));
+      if (HAS_HI) atomicAdd(g1 + t, pack_fix(ph * s1.x, ph * s1.y));
     }
-    __syncthreads();
   }
+  __syncthreads();
 }
 
 // Fold the ghost cells back, decode the slot in place to FP32, inverse q-grid
@@ -708,8 +670,7 @@ __global__ __launch_bounds__(kBlockG) void k_nufft_spread(const float2* __restri
   const int slot_sz = ft * dm.ldr;
   unsigned long long* slot0 = reinterpret_cast<unsigned long long*>(lds);
   unsigned long long* slot1 = slot0 + slot_sz;
-  const Stage st = stage_at(lds + 2 * slot_sz);
-  float2* twl = lds + 2 * slot_sz + kStageTraces * (3 + ft);  // q-grid twiddles
+  float2* twl = lds + 2 * slot_sz;  // q-grid twiddles
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int b = tile / dm.nftile;
   const int f0 = (tile - b * dm.nftile) * ft;
@@ -730,7 +691,12 @@ __global__ __launch_bounds__(kBlockG) void k_nufft_spread(const float2* __restri
     unsigned long long* lo = step == 0 ? nullptr : (((step - 1) & 1) ? slot1 : slot0);
     unsigned long long* hi = step == last + 1 ? nullptr : ((step & 1) ? slot1 : slot0);
     const float S_hi = step <= last ? slice_scale[(size_t)b * dm.ntheta + step] : 1.0f;
-    spread_bin<W>(lo, hi, bp[bin], bp[bin + 1], dhat, st, f0, S_prev, S_hi, tb, dm, ftl);
+    if (step == 0)
+      spread_bin<W, false, true>(lo, hi, bp[bin], bp[bin + 1], dhat, f0, S_prev, S_hi, tb, dm, ftl);
+    else if (step == last + 1)
+      spread_bin<W, true, false>(lo, hi, bp[bin], bp[bin + 1], dhat, f0, S_prev, S_hi, tb, dm, ftl);
+    else
+      spread_bin<W, true, true>(lo, hi, bp[bin], bp[bin + 1], dhat, f0, S_prev, S_hi, tb, dm, ftl);
     if (step >= 1)
       finish_slot<W>(lo, mb + (size_t)(step - 1) * slice_stride, f0, 1.0f / S_prev, twl, dm, fpg, ftl);
     S_prev = S_hi;
