@@ -387,8 +387,8 @@ __device__ __forceinline__ int xcd_tile(int id, int n) {
   return x < r ? x * (q + 1) + loc : r * (q + 1) + (x - r) * q + loc;
 }
 
-// q-coefficients of one slice for the tile, c[l][fl] = Mh[b][s][l][f0 + fl], held in
-// registers (kCoefRegs per thread) so their loads overlap the preceding work.
+// q-coefficients of one slice for the tile, c[l][fl] = Mh[b][s][l][f0 + fl], kCoefRegs
+// per thread.
 constexpr int kCoefRegs = 4;
 static_assert(kCoefRegs * kBlockG >= kPrefetchCells, "coefficient prefetch capacity");
 
@@ -505,13 +505,13 @@ __global__ __launch_bounds__(kBlockG) void k_nufft_interp(const float2* __restri
 
   // step -2 and -1 build slices 0 and 1; step j >= 0 interpolates bin j, then builds
   // slice (j + 2) mod ntheta into the slot of slice j (while j + 2 <= ntheta).  The
-  // coefficients of the slice built at the end of a step are loaded at its start.
+  // coefficients are loaded just before the build (holding them across the
+  // interpolation costs registers, hence resident waves, for little overlap).
   float2 cr[kCoefRegs];
   for (int j = -2; j < nt; ++j) {
     const int sb = j + 2;
     const bool build = sb < 2 ? sb < nt : sb <= nt;
     const int sbm = sb >= nt ? sb - nt : sb;
-    if (build) load_coefs(cr, mb + (size_t)sbm * slice_stride, f0, dm, ftl);
     if (j >= 0) {
       const Cell* G0 = slots + (nt == 1 ? 0 : (j & 1)) * slot_sz;
       const Cell* G1 = slots + (nt == 1 ? 0 : ((j + 1) & 1)) * slot_sz;
@@ -542,6 +542,7 @@ __global__ __launch_bounds__(kBlockG) void k_nufft_interp(const float2* __restri
       __syncthreads();
     }
     if (build) {
+      load_coefs(cr, mb + (size_t)sbm * slice_stride, f0, dm, ftl);
       if (sb >= 2 && nt == 2 && sbm == 0) {
         // two slices: slice 0 is still in its slot
       } else if constexpr (GD == AAHRT_GRID_F32) {
