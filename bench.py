@@ -43,6 +43,7 @@ def kernel_bytes(plan, name: str) -> float:
         'model_c2r': rows * (8 * nf + 4 * a.ntau),
         'residual_r2c': ntr * (16 * nf + 4 * a.nt),
         'model_c2r_update': rows * (8 * nf + 16 * a.ntau),
+        'model_update_r2c': rows * (16 * nf + 16 * a.ntau),
     }[name]
 
 

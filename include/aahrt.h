@@ -203,7 +203,8 @@ typedef enum {
   AAHRT_K_MODEL_C2R = 5,        /* model rows: inverse real DFT, stretch transpose (L^T) */
   AAHRT_K_RESIDUAL_R2C = 6,     /* solver: residual d - L y fused with the data side of L^T */
   AAHRT_K_MODEL_C2R_UPDATE = 7, /* solver: model side of L^T fused with shrinkage + momentum */
-  AAHRT_K_COUNT = 8
+  AAHRT_K_MODEL_UPDATE_R2C = 8, /* solver: the same, then L steps 1-2 on the new y (next iteration) */
+  AAHRT_K_COUNT = 9
 } aahrt_kernel_id;
 
 /*

@@ -22,7 +22,7 @@ EXPORTED = ['aahrt_version', 'aahrt_last_error', 'aahrt_plan_create', 'aahrt_pla
             'aahrt_operator_norm2', 'aahrt_sparse_solve', 'aahrt_profile_enable', 'aahrt_profile_read']
 
 KERNELS = ['model_r2c', 'nufft_interp', 'data_c2r', 'data_r2c', 'nufft_spread', 'model_c2r',
-           'residual_r2c', 'model_c2r_update']
+           'residual_r2c', 'model_c2r_update', 'model_update_r2c']
 
 
 class Params(ctypes.Structure):

@@ -166,9 +166,9 @@ hipError_t launch_residual_r2c(const Plan& p, float2* dhat, const float* dobs, f
                                hipStream_t s);
 hipError_t launch_nufft_spread(const Plan& p, const float2* dhat, float2* mhat, hipStream_t s);
 hipError_t launch_model_c2r(const Plan& p, const float2* mhat, float* m, hipStream_t s);
-hipError_t launch_model_c2r_update(const Plan& p, const float2* mhat, float* y, float* x,
-                                   const float* gam, const float* lam, float beta, int ista,
-                                   float* l1, hipStream_t s);
+hipError_t launch_model_c2r_update(const Plan& p, float2* mhat, float* y, float* x, const float* gam,
+                                   const float* lam, float beta, int ista, float* l1, bool next,
+                                   hipStream_t s);
 hipError_t launch_fill(float* p, float v, size_t n, hipStream_t s);
 hipError_t launch_copy(float* dst, const float* src, size_t n, hipStream_t s);
 hipError_t launch_seed_vector(float* v, size_t n, unsigned seed, hipStream_t s);

@@ -137,6 +137,26 @@ __device__ __forceinline__ float2* row_fft(float2* A, float2* B, const FftPlan& 
   return fft_lds<INV, kBlock>(A, B, fp, 1, dm.nh, tb.tw_half);
 }
 
+// Stretch S of a staged model row, times sc, packed as z[p] = M'[2p] + i M'[2p+1]
+// (zero beyond nt').
+__device__ __forceinline__ void stretch_pack(float2* A, const float* row, float sc, const Tables& tb,
+                                             const Dims& dm) {
+#pragma unroll 4
+  for (int p = threadIdx.x; p < dm.nh; p += kBlock) {
+    const int r0 = 2 * p, r1 = 2 * p + 1;
+    float a = 0.f, b = 0.f;
+    if (r0 < dm.nts) {
+      const Tap t = tb.s_tap[r0];
+      a = sc * (t.w0 * row[t.i0] + t.w1 * row[t.i1]);
+    }
+    if (r1 < dm.nts) {
+      const Tap t = tb.s_tap[r1];
+      b = sc * (t.w0 * row[t.i0] + t.w1 * row[t.i1]);
+    }
+    A[p] = make_float2(a, b);
+  }
+}
+
 // Steps 1-2 of L: M'(tau') = S M, times the deapodisation of its curvature
 // index, real DFT of length N, bins 0..N/2-1 stored as mhat[row][f].
 template <bool IP>
@@ -152,21 +172,7 @@ __global__ __launch_bounds__(kBlock) void k_model_r2c(const float* __restrict__ 
   const float* src = m + rid * dm.ntau;
   for (int i = threadIdx.x; i < dm.ntau; i += kBlock) row[i] = src[i];
   __syncthreads();
-  const float sc = tb.deapod[l];
-#pragma unroll 4
-  for (int p = threadIdx.x; p < dm.nh; p += kBlock) {
-    const int r0 = 2 * p, r1 = 2 * p + 1;
-    float a = 0.f, b = 0.f;
-    if (r0 < dm.nts) {
-      const Tap t = tb.s_tap[r0];
-      a = sc * (t.w0 * row[t.i0] + t.w1 * row[t.i1]);
-    }
-    if (r1 < dm.nts) {
-      const Tap t = tb.s_tap[r1];
-      b = sc * (t.w0 * row[t.i0] + t.w1 * row[t.i1]);
-    }
-    A[p] = make_float2(a, b);
-  }
+  stretch_pack(A, row, tb.deapod[l], tb, dm);
   __syncthreads();
   const float2* X = row_fft<false, IP>(A, B, fp, tb, dm);
   store_real_spectrum(X, mhat + rid * dm.nf, tb, dm);
@@ -175,7 +181,7 @@ __global__ __launch_bounds__(kBlock) void k_model_r2c(const float* __restrict__ 
 // Transpose of steps 1-2: inverse real DFT (1/N, doubled positive bins), first
 // nt' samples, times the deapodisation, then S^T.
 template <bool IP>
-__device__ __forceinline__ const float* model_c2r_core(const float2* __restrict__ mhat, float2* A,
+__device__ __forceinline__ const float* model_c2r_core(const float2* mhat, float2* A,
                                                        float2* B, const Tables& tb, const Dims& dm,
                                                        const FftPlan& fp, size_t rid) {
   load_packed_c2r(A, mhat + rid * dm.nf, tb, dm);
@@ -200,9 +206,11 @@ __global__ __launch_bounds__(kBlock) void k_model_c2r(const float2* __restrict__
 
 // Same transpose, fused with one forward-backward step on the row:
 //   x_new = soft(y + gamma g, gamma lambda); y <- x_new + beta (x_new - x_old); x <- x_new
-// (ISTA: y <- x_new).  l1[row] receives sum |x_new| when l1 is not null.
-template <bool IP>
-__global__ __launch_bounds__(kBlock) void k_model_c2r_update(const float2* __restrict__ mhat,
+// (ISTA: y <- x_new).  l1[row] receives sum |x_new| when l1 is not null.  NEXT: the
+// row then goes on through steps 1-2 of L for the next iteration, S y_new -> R2C,
+// written over its own spectrum row (each row is read and written by one block).
+template <bool IP, bool NEXT>
+__global__ __launch_bounds__(kBlock) void k_model_c2r_update(float2* __restrict__ mhat,
                                                              float* __restrict__ y,
                                                              float* __restrict__ x, Tables tb,
                                                              Dims dm, FftPlan fp,
@@ -215,7 +223,12 @@ __global__ __launch_bounds__(kBlock) void k_model_c2r_update(const float2* __res
   const size_t rid = blockIdx.x;
   const int l = (int)(rid % dm.nq);
   const int b = (int)(rid / ((size_t)dm.nq * dm.ntheta));
-  const float* xs = model_c2r_core<IP>(mhat, lds, lds + dm.nhp, tb, dm, fp, rid);
+  float2* A = lds;
+  float2* B = lds + dm.nhp;
+  const float* xs = model_c2r_core<IP>(mhat, A, B, tb, dm, fp, rid);
+  // the new y row is staged after A (in place) or in the buffer not holding xs
+  float* stage = IP ? reinterpret_cast<float*>(B)
+                    : reinterpret_cast<float*>(xs == reinterpret_cast<const float*>(A) ? B : A);
   const float sc = tb.deapod[l] / (float)dm.nfft;
   const float g = gam[b];
   const float thr = g * lam[b];
@@ -227,13 +240,24 @@ __global__ __launch_bounds__(kBlock) void k_model_c2r_update(const float2* __res
     const float a = fabsf(v) - thr;
     const float xn = a > 0.f ? copysignf(a, v) : 0.f;
     const float xo = xr[i];
-    yr[i] = ista ? xn : xn + beta * (xn - xo);
+    const float yn = ista ? xn : xn + beta * (xn - xo);
+    yr[i] = yn;
     xr[i] = xn;
+    if (NEXT) stage[i] = yn;
     s1 += fabsf(xn);
   }
   if (l1) {
     const float t = block_sum<kBlock>(s1, red);
     if (threadIdx.x == 0) l1[rid] = t;
+  }
+  if (NEXT) {
+    __syncthreads();  // S^T reads of xs done, new row staged
+    float2* in = IP ? A : (stage == reinterpret_cast<float*>(A) ? B : A);
+    float2* other = IP ? B : reinterpret_cast<float2*>(stage);
+    stretch_pack(in, stage, tb.deapod[l], tb, dm);
+    __syncthreads();
+    const float2* X = row_fft<false, IP>(in, other, fp, tb, dm);
+    store_real_spectrum(X, mhat + rid * dm.nf, tb, dm);
   }
 }
 
@@ -847,12 +871,15 @@ hipError_t launch_model_c2r(const Plan& p, const float2* mhat, float* m, hipStre
                     p.fft_half);
 }
 
-hipError_t launch_model_c2r_update(const Plan& p, const float2* mhat, float* y, float* x,
-                                   const float* gam, const float* lam, float beta, int ista,
-                                   float* l1, hipStream_t s) {
+hipError_t launch_model_c2r_update(const Plan& p, float2* mhat, float* y, float* x, const float* gam,
+                                   const float* lam, float beta, int ista, float* l1, bool next,
+                                   hipStream_t s) {
   const Dims& dm = p.dm;
-  return launch_row(k_model_c2r_update<true>, k_model_c2r_update<false>, dm, 0, model_rows(dm), s, mhat, y,
-                    x, p.tb, dm, p.fft_half, gam, lam, beta, ista, l1);
+  if (next)
+    return launch_row(k_model_c2r_update<true, true>, k_model_c2r_update<false, true>, dm, dm.ntau,
+                      model_rows(dm), s, mhat, y, x, p.tb, dm, p.fft_half, gam, lam, beta, ista, l1);
+  return launch_row(k_model_c2r_update<true, false>, k_model_c2r_update<false, false>, dm, 0, model_rows(dm), s,
+                    mhat, y, x, p.tb, dm, p.fft_half, gam, lam, beta, ista, l1);
 }
 
 hipError_t launch_data_c2r(const Plan& p, const float2* dhat, float* d, hipStream_t s) {

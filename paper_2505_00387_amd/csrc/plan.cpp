@@ -695,14 +695,17 @@ std::vector<double> fista_betas(int n, bool ista) {
 int enqueue_iterations(Plan& P, const float* d, float* m, int n_iter, bool ista, float* objective,
                        hipStream_t s) {
   const std::vector<double> betas = fista_betas(n_iter, ista);
+  // the forward spectra of y come from model_r2c for the first iteration and from the
+  // fused update kernel of the previous iteration afterwards
+  if (n_iter > 0) KCALL(AAHRT_K_MODEL_R2C, launch_model_r2c(P, P.ybuf, P.mhat, s));
   for (int k = 0; k < n_iter; ++k) {
-    KCALL(AAHRT_K_MODEL_R2C, launch_model_r2c(P, P.ybuf, P.mhat, s));
+    const bool next = k + 1 < n_iter;
     KCALL(AAHRT_K_NUFFT_INTERP, launch_nufft_interp(P, P.mhat, P.dhat, s));
     KCALL(AAHRT_K_RESIDUAL_R2C, launch_residual_r2c(P, P.dhat, d, objective ? P.rss : nullptr, s));
     KCALL(AAHRT_K_NUFFT_SPREAD, launch_nufft_spread(P, P.dhat, P.mhat, s));
-    KCALL(AAHRT_K_MODEL_C2R_UPDATE,
+    KCALL(next ? AAHRT_K_MODEL_UPDATE_R2C : AAHRT_K_MODEL_C2R_UPDATE,
           launch_model_c2r_update(P, P.mhat, P.ybuf, m, P.gam, P.lam, (float)betas[k], ista ? 1 : 0,
-                                  objective ? P.l1row : nullptr, s));
+                                  objective ? P.l1row : nullptr, next, s));
     if (objective)
       HIP_TRY(launch_objective(P, P.rss, P.trace_ptr_dev, P.l1row, P.lam,
                                objective + (size_t)k * P.dm.batch, s));
