@@ -78,7 +78,7 @@ typedef struct aahrt_params {
                             >= nt' + ceil(max(q_max,0) h2max/dt') + ceil(max(-q_min,0) h2max/dt');
                             otherwise it must be even, 2^a3^b5^c and >= nt' */
   double nufft_tol;      /* target relative error of the q nonuniform FFT; 0 -> 1e-6 */
-  double sigma;          /* q-grid oversampling in [1.25, 4]; 0 -> autotune between 2 and 1.5 */
+  double sigma;          /* q-grid oversampling in [1.25, 4]; 0 -> autotune among 2, 1.5 and 1.25 */
   int32_t kernel_width;  /* spreading kernel width w (3..12); 0 -> chosen from nufft_tol and sigma */
   int32_t freq_tile;     /* frequencies per work item of the GFST stage (power of 2, 1..64); 0 -> autotune */
   int32_t grid_dtype;    /* aahrt_grid_dtype */
@@ -123,7 +123,7 @@ const char* aahrt_last_error(void);
  * Computes the FP64 tables (stretch taps, azimuth weights, 64-bit fixed-point
  * phase increments, kernel deapodisation), allocates the device tables and the
  * workspace (hipMalloc).  When sigma or freq_tile is 0 it then autotunes the
- * GFST stage: every admissible (sigma in {2, 1.5}, freq_tile in {4, 8, 16, 32})
+ * GFST stage: every admissible (sigma in {2, 1.5, 1.25}, freq_tile in {4, 8, 16, 32})
  * setting, with the kernel width that meets nufft_tol at that sigma, is timed
  * on the interpolation and on the spreading launch over the batch (on zeroed
  * spectra, in a stream of its own, synchronously); each kernel keeps its fastest

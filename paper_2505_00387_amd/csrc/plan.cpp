@@ -258,7 +258,7 @@ int nufft_candidates(const aahrt_params& prm, const Dims& dm, std::vector<NufftC
   if (dm.nq > kPrefetchCells) return fail(AAHRT_E_UNSUPPORTED, "nq too large for the q-coefficient prefetch");
   std::vector<double> sig;
   if (prm.sigma != 0.0) sig.push_back(prm.sigma);
-  else sig = {2.0, 1.5};
+  else sig = {2.0, 1.5, 1.25};
   std::vector<int> fts;
   if (prm.freq_tile != 0) fts.push_back(prm.freq_tile);
   else fts = {16, 8, 32, 4};

@@ -250,9 +250,10 @@ def test_autotuner_times_the_candidates():
     info = plan.info
     print('autotuned', {k: info[k] for k in ('sigma', 'kernel_width', 'freq_tile', 'autotune_candidates',
                                              'autotune_seconds')})
-    assert info['autotune_candidates'] >= 6          # two oversamplings x several tiles
-    assert info['sigma'] in (2.0, 1.5) and info['freq_tile'] in (4, 8, 16, 32)
-    assert info['kernel_width'] == (7 if info['sigma'] == 2.0 else 9)
+    assert info['autotune_candidates'] >= 6          # three oversamplings x several tiles
+    widths = {2.0: 7, 1.5: 9, 1.25: 10}               # tolerance 1e-6
+    assert info['sigma'] in widths and info['kernel_width'] == widths[info['sigma']]
+    assert info['freq_tile'] in (4, 8, 16, 32) and info['freq_tile_adjoint'] in (4, 8, 16, 32)
     plan.close()
 
 
