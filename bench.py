@@ -55,8 +55,9 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel: str, workload: str):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if taken on this kernel source."""
+def load_traffic(kernel: str, workload: str, gfst: dict):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if taken on this kernel source
+    (and, for the GFST kernels, on the same autotuned grid setting)."""
     path = os.path.join(ROOT, 'profiles', 'hbm_counters.json')
     if not os.path.exists(path):
         return None
@@ -66,6 +67,10 @@ def load_traffic(kernel: str, workload: str):
         return None
     if rec.get('source_hash') != source_hash() or rec.get('workload') != workload:
         return None
+    if kernel.startswith('nufft_'):
+        cfg = rec.get('gfst_config', {})
+        if any(cfg.get(k) != gfst.get(k) for k in ('grid', 'kernel_width', 'freq_tile', 'freq_tile_adjoint')):
+            return None
     k = rec.get('kernels', {}).get(kernel)
     return None if k is None else k.get('bytes_per_launch')
 
@@ -314,7 +319,9 @@ def main():
     dom = max(kernels, key=lambda k: kernels[k]['total_ms'])
     avg = kernels[dom]['avg_ms']
     ach = kernel_bytes(plan, dom) / (avg * 1e-3) / 1e9
-    traffic = load_traffic(dom, w.name)
+    gfst = {'grid': plan.info['grid_size'], 'kernel_width': plan.info['kernel_width'],
+            'freq_tile': plan.info['freq_tile'], 'freq_tile_adjoint': plan.info['freq_tile_adjoint']}
+    traffic = load_traffic(dom, w.name, gfst)
     roofline = {'bound': 'hbm', 'achieved': round(ach, 1), 'peak': HBM_PEAK_GBS, 'unit': 'GB/s',
                 'frac': round(ach / HBM_PEAK_GBS, 4), 'traffic': traffic, 'kernel': dom,
                 'alg_bytes_per_launch': int(kernel_bytes(plan, dom)), 'avg_ms': avg}
