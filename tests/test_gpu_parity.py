@@ -318,6 +318,31 @@ def test_fista_parity_config1_20_iterations():
     assert errs[0] < TOL
 
 
+def test_fista_parity_config4_smallest_fold():
+    """FISTA on the smallest-fold gather of the 256-gather workload (200 traces, nt = 1024, N = 4320
+    from the whole batch's offsets), 5 iterations with the oracle's lambda and step: the most the
+    FP64 oracle can run in a test (about a second per operator application)."""
+    w4 = wl.config4(with_data=True)
+    folds = np.diff(w4.trace_ptr)
+    b = int(np.argmin(folds))
+    g = geoms(w4)[b]
+    w = wl.Workload('cmp_batch256_uneven_nt1024_min_fold', w4.axes, [w4.gathers[b]], 5, 'one gather')
+    d = w4.gathers[b].data
+    L = lambda v: gfst.forward(v, g)
+    Lt = lambda v: gfst.adjoint(v, g)
+    rng = np.random.default_rng(4)
+    n2 = fista.power_norm2(L, Lt, rng.standard_normal((g.ntheta, g.nq, g.ntau)), 6)
+    lam, gam = fista.lambda_rule(Lt, d), fista.step_from_norm2(n2)
+    plan = make_plan(w, nfft=g.nfft)
+    x, _ = plan.sparse_solve(to_dev(d), 5, lam=to_dev(np.array([lam])), step=to_dev(np.array([gam])))
+    ref = fista.solve(L, Lt, d, lam, gam, 5)
+    err = rel(to_host(x)[0], ref)
+    print(f'fista smallest fold ({folds[b]} traces): {err:.2e}, support {np.count_nonzero(ref)}')
+    assert np.count_nonzero(ref) > 0
+    assert err < TOL
+    plan.close()
+
+
 def test_ista_parity_config1():
     errs, _ = _fista_parity(wl.config1(), 8, ista=True)
     assert errs[0] < TOL
