@@ -48,10 +48,15 @@ def kernel_bytes(plan, name: str) -> float:
 
 
 def source_hash() -> str:
+    """Hash of the kernel sources with comments and blank space removed (comment edits keep it)."""
+    import re
     h = hashlib.sha256()
     for f in ('kernels.hip', 'fft_lds.hpp', 'aahrt_internal.hpp'):
-        with open(os.path.join(ROOT, 'paper_2505_00387_amd', 'csrc', f), 'rb') as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, 'paper_2505_00387_amd', 'csrc', f)) as fh:
+            text = fh.read()
+        text = re.sub(r'/\*.*?\*/', '', text, flags=re.S)
+        text = re.sub(r'//[^\n]*', '', text)
+        h.update(''.join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

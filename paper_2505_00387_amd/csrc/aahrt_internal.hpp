@@ -143,8 +143,8 @@ struct Plan {
 
 // LDS of the GFST kernels in float2 units (q-grid transforms run in place).
 // Interpolation: two slots (one if ntheta = 1; 16-bit grids pack a cell in 4
-// bytes, plus one FP32 transform buffer), the trace stage and the q-grid
-// twiddles.  Spreading: two fixed-point slots, the trace stage and the twiddles.
+// bytes, plus one FP32 transform buffer) and the q-grid twiddles.  Spreading:
+// two fixed-point slots and the twiddles.
 __host__ __device__ inline size_t interp_slots_f2(int ft, int ldr, int ntheta, int gdt) {
   const int nslot = ntheta >= 2 ? 2 : 1;
   const size_t cells = (size_t)nslot * ft * ldr;

@@ -7,7 +7,9 @@
 //   k_data_c2r      traces: inverse real DFT, unstretch S^-1                   (steps 4-5)
 // L^T runs the transposes in reverse order (k_data_r2c, k_nufft_spread,
 // k_model_c2r).  The solver fuses the residual into the data-side kernels and
-// the soft-threshold/momentum update into the model-side inverse DFT.
+// the soft-threshold/momentum update into the model-side inverse DFT, which then
+// carries the new y through steps 1-2 for the next iteration: an iteration is
+// k_nufft_interp, k_residual_r2c, k_nufft_spread, k_model_c2r_update.
 #include <hip/hip_runtime.h>
 
 #include "aahrt_internal.hpp"
