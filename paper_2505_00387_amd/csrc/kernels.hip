@@ -113,14 +113,13 @@ __device__ __forceinline__ float lerp_transpose(int i, const int* __restrict__ s
   return acc;
 }
 
-// Pack x[r] = (U^T g)[r] (r < nts, zero beyond) as z[p] = x[2p] + i x[2p+1].
+// Pack x[r] = (U^T g)[r] (r < nts, zero beyond) as z[p] = x[2p] + i x[2p+1], i.e. x
+// written in order over the floats of buf.  One output per thread and pass: the
+// first outputs gather the most inputs (t' = t^2 is flat near t = 0).
 __device__ __forceinline__ void pack_transpose(float2* buf, const float* g, const Tables& tb, int nts, int nh) {
-  for (int p = threadIdx.x; p < nh; p += kBlock) {
-    const int r0 = 2 * p, r1 = 2 * p + 1;
-    const float v0 = r0 < nts ? lerp_transpose(r0, tb.u_start, tb.u_w, g) : 0.f;
-    const float v1 = r1 < nts ? lerp_transpose(r1, tb.u_start, tb.u_w, g) : 0.f;
-    buf[p] = make_float2(v0, v1);
-  }
+  float* xf = reinterpret_cast<float*>(buf);
+  for (int r = threadIdx.x; r < 2 * nh; r += kBlock)
+    xf[r] = r < nts ? lerp_transpose(r, tb.u_start, tb.u_w, g) : 0.f;
 }
 
 // ------------------------------------------------------------------ model side
