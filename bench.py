@@ -302,6 +302,17 @@ def main():
     torch.cuda.synchronize()
     t_pair = (time.perf_counter() - t0) / args.pairs
     pairs_per_s = w.batch / t_pair
+
+    # the same solve as a captured hipGraph (the library's default): capture, then one timed replay
+    m.zero_()
+    plan.sparse_solve(d, n_iter, m=m, step=gam, graph=True)
+    torch.cuda.synchronize()
+    m.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.sparse_solve(d, n_iter, m=m, step=gam, graph=True)
+    torch.cuda.synchronize()
+    t_graph = time.perf_counter() - t0
     a = w.axes
     nf = plan.info['nfreq']
     rows = w.batch * a.ntheta * a.nq
@@ -350,7 +361,8 @@ def main():
                    'freq_tile_adjoint': plan.info['freq_tile_adjoint']},
         'roofline': roofline,
         'cpu_baseline': cpu,
-        'secondary': {'fwd_adj_pairs_per_s': round(pairs_per_s, 1), 'fwd_adj_pair_ms': round(1e3 * t_pair, 3),
+        'secondary': {'graph_solve_ms': round(1e3 * t_graph, 2), 'graph_gathers_per_s': round(w.batch / t_graph, 2),
+                      'fwd_adj_pairs_per_s': round(pairs_per_s, 1), 'fwd_adj_pair_ms': round(1e3 * t_pair, 3),
                       'fwd_adj_alg_GBs': round(pair_gbs, 1), 'setup_plan_s': round(t_plan, 3),
                       'setup_autotune_s': round(plan.info['autotune_seconds'], 3),
                       'autotune_candidates': plan.info['autotune_candidates'],
