@@ -24,6 +24,8 @@ Parts
 * ``fista`` -- oracle-3: forward-backward splitting of Section 4 (soft
   shrinkage), with FISTA momentum, the step from a power iteration, and the
   lambda rule lambda = 0.05 max|L^T d|.
+* ``velocity`` -- the automatic anisotropic velocity estimate of Section 3
+  (curvature-weighted mean of the Radon cube per intercept and azimuth).
 
 Pins: every function here is pinned by ``tests/test_oracle_pins.py`` against
 closed forms, invariants, brute force and special cases.  The difference
@@ -32,7 +34,7 @@ operator) is reported only: parity unpinned for that comparison, as the paper
 shows it only as a figure.
 """
 from .geometry import Geometry, nfft_rule, theta_weights, stretch_matrix, unstretch_matrix
-from . import gfst, timedomain, fista
+from . import gfst, timedomain, fista, velocity
 
 __all__ = ['Geometry', 'nfft_rule', 'theta_weights', 'stretch_matrix', 'unstretch_matrix',
-           'gfst', 'timedomain', 'fista']
+           'gfst', 'timedomain', 'fista', 'velocity']

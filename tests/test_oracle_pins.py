@@ -413,3 +413,37 @@ def test_fista_on_gfst_kkt_decreases():
     k10 = fista.kkt_residual(L, Lt, d, fista.solve(L, Lt, d, lam, gam, 10), lam)
     k300 = fista.kkt_residual(L, Lt, d, fista.solve(L, Lt, d, lam, gam, 300), lam)
     assert k300 < 0.2 * k10
+
+
+# ------------------------------------------------------------------ velocity estimate (Section 3)
+def test_velocity_single_spike_gives_its_curvature():
+    from oracle import velocity
+    q = np.linspace(0.04, 0.49, 10)
+    m = np.zeros((3, 10, 5))
+    m[1, 7, 2] = -2.5                          # sign does not matter (weights |M|)
+    qbar, v = velocity.velocity(m, q)
+    assert qbar[1, 2] == q[7] and abs(v[1, 2] - q[7] ** -0.5) < 1e-15
+    assert np.all(qbar[0] == 0) and np.all(v[0] == 0)   # no energy -> 0
+
+
+def test_velocity_two_spikes_weighted_mean_and_scale_invariance():
+    from oracle import velocity
+    q = np.array([0.1, 0.2, 0.3, 0.4])
+    m = np.zeros((4, 1))
+    m[0, 0], m[3, 0] = 1.0, 3.0
+    qbar = velocity.curvature_mean(m, q)
+    assert abs(qbar[0] - (0.1 * 1 + 0.4 * 3) / 4) < 1e-15
+    assert abs(velocity.curvature_mean(7.0 * m, q)[0] - qbar[0]) < 1e-15
+
+
+def test_velocity_of_isotropic_event_cube_recovers_slowness():
+    """A cube whose energy sits symmetrically about q0 (a line smeared over neighbouring q
+    samples) gives v^-2 = q0 exactly."""
+    from oracle import velocity
+    q = 0.04 + 0.01 * np.arange(21)
+    m = np.zeros((21, 3))
+    for k, a in zip((-2, -1, 0, 1, 2), (0.1, 0.5, 1.0, 0.5, 0.1)):
+        m[10 + k, :] = a
+    qbar, v = velocity.velocity(m, q)
+    assert np.allclose(qbar, q[10], rtol=0, atol=1e-15)
+    assert np.allclose(v, q[10] ** -0.5, rtol=1e-14)
