@@ -303,6 +303,16 @@ def main():
     t_pair = (time.perf_counter() - t0) / args.pairs
     pairs_per_s = w.batch / t_pair
 
+    # velocity estimate of the solved cube (Section 3): one read of the model, two small outputs
+    plan.velocity(m)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        plan.velocity(m)
+    torch.cuda.synchronize()
+    t_vel = (time.perf_counter() - t0) / 5
+    vel_bytes = 4 * w.batch * w.axes.ntheta * w.axes.ntau * (w.axes.nq + 2)
+
     # the same solve as a captured hipGraph (the library's default): capture, then one timed replay
     m.zero_()
     plan.sparse_solve(d, n_iter, m=m, step=gam, graph=True)
@@ -362,6 +372,8 @@ def main():
         'roofline': roofline,
         'cpu_baseline': cpu,
         'secondary': {'graph_solve_ms': round(1e3 * t_graph, 2), 'graph_gathers_per_s': round(w.batch / t_graph, 2),
+                      'velocity_estimate_ms': round(1e3 * t_vel, 3),
+                      'velocity_estimate_GBs': round(vel_bytes / t_vel / 1e9, 1),
                       'fwd_adj_pairs_per_s': round(pairs_per_s, 1), 'fwd_adj_pair_ms': round(1e3 * t_pair, 3),
                       'fwd_adj_alg_GBs': round(pair_gbs, 1), 'setup_plan_s': round(t_plan, 3),
                       'setup_autotune_s': round(plan.info['autotune_seconds'], 3),

@@ -193,6 +193,19 @@ int aahrt_sparse_solve(aahrt_plan* plan, const float* d, float* m, const float* 
                        const float* step, int32_t n_iter, int32_t flags, float* objective,
                        aahrt_stream stream);
 
+/*
+ * Automatic anisotropic velocity estimate of a Radon cube (Section 3, "Automatic
+ * Anisotropic Velocity Peaking"): for every gather b, azimuth theta_j and intercept
+ * tau_i, the curvature-weighted mean
+ *   qbar = v^-2 = sum_l q_l |m[b][j][l][i]| / sum_l |m[b][j][l][i]|
+ * (weights |m|, as a sparse-inversion cube is signed; 0 where the cube holds no energy)
+ * and the velocity v = qbar^(-1/2) [km/s] (0 where qbar <= 0).
+ *   m    : device float[batch][ntheta][nq][ntau] (read)
+ *   qbar : device float[batch][ntheta][ntau] (written) [s^2/km^2]
+ *   vel  : device float[batch][ntheta][ntau] (written) [km/s]
+ */
+int aahrt_velocity(aahrt_plan* plan, const float* m, float* qbar, float* vel, aahrt_stream stream);
+
 /* Kernels of the library, for per-kernel timing. */
 typedef enum {
   AAHRT_K_MODEL_R2C = 0,        /* model rows: stretch S, deapodise, real DFT along tau' (L steps 1-2) */

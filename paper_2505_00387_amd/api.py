@@ -58,6 +58,7 @@ class Plan:
         self.batch = int(tp.size - 1)
         self.trace_ptr = tp
         self.device = device
+        self._params = p
         h = ctypes.c_void_p()
         check(lib.aahrt_plan_create(ctypes.byref(h), ctypes.byref(p), self.batch,
                                     tp.ctypes.data, xs.ctypes.data, ys.ctypes.data, device))
@@ -124,6 +125,30 @@ class Plan:
         out = torch.empty(self.batch, dtype=torch.float32, device=d.device)
         check(self._lib.aahrt_lambda_max(self._h, d.data_ptr(), out.data_ptr(), _stream(stream)))
         return out
+
+    def velocity(self, m, stream=None):
+        """Automatic anisotropic velocity estimate (aahrt_velocity): returns (qbar, v), each
+        [batch, ntheta, ntau]; qbar = v^-2 in s^2/km^2, v in km/s."""
+        import torch
+        self._check(m, self.model_shape, 'm')
+        a = self.axes
+        qbar = torch.empty((self.batch, a.ntheta, a.ntau), dtype=torch.float32, device=m.device)
+        v = torch.empty_like(qbar)
+        check(self._lib.aahrt_velocity(self._h, m.data_ptr(), qbar.data_ptr(), v.data_ptr(), _stream(stream)))
+        return qbar, v
+
+    def reconstruct(self, m, x_km, y_km, stream=None):
+        """Data of the model m on another trace geometry (one gather per model gather):
+        L applied through a plan on the new offsets (x_km, y_km lists of per-gather arrays)."""
+        import numpy as np
+        tp = np.concatenate([[0], np.cumsum([len(x) for x in x_km])]).astype(np.int64)
+        other = Plan(self.axes, tp, np.concatenate(x_km), np.concatenate(y_km), nfft=0,
+                     nufft_tol=self._params.nufft_tol, sigma=self.info['sigma'],
+                     kernel_width=self._params.kernel_width, device=self.device)
+        try:
+            return other.forward(m, stream=stream)
+        finally:
+            other.close()
 
     def operator_norm2(self, n_iter=30, stream=None):
         import torch

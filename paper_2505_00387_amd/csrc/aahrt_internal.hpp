@@ -169,6 +169,7 @@ hipError_t launch_model_c2r(const Plan& p, const float2* mhat, float* m, hipStre
 hipError_t launch_model_c2r_update(const Plan& p, float2* mhat, float* y, float* x, const float* gam,
                                    const float* lam, float beta, int ista, float* l1, bool next,
                                    hipStream_t s);
+hipError_t launch_velocity(const Plan& p, const float* m, float* qbar, float* vel, hipStream_t s);
 hipError_t launch_fill(float* p, float v, size_t n, hipStream_t s);
 hipError_t launch_copy(float* dst, const float* src, size_t n, hipStream_t s);
 hipError_t launch_seed_vector(float* v, size_t n, unsigned seed, hipStream_t s);

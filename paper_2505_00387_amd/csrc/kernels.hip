@@ -818,6 +818,28 @@ __global__ void k_objective(const float* __restrict__ rss, const int64_t* __rest
   out[b] = 0.5f * r + lam[b] * s;
 }
 
+// Automatic anisotropic velocity estimate (Section 3): for every gather b, azimuth j
+// and intercept i, qbar = sum_l q_l |m| / sum_l |m| over the curvature samples
+// (0 where the cube holds no energy) and v = qbar^(-1/2) (0 where qbar <= 0).  One
+// thread per intercept; the curvature loop reads rows of the model, coalesced in tau.
+__global__ __launch_bounds__(kBlock) void k_velocity(const float* __restrict__ m, float* __restrict__ qbar,
+                                                     float* __restrict__ vel, int nq, int ntau, float q_min,
+                                                     float dq) {
+  const size_t bj = blockIdx.y;
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= ntau) return;
+  const float* src = m + bj * (size_t)nq * ntau + i;
+  float num = 0.f, den = 0.f;
+  for (int l = 0; l < nq; ++l) {
+    const float a = fabsf(src[(size_t)l * ntau]);
+    den += a;
+    num = fmaf(fmaf((float)l, dq, q_min), a, num);
+  }
+  const float qb = den > 0.f ? num / den : 0.f;
+  qbar[bj * ntau + i] = qb;
+  vel[bj * ntau + i] = qb > 0.f ? 1.0f / sqrtf(qb) : 0.f;
+}
+
 // ------------------------------------------------------------------ launchers
 
 static size_t interp_lds_bytes(const Dims& dm) {
@@ -1021,6 +1043,15 @@ hipError_t launch_objective(const Plan& p, const float* rss, const int64_t* trac
                             const float* l1, const float* lam, float* out, hipStream_t s) {
   hipLaunchKernelGGL(k_objective, dim3((p.dm.batch + 63) / 64), dim3(64), 0, s, rss, trace_ptr_dev, l1,
                      p.dm.ntheta * p.dm.nq, lam, p.dm.batch, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_velocity(const Plan& p, const float* m, float* qbar, float* vel, hipStream_t s) {
+  const Dims& dm = p.dm;
+  const double dq = (p.prm.q_max - p.prm.q_min) / (dm.nq - 1);
+  const dim3 grid((unsigned)((dm.ntau + kBlock - 1) / kBlock), (unsigned)(dm.batch * dm.ntheta));
+  hipLaunchKernelGGL(k_velocity, grid, dim3(kBlock), 0, s, m, qbar, vel, dm.nq, dm.ntau, (float)p.prm.q_min,
+                     (float)dq);
   return hipGetLastError();
 }
 

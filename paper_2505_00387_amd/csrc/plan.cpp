@@ -812,6 +812,15 @@ int aahrt_lambda_max(aahrt_plan* plan, const float* d, float* lmax, aahrt_stream
   return do_lambda_max(P, d, lmax, as_stream(stream));
 }
 
+int aahrt_velocity(aahrt_plan* plan, const float* m, float* qbar, float* vel, aahrt_stream stream) {
+  TRY(check_plan(plan));
+  Plan& P = P_of(plan);
+  if (!m || !qbar || !vel) return fail(AAHRT_E_INVALID, "m, qbar and vel must not be NULL");
+  HIP_TRY(hipSetDevice(P.device));
+  HIP_TRY(launch_velocity(P, m, qbar, vel, as_stream(stream)));
+  return AAHRT_OK;
+}
+
 int aahrt_operator_norm2(aahrt_plan* plan, int32_t n_iter, float* norm2, aahrt_stream stream) {
   TRY(check_plan(plan));
   Plan& P = P_of(plan);

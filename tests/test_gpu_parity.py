@@ -400,3 +400,57 @@ def test_graph_replay_equals_eager():
         assert torch.equal(m, ref), rep
         _ = plan.forward(m)  # eager work between replays
     plan.close()
+
+
+# ------------------------------------------------------------------ velocity estimate, reconstruction
+def _velocity_parity(w, seed, zero_cols=0):
+    from oracle import velocity
+    plan = make_plan(w)
+    m = wl.random_model(w.axes, w.batch, seed)
+    if zero_cols:
+        m[..., :zero_cols] = 0.0                    # intercepts with no energy
+    q = w.axes.q_min + w.axes.dq * np.arange(w.axes.nq)
+    ref_q, ref_v = velocity.velocity(m.astype(np.float32).astype(np.float64), q)
+    got_q, got_v = plan.velocity(to_dev(m))
+    got_q, got_v = to_host(got_q), to_host(got_v)
+    plan.close()
+    return ref_q, ref_v, got_q, got_v
+
+
+def test_velocity_estimate_parity_batch():
+    ref_q, ref_v, got_q, got_v = _velocity_parity(wl.config3(with_data=False), 31, zero_cols=5)
+    assert np.all(got_q[..., :5] == 0) and np.all(got_v[..., :5] == 0)
+    eq = np.max(np.abs(got_q - ref_q) / np.maximum(ref_q, 1e-30) * (ref_q > 0))
+    ev = np.max(np.abs(got_v - ref_v) / np.maximum(ref_v, 1e-30) * (ref_v > 0))
+    print(f'velocity estimate: max rel err qbar {eq:.2e}, v {ev:.2e}')
+    assert eq < 1e-5 and ev < 1e-5
+
+
+def test_velocity_estimate_parity_full_size():
+    ref_q, ref_v, got_q, got_v = _velocity_parity(wl.config4(with_data=False), 32)
+    eq = np.max(np.abs(got_q - ref_q) / ref_q)
+    print(f'velocity estimate, 256 gathers: max rel err qbar {eq:.2e}')
+    assert eq < 1e-5
+
+
+def test_reconstruction_on_a_new_geometry():
+    """Data of a model on another trace geometry (a regular 12x12 offset grid per gather) is L
+    on that geometry: compared with the oracle's L there."""
+    from oracle.geometry import Geometry
+    w = wl.config3(with_data=False)
+    plan = make_plan(w)
+    m = wl.random_model(w.axes, w.batch, 33)
+    g1 = np.linspace(-1.0, 1.0, 12)
+    X, Y = np.meshgrid(g1, g1, indexing='ij')
+    xs = [X.ravel() * (1.0 - 0.05 * b) for b in range(w.batch)]
+    ys = [Y.ravel() * (1.0 - 0.05 * b) for b in range(w.batch)]
+    got = to_host(plan.reconstruct(to_dev(m), xs, ys))
+    h2max = max(float(np.max(x * x + y * y)) for x, y in zip(xs, ys))
+    off = 0
+    for b in range(w.batch):
+        g = Geometry.build(w.axes, xs[b], ys[b], h2max=h2max)
+        ref = gfst.forward(m[b], g)
+        e = rel(got[off:off + xs[b].size], ref)
+        off += xs[b].size
+        assert e < TOL, (b, e)
+    plan.close()
