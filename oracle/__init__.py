@@ -26,6 +26,8 @@ Parts
   lambda rule lambda = 0.05 max|L^T d|.
 * ``velocity`` -- the automatic anisotropic velocity estimate of Section 3
   (curvature-weighted mean of the Radon cube per intercept and azimuth).
+* ``deconv`` -- the deconvolutive AAHRT of Section 4: L_w = W L with W the
+  convolution of every trace with the wavelet, and its transpose.
 
 Pins: every function here is pinned by ``tests/test_oracle_pins.py`` against
 closed forms, invariants, brute force and special cases.  The difference
@@ -34,7 +36,7 @@ operator) is reported only: parity unpinned for that comparison, as the paper
 shows it only as a figure.
 """
 from .geometry import Geometry, nfft_rule, theta_weights, stretch_matrix, unstretch_matrix
-from . import gfst, timedomain, fista, velocity
+from . import gfst, timedomain, fista, velocity, deconv
 
 __all__ = ['Geometry', 'nfft_rule', 'theta_weights', 'stretch_matrix', 'unstretch_matrix',
-           'gfst', 'timedomain', 'fista', 'velocity']
+           'gfst', 'timedomain', 'fista', 'velocity', 'deconv']

@@ -447,3 +447,39 @@ def test_velocity_of_isotropic_event_cube_recovers_slowness():
     qbar, v = velocity.velocity(m, q)
     assert np.allclose(qbar, q[10], rtol=0, atol=1e-15)
     assert np.allclose(v, q[10] ** -0.5, rtol=1e-14)
+
+
+# ------------------------------------------------------------------ deconvolutive AAHRT (Section 4)
+def test_deconv_convolution_matches_numpy_full_convolution():
+    """W d equals numpy's full linear convolution cut to the trace's samples at origin c."""
+    from oracle import deconv
+    rng = np.random.default_rng(5)
+    d = rng.standard_normal((3, 40))
+    for nw, c in ((1, 0), (7, 3), (9, 0), (9, 8), (60, 20)):
+        w = rng.standard_normal(nw)
+        full = np.stack([np.convolve(row, w) for row in d])      # index s + c of full = output s
+        ref = full[:, c:c + d.shape[1]]
+        assert np.allclose(deconv.convolve(d, w, c), ref, rtol=0, atol=1e-13)
+
+
+def test_deconv_delta_wavelet_is_identity_and_shift_is_shift():
+    from oracle import deconv
+    d = np.random.default_rng(6).standard_normal((2, 30))
+    assert np.array_equal(deconv.convolve(d, [1.0], 0), d)
+    out = deconv.convolve(d, [0.0, 0.0, 1.0], 0)                   # delay by 2 samples
+    assert np.array_equal(out[:, 2:], d[:, :-2]) and np.all(out[:, :2] == 0)
+
+
+def test_deconv_correlation_is_the_transpose_and_operator_dot_test():
+    from oracle import deconv
+    rng = np.random.default_rng(7)
+    w, c = rng.standard_normal(11), 4
+    a, b = rng.standard_normal((4, 50)), rng.standard_normal((4, 50))
+    assert abs(np.sum(deconv.convolve(a, w, c) * b) - np.sum(a * deconv.correlate(b, w, c))) < 1e-11
+    wk = wl.small_case(nt=32, ntr=6, nq=5, ntheta=3, seed=8)
+    g = Geometry.build(wk.axes, wk.gathers[0].x, wk.gathers[0].y)
+    m = rng.standard_normal((3, 5, 32))
+    d = rng.standard_normal((6, 32))
+    lhs = np.sum(deconv.forward(m, g, w, c) * d)
+    rhs = np.sum(m * deconv.adjoint(d, g, w, c))
+    assert abs(lhs - rhs) < 1e-12 * max(1.0, abs(lhs))
