@@ -194,6 +194,20 @@ int aahrt_sparse_solve(aahrt_plan* plan, const float* d, float* m, const float* 
                        aahrt_stream stream);
 
 /*
+ * Deconvolutive AAHRT (Section 4, "Deconvolutive AAHRT"): from this call on, every
+ * operator of the plan is L_w = W L and L_w^T = L^T W^T, with W the linear convolution
+ * of every trace with the wavelet along t (the basis functions carry the wavelet
+ * instead of a delta in time):
+ *   (W d)[s] = sum_j w[j] d[s - j + center],  samples outside 0..nt-1 taken as zero.
+ *   w      : host float[nw] wavelet taps (copied); nw = 0 returns to the plain operator
+ *   nw     : 0..4096
+ *   center : index of the tap at zero lag, 0..nw-1
+ * Synchronises the device and drops a captured solver graph; must not overlap other
+ * calls on the plan.
+ */
+int aahrt_set_wavelet(aahrt_plan* plan, const float* w, int32_t nw, int32_t center);
+
+/*
  * Automatic anisotropic velocity estimate of a Radon cube (Section 3, "Automatic
  * Anisotropic Velocity Peaking"): for every gather b, azimuth theta_j and intercept
  * tau_i, the curvature-weighted mean

@@ -126,6 +126,17 @@ class Plan:
         check(self._lib.aahrt_lambda_max(self._h, d.data_ptr(), out.data_ptr(), _stream(stream)))
         return out
 
+    def set_wavelet(self, w=None, center=0):
+        """Deconvolutive operator L_w = W L (aahrt_set_wavelet); w None or empty: plain L."""
+        import numpy as np
+        if w is None or len(w) == 0:
+            check(self._lib.aahrt_set_wavelet(self._h, None, 0, 0))
+            self._wavelet = None
+            return
+        wa = np.ascontiguousarray(w, dtype=np.float32)
+        check(self._lib.aahrt_set_wavelet(self._h, wa.ctypes.data, int(wa.size), int(center)))
+        self._wavelet = (wa, int(center))
+
     def velocity(self, m, stream=None):
         """Automatic anisotropic velocity estimate (aahrt_velocity): returns (qbar, v), each
         [batch, ntheta, ntau]; qbar = v^-2 in s^2/km^2, v in km/s."""
@@ -139,13 +150,16 @@ class Plan:
 
     def reconstruct(self, m, x_km, y_km, stream=None):
         """Data of the model m on another trace geometry (one gather per model gather):
-        L applied through a plan on the new offsets (x_km, y_km lists of per-gather arrays)."""
+        L (L_w when a wavelet is set) applied through a plan on the new offsets (x_km, y_km
+        lists of per-gather arrays)."""
         import numpy as np
         tp = np.concatenate([[0], np.cumsum([len(x) for x in x_km])]).astype(np.int64)
         other = Plan(self.axes, tp, np.concatenate(x_km), np.concatenate(y_km), nfft=0,
                      nufft_tol=self._params.nufft_tol, sigma=self.info['sigma'],
                      kernel_width=self._params.kernel_width, device=self.device)
         try:
+            if getattr(self, '_wavelet', None) is not None:
+                other.set_wavelet(*self._wavelet)
             return other.forward(m, stream=stream)
         finally:
             other.close()

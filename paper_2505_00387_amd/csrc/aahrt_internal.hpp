@@ -68,6 +68,7 @@ struct Tables {
   const float* tr_alpha;               // azimuth weight on the upper bin
   const int* bin_ptr;                  // [batch][ntheta+1] positions into the bin-ordered arrays
   const int* gather_of_row;            // data row -> gather
+  const float* wav;                    // wavelet taps (deconvolutive operator), or null
 };
 
 struct Dims {
@@ -87,6 +88,7 @@ struct Dims {
   int nftile;   // ceil(nf/ft)
   int qhalf;    // nq/2 (mode offset)
   int gdt;      // storage of the forward q-grid (aahrt_grid_dtype)
+  int nw, wc;   // wavelet of the deconvolutive operator: taps and origin (nw = 0: none)
 };
 
 struct Plan {
@@ -114,6 +116,7 @@ struct Plan {
   float* rss = nullptr;     // [ntr] per-trace residual sums of squares (objective)
   float* tr_bound = nullptr; // [ntr] max_f |Re Dh| + |Im Dh| of each trace (spreading scale bound)
   float* slice_scale = nullptr; // [batch][ntheta] fixed-point scale of each azimuth slice (spreading)
+  float* wav_dev = nullptr;      // wavelet taps (owned; replaced by each aahrt_set_wavelet)
   float* deapod_dev = nullptr;   // [nq] deapodisation of the current q-grid setting
   float2* twgrid_dev = nullptr;  // [mg] q-grid twiddles of the current setting
   int ft_interp = 16;            // frequency tile of the interpolation kernel

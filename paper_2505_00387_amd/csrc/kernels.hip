@@ -263,8 +263,27 @@ __global__ __launch_bounds__(kBlock) void k_model_c2r_update(float2* __restrict_
 }
 
 // ------------------------------------------------------------------ data side
-// Steps 4-5 of L: inverse real DFT of Dh[n][0..N/2-1], unstretch.
-template <bool IP>
+// Deconvolutive AAHRT (Section 4): with a wavelet set (WAV), the data side of L ends
+// with W, the linear convolution of every trace with the wavelet taps w[0..nw-1]
+// (origin wc, samples outside the trace zero), and the data side of L^T starts with
+// W^T, the correlation:
+//   (W v)[s] = sum_j w[j] v[s - j + wc],   (W^T r)[s] = sum_j w[j] r[s + j - wc].
+__device__ __forceinline__ float wav_conv(const float* v, int s, const Tables& tb, const Dims& dm) {
+  const int jlo = max(0, s + dm.wc - dm.nt + 1), jhi = min(dm.nw - 1, s + dm.wc);
+  float acc = 0.f;
+  for (int j = jlo; j <= jhi; ++j) acc = fmaf(tb.wav[j], v[s - j + dm.wc], acc);
+  return acc;
+}
+
+__device__ __forceinline__ float wav_corr(const float* r, int s, const Tables& tb, const Dims& dm) {
+  const int jlo = max(0, dm.wc - s), jhi = min(dm.nw - 1, dm.nt - 1 - s + dm.wc);
+  float acc = 0.f;
+  for (int j = jlo; j <= jhi; ++j) acc = fmaf(tb.wav[j], r[s + j - dm.wc], acc);
+  return acc;
+}
+
+// Steps 4-5 of L: inverse real DFT of Dh[n][0..N/2-1], unstretch (then W).
+template <bool IP, bool WAV>
 __global__ __launch_bounds__(kBlock) void k_data_c2r(const float2* __restrict__ dhat,
                                                      float* __restrict__ d, Tables tb, Dims dm,
                                                      FftPlan fp) {
@@ -274,19 +293,30 @@ __global__ __launch_bounds__(kBlock) void k_data_c2r(const float2* __restrict__ 
   const size_t n = blockIdx.x;
   load_packed_c2r(A, dhat + n * dm.nf, tb, dm);
   __syncthreads();
-  const float* xs = reinterpret_cast<const float*>(row_fft<true, IP>(A, B, fp, tb, dm));
+  const float2* X = row_fft<true, IP>(A, B, fp, tb, dm);
+  const float* xs = reinterpret_cast<const float*>(X);
   const float invN = 1.0f / (float)dm.nfft;
   float* dst = d + n * dm.nt;
+  if (!WAV) {
 #pragma unroll 4
-  for (int s = threadIdx.x; s < dm.nt; s += kBlock) {
-    const Tap t = tb.u_tap[s];
-    dst[s] = invN * (t.w0 * xs[t.i0] + t.w1 * xs[t.i1]);
+    for (int s = threadIdx.x; s < dm.nt; s += kBlock) {
+      const Tap t = tb.u_tap[s];
+      dst[s] = invN * (t.w0 * xs[t.i0] + t.w1 * xs[t.i1]);
+    }
+  } else {
+    float* v = reinterpret_cast<float*>(X == A ? B : A);  // IP: the staging area after A
+    for (int s = threadIdx.x; s < dm.nt; s += kBlock) {
+      const Tap t = tb.u_tap[s];
+      v[s] = invN * (t.w0 * xs[t.i0] + t.w1 * xs[t.i1]);
+    }
+    __syncthreads();
+    for (int s = threadIdx.x; s < dm.nt; s += kBlock) dst[s] = wav_conv(v, s, tb, dm);
   }
 }
 
-// Transpose of step 5 then the forward real DFT (the data side of L^T).
+// (W^T, then) transpose of step 5, then the forward real DFT (the data side of L^T).
 // tr_bound[n] = max_f (|Re Dh[n,f]| + |Im Dh[n,f]|) (the spreading scale bound).
-template <bool IP>
+template <bool IP, bool WAV>
 __global__ __launch_bounds__(kBlock) void k_data_r2c(const float* __restrict__ d,
                                                      float2* __restrict__ dhat,
                                                      float* __restrict__ tr_bound, Tables tb, Dims dm,
@@ -298,7 +328,14 @@ __global__ __launch_bounds__(kBlock) void k_data_r2c(const float* __restrict__ d
   float* g = reinterpret_cast<float*>(B);
   const size_t n = blockIdx.x;
   const float* src = d + n * dm.nt;
-  for (int s = threadIdx.x; s < dm.nt; s += kBlock) g[s] = src[s];
+  if (!WAV) {
+    for (int s = threadIdx.x; s < dm.nt; s += kBlock) g[s] = src[s];
+  } else {
+    float* r = reinterpret_cast<float*>(A);
+    for (int s = threadIdx.x; s < dm.nt; s += kBlock) r[s] = src[s];
+    __syncthreads();
+    for (int s = threadIdx.x; s < dm.nt; s += kBlock) g[s] = wav_corr(r, s, tb, dm);
+  }
   __syncthreads();
   pack_transpose(A, g, tb, dm.nts, dm.nh);
   __syncthreads();
@@ -307,9 +344,9 @@ __global__ __launch_bounds__(kBlock) void k_data_r2c(const float* __restrict__ d
   if (threadIdx.x == 0) tr_bound[n] = mx;
 }
 
-// Solver data side, in place on dhat[n]: r = d_obs - S^-1 F1^-1 Dh (steps 4-5),
+// Solver data side, in place on dhat[n]: r = d_obs - (W) S^-1 F1^-1 Dh (steps 4-5),
 // then the data side of L^T applied to r.  rss[n] = sum r^2 when not null.
-template <bool IP>
+template <bool IP, bool WAV>
 __global__ __launch_bounds__(kBlock) void k_residual_r2c(float2* __restrict__ dhat,
                                                          const float* __restrict__ dobs,
                                                          float* __restrict__ rss,
@@ -329,13 +366,30 @@ __global__ __launch_bounds__(kBlock) void k_residual_r2c(float2* __restrict__ dh
   const float invN = 1.0f / (float)dm.nfft;
   const float* ob = dobs + n * dm.nt;
   float ss = 0.f;
+  if (!WAV) {
 #pragma unroll 4
-  for (int s = threadIdx.x; s < dm.nt; s += kBlock) {
-    const Tap t = tb.u_tap[s];
-    const float v = invN * (t.w0 * xs[t.i0] + t.w1 * xs[t.i1]);
-    const float r = ob[s] - v;
-    g[s] = r;
-    ss += r * r;
+    for (int s = threadIdx.x; s < dm.nt; s += kBlock) {
+      const Tap t = tb.u_tap[s];
+      const float v = invN * (t.w0 * xs[t.i0] + t.w1 * xs[t.i1]);
+      const float r = ob[s] - v;
+      g[s] = r;
+      ss += r * r;
+    }
+  } else {
+    // v = S^-1 F1^-1 Dh into g; r = d_obs - W v into X (its spectrum is consumed); g = W^T r
+    for (int s = threadIdx.x; s < dm.nt; s += kBlock) {
+      const Tap t = tb.u_tap[s];
+      g[s] = invN * (t.w0 * xs[t.i0] + t.w1 * xs[t.i1]);
+    }
+    __syncthreads();
+    float* rr = reinterpret_cast<float*>(X);
+    for (int s = threadIdx.x; s < dm.nt; s += kBlock) {
+      const float r = ob[s] - wav_conv(g, s, tb, dm);
+      rr[s] = r;
+      ss += r * r;
+    }
+    __syncthreads();
+    for (int s = threadIdx.x; s < dm.nt; s += kBlock) g[s] = wav_corr(rr, s, tb, dm);
   }
   __syncthreads();
   pack_transpose(X, g, tb, dm.nts, dm.nh);
@@ -907,21 +961,30 @@ hipError_t launch_model_c2r_update(const Plan& p, float2* mhat, float* y, float*
 
 hipError_t launch_data_c2r(const Plan& p, const float2* dhat, float* d, hipStream_t s) {
   const Dims& dm = p.dm;
-  return launch_row(k_data_c2r<true>, k_data_c2r<false>, dm, 0, (unsigned)dm.ntr, s, dhat, d, p.tb, dm,
-                    p.fft_half);
+  if (dm.nw > 0)
+    return launch_row(k_data_c2r<true, true>, k_data_c2r<false, true>, dm, dm.nt, (unsigned)dm.ntr, s, dhat, d,
+                      p.tb, dm, p.fft_half);
+  return launch_row(k_data_c2r<true, false>, k_data_c2r<false, false>, dm, 0, (unsigned)dm.ntr, s, dhat, d, p.tb,
+                    dm, p.fft_half);
 }
 
 hipError_t launch_data_r2c(const Plan& p, const float* d, float2* dhat, hipStream_t s) {
   const Dims& dm = p.dm;
-  return launch_row(k_data_r2c<true>, k_data_r2c<false>, dm, dm.nt, (unsigned)dm.ntr, s, d, dhat, p.tr_bound,
-                    p.tb, dm, p.fft_half);
+  if (dm.nw > 0)
+    return launch_row(k_data_r2c<true, true>, k_data_r2c<false, true>, dm, dm.nt, (unsigned)dm.ntr, s, d, dhat,
+                      p.tr_bound, p.tb, dm, p.fft_half);
+  return launch_row(k_data_r2c<true, false>, k_data_r2c<false, false>, dm, dm.nt, (unsigned)dm.ntr, s, d, dhat,
+                    p.tr_bound, p.tb, dm, p.fft_half);
 }
 
 hipError_t launch_residual_r2c(const Plan& p, float2* dhat, const float* dobs, float* rss,
                                hipStream_t s) {
   const Dims& dm = p.dm;
-  return launch_row(k_residual_r2c<true>, k_residual_r2c<false>, dm, dm.nt, (unsigned)dm.ntr, s, dhat, dobs,
-                    rss, p.tr_bound, p.tb, dm, p.fft_half);
+  if (dm.nw > 0)
+    return launch_row(k_residual_r2c<true, true>, k_residual_r2c<false, true>, dm, dm.nt, (unsigned)dm.ntr, s,
+                      dhat, dobs, rss, p.tr_bound, p.tb, dm, p.fft_half);
+  return launch_row(k_residual_r2c<true, false>, k_residual_r2c<false, false>, dm, dm.nt, (unsigned)dm.ntr, s,
+                    dhat, dobs, rss, p.tr_bound, p.tb, dm, p.fft_half);
 }
 
 #define AAHRT_W_CASES(MACRO) \

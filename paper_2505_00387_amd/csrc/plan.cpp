@@ -179,6 +179,7 @@ int alloc(Plan& p, size_t count, T** out) {
 
 void free_plan(Plan* p) {
   if (!p) return;
+  if (p->wav_dev) (void)hipFree(p->wav_dev);
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
   if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
@@ -446,6 +447,9 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
   // is built now, the others are timed by the autotuner once the plan is complete
   dm.qhalf = dm.nq / 2;
   dm.gdt = prm.grid_dtype;
+  dm.nw = 0;
+  dm.wc = 0;
+  P.tb.wav = nullptr;
   std::vector<NufftChoice> cands;
   TRY(nufft_candidates(prm, dm, cands));
   if (2 * (size_t)dm.nhp * sizeof(float2) > 160 * 1024 || std::max(dm.nt, dm.ntau) > 2 * dm.nh)
@@ -818,6 +822,39 @@ int aahrt_velocity(aahrt_plan* plan, const float* m, float* qbar, float* vel, aa
   if (!m || !qbar || !vel) return fail(AAHRT_E_INVALID, "m, qbar and vel must not be NULL");
   HIP_TRY(hipSetDevice(P.device));
   HIP_TRY(launch_velocity(P, m, qbar, vel, as_stream(stream)));
+  return AAHRT_OK;
+}
+
+int aahrt_set_wavelet(aahrt_plan* plan, const float* w, int32_t nw, int32_t center) {
+  TRY(check_plan(plan));
+  Plan& P = P_of(plan);
+  if (nw < 0 || nw > 4096) return fail(AAHRT_E_INVALID, "nw must be in 0..4096");
+  if (nw > 0 && !w) return fail(AAHRT_E_INVALID, "w is NULL");
+  if (nw > 0 && (center < 0 || center >= nw)) return fail(AAHRT_E_INVALID, "center must be in 0..nw-1");
+  for (int j = 0; j < nw; ++j)
+    if (!std::isfinite(w[j])) return fail(AAHRT_E_INVALID, "non-finite wavelet tap");
+  HIP_TRY(hipSetDevice(P.device));
+  HIP_TRY(hipDeviceSynchronize());
+  if (P.wav_dev) {
+    HIP_TRY(hipFree(P.wav_dev));
+    P.wav_dev = nullptr;
+  }
+  if (nw > 0) {
+    void* dptr = nullptr;
+    if (hipMalloc(&dptr, (size_t)nw * sizeof(float)) != hipSuccess)
+      return fail(AAHRT_E_NOMEM, "hipMalloc of the wavelet failed");
+    P.wav_dev = static_cast<float*>(dptr);
+    HIP_TRY(hipMemcpy(P.wav_dev, w, (size_t)nw * sizeof(float), hipMemcpyHostToDevice));
+  }
+  P.tb.wav = P.wav_dev;
+  P.dm.nw = nw;
+  P.dm.wc = nw > 0 ? center : 0;
+  // a captured solver graph holds the kernels of the previous operator
+  if (P.graph_exec) (void)hipGraphExecDestroy(P.graph_exec);
+  if (P.graph) (void)hipGraphDestroy(P.graph);
+  P.graph_exec = nullptr;
+  P.graph = nullptr;
+  P.graph_key.clear();
   return AAHRT_OK;
 }
 

@@ -454,3 +454,67 @@ def test_reconstruction_on_a_new_geometry():
         off += xs[b].size
         assert e < TOL, (b, e)
     plan.close()
+
+
+# ------------------------------------------------------------------ deconvolutive AAHRT (Section 4)
+def _ricker_taps(f0, dt):
+    half = int(np.ceil(1.6 / (f0 * dt)))
+    t = dt * np.arange(-half, half + 1)
+    return wl.ricker(t, f0), half
+
+
+def test_deconv_operator_parity():
+    from oracle import deconv
+    for w, seed in ((wl.config1(with_data=False), 41), (wl.config3(with_data=False), 42)):
+        taps, c = _ricker_taps(25.0, w.axes.dt)
+        gs = geoms(w)
+        plan = make_plan(w)
+        plan.set_wavelet(taps, c)
+        m = wl.random_model(w.axes, w.batch, seed)
+        d = wl.random_data(plan.ntraces, w.axes.nt, seed)
+        got_d = to_host(plan.forward(to_dev(m)))
+        got_m = to_host(plan.adjoint(to_dev(d)))
+        tp = w.trace_ptr
+        tw = taps.astype(np.float32).astype(np.float64)
+        for b, g in enumerate(gs):
+            ef = rel(got_d[tp[b]:tp[b + 1]], deconv.forward(m[b], g, tw, c))
+            ea = rel(got_m[b], deconv.adjoint(d[tp[b]:tp[b + 1]], g, tw, c))
+            assert ef < TOL and ea < TOL, (w.name, b, ef, ea)
+        print(f'{w.name} deconvolutive forward {ef:.2e} adjoint {ea:.2e}')
+        # clearing the wavelet gives back the plain operator, bitwise
+        plan.set_wavelet(None)
+        plain = make_plan(w)
+        assert np.array_equal(to_host(plan.forward(to_dev(m))), to_host(plain.forward(to_dev(m))))
+        plain.close()
+        plan.close()
+
+
+def test_deconv_fista_parity_config1():
+    """20 FISTA iterations of the deconvolutive sparse AAHRT, oracle lambda and step; also the
+    captured graph after a change of wavelet equals the eager run."""
+    from oracle import deconv
+    w = wl.config1()
+    taps, c = _ricker_taps(25.0, w.axes.dt)
+    tw = taps.astype(np.float32).astype(np.float64)
+    g = geoms(w)[0]
+    d = w.gathers[0].data
+    L = lambda v: deconv.forward(v, g, tw, c)
+    Lt = lambda v: deconv.adjoint(v, g, tw, c)
+    rng = np.random.default_rng(0)
+    n2 = fista.power_norm2(L, Lt, rng.standard_normal((g.ntheta, g.nq, g.ntau)), 30)
+    lam, gam = fista.lambda_rule(Lt, d), fista.step_from_norm2(n2)
+    ref = fista.solve(L, Lt, d, lam, gam, 20)
+    plan = make_plan(w)
+    x0, _ = plan.sparse_solve(to_dev(d), 20, lam=to_dev(np.array([lam])), step=to_dev(np.array([gam])),
+                              graph=True)                       # captures the plain-operator graph
+    plan.set_wavelet(taps, c)
+    xg, _ = plan.sparse_solve(to_dev(d), 20, lam=to_dev(np.array([lam])), step=to_dev(np.array([gam])),
+                              graph=True)
+    xe, _ = plan.sparse_solve(to_dev(d), 20, lam=to_dev(np.array([lam])), step=to_dev(np.array([gam])),
+                              graph=False)
+    err = rel(to_host(xg)[0], ref)
+    print(f'deconvolutive fista config1: {err:.2e}')
+    assert err < TOL
+    assert np.array_equal(to_host(xg), to_host(xe))
+    assert rel(to_host(x0)[0], ref) > 10 * TOL                   # the plain operator solves another problem
+    plan.close()
