@@ -318,6 +318,19 @@ def main():
     t_pair_w = (time.perf_counter() - t0) / args.pairs
     plan.set_wavelet(None)
 
+    # the paper's linear k-interpolation (kernel width 2, sigma 2) on the same batch
+    plan_lin = plan_from_workload(w, device=0, kernel_width=2, sigma=2.0)
+    plan_lin.forward(mr, dd)
+    plan_lin.adjoint(dd, ma)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.pairs):
+        plan_lin.forward(mr, dd)
+        plan_lin.adjoint(dd, ma)
+    torch.cuda.synchronize()
+    t_pair_lin = (time.perf_counter() - t0) / args.pairs
+    plan_lin.close()
+
     # velocity estimate of the solved cube (Section 3): one read of the model, two small outputs
     plan.velocity(m)
     torch.cuda.synchronize()
@@ -390,6 +403,7 @@ def main():
                       'velocity_estimate_ms': round(1e3 * t_vel, 3),
                       'deconvolutive_fwd_adj_pair_ms': round(1e3 * t_pair_w, 3),
                       'deconvolutive_wavelet_taps': 2 * half + 1,
+                      'linear_k_interp_fwd_adj_pair_ms': round(1e3 * t_pair_lin, 3),
                       'velocity_estimate_GBs': round(vel_bytes / t_vel / 1e9, 1),
                       'fwd_adj_pairs_per_s': round(pairs_per_s, 1), 'fwd_adj_pair_ms': round(1e3 * t_pair, 3),
                       'fwd_adj_alg_GBs': round(pair_gbs, 1), 'setup_plan_s': round(t_plan, 3),

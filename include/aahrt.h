@@ -79,7 +79,9 @@ typedef struct aahrt_params {
                             otherwise it must be even, 2^a3^b5^c and >= nt' */
   double nufft_tol;      /* target relative error of the q nonuniform FFT; 0 -> 1e-6 */
   double sigma;          /* q-grid oversampling in [1.25, 4]; 0 -> autotune among 2, 1.5 and 1.25 */
-  int32_t kernel_width;  /* spreading kernel width w (3..12); 0 -> chosen from nufft_tol and sigma */
+  int32_t kernel_width;  /* spreading kernel width w (3..12); 0 -> chosen from nufft_tol and sigma;
+                            2 -> the paper's own step 3 (Section 3.4): linear interpolation in k on the
+                            sigma-oversampled grid, no deapodisation (low accuracy, reported only) */
   int32_t freq_tile;     /* frequencies per work item of the GFST stage (power of 2, 1..64); 0 -> autotune */
   int32_t grid_dtype;    /* aahrt_grid_dtype */
 } aahrt_params;

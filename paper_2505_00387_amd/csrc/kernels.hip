@@ -458,6 +458,15 @@ __device__ __forceinline__ float es_tap(float z, float cbeta) {
   return __builtin_amdgcn_exp2f(fmaf(cbeta, __builtin_amdgcn_sqrtf(q), -cbeta));
 }
 
+// Interpolation weight of a tap at normalised distance z: the exponential of
+// semicircle for W >= 3; W = 2 is the linear interpolation of the paper's step 3
+// (Section 3.4), weight 1 - |z| between the two neighbouring grid cells.
+template <int W>
+__device__ __forceinline__ float grid_tap(float z, float cbeta) {
+  if (W == 2) return fmaxf(1.0f - fabsf(z), 0.0f);
+  return es_tap(z, cbeta);
+}
+
 // Logical tile index with consecutive tiles (same gather) on one XCD: the
 // hardware deals workgroup i to XCD i mod 8.
 __device__ __forceinline__ int xcd_tile(int id, int n) {
@@ -607,7 +616,7 @@ __global__ __launch_bounds__(kBlockG) void k_nufft_interp(const float2* __restri
         float2 a0 = make_float2(0.f, 0.f), a1 = make_float2(0.f, 0.f);
 #pragma unroll
         for (int t = 0; t < W; ++t) {
-          const float ph = es_tap(fmaf((float)t, -2.0f / (float)W, kp.z0), dm.cbeta);
+          const float ph = grid_tap<W>(fmaf((float)t, -2.0f / (float)W, kp.z0), dm.cbeta);
           const float2 v0 = dec_cell<GD>(g0[t]), v1 = dec_cell<GD>(g1[t]);
           a0.x = fmaf(ph, v0.x, a0.x);
           a0.y = fmaf(ph, v0.y, a0.y);
@@ -697,7 +706,7 @@ __device__ __forceinline__ void spread_bin(unsigned long long* lo, unsigned long
     unsigned long long* g1 = HAS_HI ? hi + fl * ldr + kp.base : nullptr;
 #pragma unroll
     for (int t = 0; t < W; ++t) {
-      const float ph = es_tap(fmaf((float)t, -2.0f / (float)W, kp.z0), dm.cbeta);
+      const float ph = grid_tap<W>(fmaf((float)t, -2.0f / (float)W, kp.z0), dm.cbeta);
       if (HAS_LO) atomicAdd(g0 + t, pack_fix(ph * s0.x, ph * s0.y));
       if (HAS_HI) atomicAdd(g1 + t, pack_fix(ph * s1.x, ph * s1.y));
     }
@@ -988,7 +997,7 @@ hipError_t launch_residual_r2c(const Plan& p, float2* dhat, const float* dobs, f
 }
 
 #define AAHRT_W_CASES(MACRO) \
-  MACRO(3) MACRO(4) MACRO(5) MACRO(6) MACRO(7) MACRO(8) MACRO(9) MACRO(10) MACRO(11) MACRO(12)
+  MACRO(2) MACRO(3) MACRO(4) MACRO(5) MACRO(6) MACRO(7) MACRO(8) MACRO(9) MACRO(10) MACRO(11) MACRO(12)
 
 // Dims of a GFST launch with the kernel's own frequency tile.
 static Dims tile_dims(const Dims& d0, int ft) {

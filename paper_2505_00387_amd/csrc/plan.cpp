@@ -204,8 +204,8 @@ int validate_params(const aahrt_params& q) {
     return bad("nfft must be 0 or even, 2^a3^b5^c and >= nt'");
   if (q.nufft_tol < 0.0 || !std::isfinite(q.nufft_tol)) return bad("nufft_tol must be >= 0");
   if (q.sigma != 0.0 && !(q.sigma >= 1.25 && q.sigma <= 4.0)) return bad("sigma must be 0 or in [1.25, 4]");
-  if (q.kernel_width != 0 && (q.kernel_width < 3 || q.kernel_width > 12))
-    return bad("kernel_width must be 0 or in 3..12");
+  if (q.kernel_width != 0 && (q.kernel_width < 2 || q.kernel_width > 12))
+    return bad("kernel_width must be 0 or in 2..12");
   if (q.freq_tile != 0 && (q.freq_tile < 1 || q.freq_tile > 64 || (q.freq_tile & (q.freq_tile - 1))))
     return bad("freq_tile must be 0 or a power of two in 1..64");
   if (q.grid_dtype != AAHRT_GRID_F32 && q.grid_dtype != AAHRT_GRID_F16 && q.grid_dtype != AAHRT_GRID_BF16)
@@ -313,7 +313,8 @@ int set_nufft(Plan& P, const NufftChoice& c) {
   std::vector<float> deapod(dm.nq);
   for (int l = 0; l < dm.nq; ++l) {
     const int k = l - dm.qhalf;
-    deapod[l] = (float)(1.0 / es_transform(2.0 * M_PI * k / c.mg, c.w, beta));
+    // w = 2: the paper's linear interpolation in k, which it applies without correction
+    deapod[l] = c.w == 2 ? 1.0f : (float)(1.0 / es_transform(2.0 * M_PI * k / c.mg, c.w, beta));
   }
   std::vector<float2> tw_grid(c.mg);
   for (int t = 0; t < c.mg; ++t) {

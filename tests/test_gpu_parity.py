@@ -518,3 +518,30 @@ def test_deconv_fista_parity_config1():
     assert np.array_equal(to_host(xg), to_host(xe))
     assert rel(to_host(x0)[0], ref) > 10 * TOL                   # the plain operator solves another problem
     plan.close()
+
+
+# ------------------------------------------------------------------ the paper's linear k-interpolation
+def test_linear_k_interpolation_mode():
+    """kernel_width = 2: the paper's step 3 (Section 3.4), linear interpolation in k on the
+    sigma-oversampled grid without deapodisation.  The GPU pair is an exact transpose pair (FP32
+    dot test); its error against the exact operator is reported, and falls as the grid is refined."""
+    w = wl.config1(with_data=False)
+    g = geoms(w)[0]
+    m = wl.random_model(w.axes, 1, 51)
+    d = wl.random_data(256, w.axes.nt, 51)
+    ref_d, ref_m = gfst.forward(m[0], g), gfst.adjoint(d, g)
+    errs = {}
+    for sigma in (2.0, 4.0):
+        plan = make_plan(w, kernel_width=2, sigma=sigma)
+        assert plan.info['kernel_width'] == 2
+        got_d = to_host(plan.forward(to_dev(m)))
+        got_m = to_host(plan.adjoint(to_dev(d)))
+        lhs, rhs = float(np.sum(got_d * d)), float(np.sum(m * got_m))
+        scale = np.linalg.norm(got_d) * np.linalg.norm(d)
+        assert abs(lhs - rhs) < 1e-5 * scale
+        errs[sigma] = (rel(got_d, ref_d), rel(got_m[0], ref_m))
+        plan.close()
+    print('linear k-interpolation, relative error (forward, adjoint) by oversampling:',
+          {k: (f'{a:.2e}', f'{b:.2e}') for k, (a, b) in errs.items()})
+    assert errs[4.0][0] < errs[2.0][0] and errs[4.0][1] < errs[2.0][1]
+    assert errs[2.0][0] < 1.0 and errs[4.0][0] > 1e-4
