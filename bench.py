@@ -224,6 +224,59 @@ def plain_comparison(w, plan, lib_pair_s, n_sample, dev):
             'speedup_vs_plain': round(t_batch / lib_pair_s, 1), 'plain_vs_library_rel_diff': diff}
 
 
+# seconds printed in the paper's timing table (Section 5) for (nt, nx = ny, np): direct sum, proposed
+PAPER_TABLE1 = {(512, 128, 128): (218, 0.87), (512, 128, 256): (421, 1.14), (512, 256, 128): (915, 3.80),
+                (512, 256, 256): (1685, 3.98), (1024, 128, 128): (497, 1.97), (1024, 128, 256): (875, 2.78),
+                (1024, 256, 128): (1806, 8.57), (1024, 256, 256): (3416, 8.82)}
+
+
+def _timed(fn, reps):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def table1_scan(reps: int):
+    """Velocity scan (the adjoint, data -> (tau, q, theta)) at the shapes of the paper's timing
+    table: the GFST adjoint of the library against the GPU time-domain direct sum, one CMP on a
+    regular offset grid at 40 m, 90 azimuths.  One JSON line per shape."""
+    import torch
+    import workloads as wl
+    from paper_2505_00387_amd import plan_from_workload
+    dev = torch.device('cuda:0')
+    for nt, nxy, np_ in wl.TABLE1_SHAPES:
+        w = wl.table1(nt, nxy, np_)
+        t0 = time.perf_counter()
+        plan = plan_from_workload(w, device=0)
+        torch.cuda.synchronize()
+        t_plan = time.perf_counter() - t0
+        d = torch.tensor(w.gathers[0].data, dtype=torch.float32, device=dev)
+        m_g = torch.empty(plan.model_shape, dtype=torch.float32, device=dev)
+        m_d = torch.empty(plan.model_shape, dtype=torch.float32, device=dev)
+        t_gfst = _timed(lambda: plan.adjoint(d, m_g), reps)
+        t_direct = _timed(lambda: plan.adjoint_direct(d, m_d), max(1, reps // 5))
+        diff = (torch.linalg.norm(m_g - m_d) / torch.linalg.norm(m_d)).item()
+        paper = PAPER_TABLE1[(nt, nxy, np_)]
+        out = {'metric': 'velocity scan seconds (adjoint, one CMP)', 'workload': w.name,
+               'nt': nt, 'nx': nxy, 'ny': nxy, 'np': np_, 'ntheta': w.axes.ntheta, 'traces': plan.ntraces,
+               'gfst_adjoint_s': round(t_gfst, 6), 'direct_adjoint_s': round(t_direct, 6),
+               'speedup_direct_over_gfst': round(t_direct / t_gfst, 1),
+               'gfst_vs_direct_rel_diff': round(diff, 4),
+               'paper_direct_s': paper[0], 'paper_proposed_s': paper[1],
+               'paper_speedup': round(paper[0] / paper[1], 1),
+               'plan_s': round(t_plan, 3), 'nfft': plan.info['nfft'], 'grid': plan.info['grid_size'],
+               'kernel_width': plan.info['kernel_width'], 'dtype': 'f32', 'data': 'synthetic'}
+        print(json.dumps(out), flush=True)
+        plan.close()
+        del d, m_g, m_d
+        torch.cuda.empty_cache()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument('--gpus', type=int, default=1)
@@ -233,6 +286,8 @@ def main():
     ap.add_argument('--no-cpu', action='store_true', help='skip the oracle CPU-baseline leg')
     ap.add_argument('--pairs', type=int, default=5, help='timed fwd+adj pairs')
     ap.add_argument('--plain-sample', type=int, default=16, help='gathers of the plain-operator comparison (0: skip)')
+    ap.add_argument('--table1', action='store_true',
+                    help='instead of the solve: the velocity-scan timing at the paper\'s table shapes')
     args = ap.parse_args()
     if args.gpus != 1:
         print('bench.py runs on one GPU only: the batched solve shards by gather, and this build '
@@ -245,6 +300,9 @@ def main():
     from paper_2505_00387_amd import plan_from_workload
 
     assert torch.cuda.is_available(), 'bench.py needs a GPU'
+    if args.table1:
+        table1_scan(max(args.steps, 5))
+        return
     dev = torch.device('cuda:0')
     t0 = time.perf_counter()
     w = wl.config4(with_data=True)

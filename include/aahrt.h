@@ -196,6 +196,18 @@ int aahrt_sparse_solve(aahrt_plan* plan, const float* d, float* m, const float* 
                        aahrt_stream stream);
 
 /*
+ * Conventional time-domain adjoint (Section 5's direct summation, the method the
+ * paper's timing table compares against): for every gather b, azimuth theta_j,
+ * curvature q_l and intercept tau_i, the Riemann sum over the traces n of
+ *   w[n][j] ((1 - a) d[n][s] + a d[n][s+1]),  s + a = sqrt(tau_i^2 + q_l h_n^2)/dt,
+ * with the linear azimuth weights of the plan and taps at or beyond nt dropped.  A
+ * second discretisation of the continuous adjoint, for timing comparison; positions
+ * in FP64, sums in FP32.  Layouts as aahrt_adjoint; m is overwritten.  Returns
+ * AAHRT_E_UNSUPPORTED when a wavelet is set or batch*ntheta or nq exceeds 65535.
+ */
+int aahrt_adjoint_direct(aahrt_plan* plan, const float* d, float* m, aahrt_stream stream);
+
+/*
  * Deconvolutive AAHRT (Section 4, "Deconvolutive AAHRT"): from this call on, every
  * operator of the plan is L_w = W L and L_w^T = L^T W^T, with W the linear convolution
  * of every trace with the wavelet along t (the basis functions carry the wavelet

@@ -69,6 +69,7 @@ struct Tables {
   const int* bin_ptr;                  // [batch][ntheta+1] positions into the bin-ordered arrays
   const int* gather_of_row;            // data row -> gather
   const float* wav;                    // wavelet taps (deconvolutive operator), or null
+  const double* tr_h2;                 // h^2 of the trace (direct time-domain operator)
 };
 
 struct Dims {
@@ -173,6 +174,7 @@ hipError_t launch_model_c2r_update(const Plan& p, float2* mhat, float* y, float*
                                    const float* lam, float beta, int ista, float* l1, bool next,
                                    hipStream_t s);
 hipError_t launch_velocity(const Plan& p, const float* m, float* qbar, float* vel, hipStream_t s);
+hipError_t launch_direct_adjoint(const Plan& p, const float* d, float* m, hipStream_t s);
 hipError_t launch_fill(float* p, float v, size_t n, hipStream_t s);
 hipError_t launch_copy(float* dst, const float* src, size_t n, hipStream_t s);
 hipError_t launch_seed_vector(float* v, size_t n, unsigned seed, hipStream_t s);

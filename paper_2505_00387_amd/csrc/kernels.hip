@@ -903,6 +903,49 @@ __global__ __launch_bounds__(kBlock) void k_velocity(const float* __restrict__ m
   vel[bj * ntau + i] = qb > 0.f ? 1.0f / sqrtf(qb) : 0.f;
 }
 
+// Conventional time-domain adjoint (the direct summation the paper compares against
+// in Section 5): for every output (b, j, l, i) the Riemann sum over the traces that
+// reach azimuth j (bin j with weight 1 - alpha, bin j-1 mod ntheta with weight alpha)
+// of the trace sample at t = sqrt(tau_i^2 + q_l h^2), linearly interpolated in time
+// (taps at or beyond nt dropped).  Positions in FP64; one thread per intercept, the
+// per-trace values are uniform across the block.
+__global__ __launch_bounds__(kBlock) void k_direct_adjoint(const float* __restrict__ d, float* __restrict__ m,
+                                                           Tables tb, Dims dm, double dtau, double dt,
+                                                           double q_min, double dq) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= dm.ntau) return;
+  const int l = blockIdx.y;
+  const int bj = blockIdx.z;
+  const int b = bj / dm.ntheta;
+  const int j = bj - b * dm.ntheta;
+  const int* bp = tb.bin_ptr + (size_t)b * (dm.ntheta + 1);
+  const int jm = j == 0 ? dm.ntheta - 1 : j - 1;  // ntheta = 1: both passes run over bin 0
+  const double tau = i * dtau;
+  const double tau2 = tau * tau;
+  const double q = q_min + l * dq;
+  const double inv_dt = 1.0 / dt;
+  float acc = 0.f;
+  for (int pass = 0; pass < 2; ++pass) {
+    const int lo = pass == 0 ? bp[j] : bp[jm];
+    const int hi = pass == 0 ? bp[j + 1] : bp[jm + 1];
+    for (int n = lo; n < hi; ++n) {
+      const double arg = tau2 + q * tb.tr_h2[n];
+      if (arg < 0.0) continue;
+      const double tt = sqrt(arg) * inv_dt;
+      const double sf = floor(tt);
+      if (sf >= (double)dm.nt) continue;
+      const int s = (int)sf;
+      const float a = (float)(tt - sf);
+      const float* row = d + (size_t)tb.tr_row[n] * dm.nt;
+      float v = (1.0f - a) * row[s];
+      if (s + 1 < dm.nt) v = fmaf(a, row[s + 1], v);
+      const float al = tb.tr_alpha[n];
+      acc = fmaf(pass == 0 ? 1.0f - al : al, v, acc);
+    }
+  }
+  m[((size_t)bj * dm.nq + l) * dm.ntau + i] = acc;
+}
+
 // ------------------------------------------------------------------ launchers
 
 static size_t interp_lds_bytes(const Dims& dm) {
@@ -1124,6 +1167,15 @@ hipError_t launch_velocity(const Plan& p, const float* m, float* qbar, float* ve
   const dim3 grid((unsigned)((dm.ntau + kBlock - 1) / kBlock), (unsigned)(dm.batch * dm.ntheta));
   hipLaunchKernelGGL(k_velocity, grid, dim3(kBlock), 0, s, m, qbar, vel, dm.nq, dm.ntau, (float)p.prm.q_min,
                      (float)dq);
+  return hipGetLastError();
+}
+
+hipError_t launch_direct_adjoint(const Plan& p, const float* d, float* m, hipStream_t s) {
+  const Dims& dm = p.dm;
+  const double dq = (p.prm.q_max - p.prm.q_min) / (dm.nq - 1);
+  const dim3 grid((unsigned)((dm.ntau + kBlock - 1) / kBlock), (unsigned)dm.nq, (unsigned)(dm.batch * dm.ntheta));
+  hipLaunchKernelGGL(k_direct_adjoint, grid, dim3(kBlock), 0, s, d, m, p.tb, dm, p.prm.dtau, p.prm.dt, p.prm.q_min,
+                     dq);
   return hipGetLastError();
 }
 

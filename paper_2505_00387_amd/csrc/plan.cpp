@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <new>
 #include <string>
 #include <vector>
@@ -146,6 +147,58 @@ bool make_fft_plan(int n, FftPlan& pl) {
   return true;
 }
 
+// Fill the passes of a plan for a given radix order.
+void fill_fft_plan(int n, const std::vector<int>& radices, FftPlan& pl) {
+  pl.n = n;
+  pl.npass = (int)radices.size();
+  int ns = 1;
+  for (int i = 0; i < pl.npass; ++i) {
+    FftPass& ps = pl.pass[i];
+    const int R = radices[i];
+    ps.r = R;
+    ps.nb = n / R;
+    ps.ns = ns;
+    ps.stride = n / (ns * R);
+    ps.dnb = make_fastdiv((unsigned)ps.nb);
+    ps.dns = make_fastdiv((unsigned)ps.ns);
+    ns *= R;
+  }
+}
+
+// Radix order of the q-grid transform, which runs in place (one butterfly per thread
+// per pass over all rows): the fewest butterflies in the busiest pass, then the fewest
+// passes; ties keep the order of make_fft_plan.
+bool make_grid_fft_plan(int n, FftPlan& pl) {
+  if (!make_fft_plan(n, pl)) return false;
+  int best_nb = 0;
+  for (int i = 0; i < pl.npass; ++i) best_nb = std::max(best_nb, pl.pass[i].nb);
+  int best_np = pl.npass;
+  std::vector<int> best, cur;
+  const int radices[] = {16, 15, 9, 8, 5, 4, 3, 2};
+  std::function<void(int)> search = [&](int m) {
+    if ((int)cur.size() > kMaxPasses) return;
+    if (m == 1) {
+      int mx = 0;
+      for (int r : cur) mx = std::max(mx, n / r);
+      if (mx < best_nb || (mx == best_nb && (int)cur.size() < best_np)) {
+        best_nb = mx;
+        best_np = (int)cur.size();
+        best = cur;
+      }
+      return;
+    }
+    for (int r : radices)
+      if (m % r == 0) {
+        cur.push_back(r);
+        search(m / r);
+        cur.pop_back();
+      }
+  };
+  search(n);
+  if (!best.empty()) fill_fft_plan(n, best, pl);
+  return true;
+}
+
 template <typename T>
 int upload(Plan& p, const std::vector<T>& h, const T** out) {
   void* d = nullptr;
@@ -245,7 +298,7 @@ int slot_row(int mg, int w) {
 // every pass of the in-place q-grid transform has at most one butterfly per thread.
 bool choice_fits(const Dims& dm, int mg, int w, int ft) {
   FftPlan fp;
-  if (!make_fft_plan(mg, fp)) return false;
+  if (!make_grid_fft_plan(mg, fp)) return false;
   for (int i = 0; i < fp.npass; ++i)
     if ((long)fp.pass[i].nb * ft > kBlockG) return false;
   return grid_lds(ft, slot_row(mg, w), dm.ntheta, mg, dm.gdt) <= 160 * 1024 && dm.nq * ft <= kPrefetchCells;
@@ -272,7 +325,7 @@ int nufft_candidates(const aahrt_params& prm, const Dims& dm, std::vector<NufftC
     if (std::find(seen_mg.begin(), seen_mg.end(), mg) != seen_mg.end()) continue;
     seen_mg.push_back(mg);
     FftPlan fp;
-    if (!make_fft_plan(mg, fp)) continue;
+    if (!make_grid_fft_plan(mg, fp)) continue;
     if (prm.freq_tile != 0) {
       // a requested tile is halved until it fits
       int ft = prm.freq_tile;
@@ -296,7 +349,7 @@ int nufft_candidates(const aahrt_params& prm, const Dims& dm, std::vector<NufftC
 // the device deapodisation and q-grid twiddle tables.
 int set_nufft(Plan& P, const NufftChoice& c) {
   Dims& dm = P.dm;
-  if (!make_fft_plan(c.mg, P.fft_grid)) return fail(AAHRT_E_UNSUPPORTED, "q-grid length not 5-smooth");
+  if (!make_grid_fft_plan(c.mg, P.fft_grid)) return fail(AAHRT_E_UNSUPPORTED, "q-grid length not 5-smooth");
   dm.mg = c.mg;
   dm.w = c.w;
   P.sigma = (double)c.mg / dm.nq;
@@ -517,6 +570,7 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
   std::vector<int> tr_row(dm.ntr), bin_ptr((size_t)batch * (prm.ntheta + 1)), gather_of_row(dm.ntr);
   std::vector<unsigned long long> tr_b(dm.ntr), tr_a(dm.ntr);
   std::vector<float> tr_alpha(dm.ntr);
+  std::vector<double> tr_h2(dm.ntr);
   std::vector<int> jbin(dm.ntr);
   std::vector<double> alpha(dm.ntr);
   for (int n = 0; n < dm.ntr; ++n) {
@@ -547,6 +601,7 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
       tr_b[pos] = to_fix64(dq * h2 / (dm.nfft * dts));
       tr_a[pos] = to_fix64(qc * h2 / (dm.nfft * dts));
       tr_alpha[pos] = (float)alpha[n];
+      tr_h2[pos] = h2;
       gather_of_row[n] = b;
     }
   }
@@ -569,6 +624,7 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
   }
   TRY(upload(P, tr_row, &tb.tr_row)); TRY(upload(P, tr_b, &tb.tr_b)); TRY(upload(P, tr_a, &tb.tr_a));
   TRY(upload(P, tr_alpha, &tb.tr_alpha)); TRY(upload(P, bin_ptr, &tb.bin_ptr));
+  TRY(upload(P, tr_h2, &tb.tr_h2));
   TRY(upload(P, gather_of_row, &tb.gather_of_row));
   std::vector<int64_t> tp(P.trace_ptr);
   const int64_t* tpd = nullptr;
@@ -856,6 +912,20 @@ int aahrt_set_wavelet(aahrt_plan* plan, const float* w, int32_t nw, int32_t cent
   P.graph_exec = nullptr;
   P.graph = nullptr;
   P.graph_key.clear();
+  return AAHRT_OK;
+}
+
+int aahrt_adjoint_direct(aahrt_plan* plan, const float* d, float* m, aahrt_stream stream) {
+  TRY(check_plan(plan));
+  Plan& P = P_of(plan);
+  if (!m) return fail(AAHRT_E_INVALID, "m is NULL");
+  if (!d && P.dm.ntr > 0) return fail(AAHRT_E_INVALID, "d is NULL");
+  if (P.dm.nw > 0) return fail(AAHRT_E_UNSUPPORTED, "the direct adjoint covers the plain operator (no wavelet)");
+  if ((long)P.dm.batch * P.dm.ntheta > 65535 || P.dm.nq > 65535)
+    return fail(AAHRT_E_UNSUPPORTED, "batch*ntheta and nq must each be at most 65535 for the direct adjoint");
+  if ((long)P.dm.batch * P.dm.ntau == 0) return AAHRT_OK;
+  HIP_TRY(hipSetDevice(P.device));
+  HIP_TRY(launch_direct_adjoint(P, d, m, as_stream(stream)));
   return AAHRT_OK;
 }
 

@@ -102,5 +102,18 @@ def test_null_arguments_are_rejected():
     assert lib.aahrt_sparse_solve(None, None, None, None, None, 1, 0, None, None) == -1
     assert lib.aahrt_set_wavelet(None, None, 0, 0) == -1
     assert lib.aahrt_velocity(None, None, None, None, None) == -1
+    assert lib.aahrt_adjoint_direct(None, None, None, None) == -1
     assert lib.aahrt_plan_destroy(None) == 0
     assert lib.aahrt_plan_create(None, None, 1, None, None, None, 0) == -1
+
+
+def test_velocity_scan_shapes():
+    """The timing-table workload: a regular grid at 40 m centred on zero offset, 4 ms, 90 azimuths."""
+    import workloads as wl
+    assert len(wl.TABLE1_SHAPES) == 8
+    w = wl.table1(64, 6, 8)
+    g = w.gathers[0]
+    assert g.x.size == 36 and g.data.shape == (36, 64)
+    assert np.allclose(np.unique(np.round(g.x, 9)), (np.arange(6) - 2.5) * 0.04)
+    assert w.axes.dt == 0.004 and w.axes.ntheta == 90 and w.axes.nq == 8
+    assert np.isfinite(g.data).all() and np.abs(g.data).max() > 0

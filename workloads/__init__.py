@@ -232,6 +232,31 @@ def config5(with_data: bool = True, batch: int = 32) -> Workload:
                     '32 CMPs x 4096 traces in a 4 km disk, nt=2048, nq=128, ntheta=36')
 
 
+def table1(nt: int, nxy: int, np_: int, ntheta: int = 90, with_data: bool = True) -> Workload:
+    """Velocity-scan shape of the paper's timing table (Section 5): one CMP on a regular
+    nxy x nxy offset grid at 40 m, centred on zero offset, nt samples at 4 ms, np_ curvatures
+    uniform in [0.2^2, 0.7^2] s^2/km^2 (the slowness range is not stated; this one is the
+    other workloads'), ntheta azimuths.  Data: 8 anisotropic 25 Hz Ricker events without
+    noise (the timing of a linear operator does not depend on its input; band-limited data
+    make the difference between two discretisations of the adjoint meaningful)."""
+    ax = Axes(nt=nt, dt=0.004, ntau=nt, dtau=0.004, nq=np_, q_min=0.2 ** 2, q_max=0.7 ** 2,
+              ntheta=ntheta)
+    g1 = (np.arange(nxy) - (nxy - 1) / 2.0) * 0.040
+    X, Y = np.meshgrid(g1, g1, indexing='ij')
+    g = Gather(x=X.ravel().copy(), y=Y.ravel().copy())
+    if with_data:
+        rng = np.random.default_rng(np.random.SeedSequence([SEED_BASE, 4000 + nt + nxy + np_]))
+        T = (nt - 1) * ax.dt
+        g.events = _events(rng, 8, 0.1, 0.8 * T, 0.2, 0.7, 25.0, 25.0)
+        g.data = synth_data(ax, g.x, g.y, g.events, None, rng)
+    return Workload(f'table1_nt{nt}_grid{nxy}_np{np_}', ax, [g], 0,
+                    f'one CMP, {nxy}x{nxy} offsets at 40 m, nt={nt} at 4 ms, nq={np_}, ntheta={ntheta}')
+
+
+TABLE1_SHAPES = [(512, 128, 128), (512, 128, 256), (512, 256, 128), (512, 256, 256),
+                 (1024, 128, 128), (1024, 128, 256), (1024, 256, 128), (1024, 256, 256)]
+
+
 CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}
 
 
