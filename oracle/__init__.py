@@ -28,6 +28,10 @@ Parts
   (curvature-weighted mean of the Radon cube per intercept and azimuth).
 * ``deconv`` -- the deconvolutive AAHRT of Section 4: L_w = W L with W the
   convolution of every trace with the wavelet, and its transpose.
+* ``alg2`` -- Algorithm 2 of Section 3.2, the paper's fast velocity stack on a
+  regular offset grid, with the (x, y) bilinear interpolation of Section 3.4.
+  Not the transpose of L; pinned step by step and by the focusing of events at
+  their azimuth-dependent curvature.
 
 Pins: every function here is pinned by ``tests/test_oracle_pins.py`` against
 closed forms, invariants, brute force and special cases.  The difference
@@ -36,7 +40,7 @@ operator) is reported only: parity unpinned for that comparison, as the paper
 shows it only as a figure.
 """
 from .geometry import Geometry, nfft_rule, theta_weights, stretch_matrix, unstretch_matrix
-from . import gfst, timedomain, fista, velocity, deconv
+from . import gfst, timedomain, fista, velocity, deconv, alg2
 
 __all__ = ['Geometry', 'nfft_rule', 'theta_weights', 'stretch_matrix', 'unstretch_matrix',
-           'gfst', 'timedomain', 'fista', 'velocity', 'deconv']
+           'gfst', 'timedomain', 'fista', 'velocity', 'deconv', 'alg2']

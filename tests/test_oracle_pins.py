@@ -483,3 +483,102 @@ def test_deconv_correlation_is_the_transpose_and_operator_dot_test():
     lhs = np.sum(deconv.forward(m, g, w, c) * d)
     rhs = np.sum(m * deconv.adjoint(d, g, w, c))
     assert abs(lhs - rhs) < 1e-12 * max(1.0, abs(lhs))
+
+
+# ------------------------------------------------------------------ Algorithm 2 (Section 3.2)
+def _grid_gather(n=9, step=0.05, shuffle_seed=None):
+    g1 = (np.arange(n) - (n - 1) / 2.0) * step
+    X, Y = np.meshgrid(g1, g1, indexing='ij')
+    x, y = X.ravel(), Y.ravel()
+    if shuffle_seed is not None:
+        p = np.random.default_rng(shuffle_seed).permutation(x.size)
+        x, y = x[p], y[p]
+    return x, y
+
+
+def test_alg2_regular_grid_recovers_the_grid_and_rejects_others():
+    from oracle import alg2
+    x, y = _grid_gather(7, 0.04, shuffle_seed=1)
+    x0, dx, mx, y0, dy, my, node = alg2.regular_grid(x, y)
+    assert (mx, my) == (7, 7) and abs(dx - 0.04) < 1e-12 and abs(x0 + 0.12) < 1e-12 and abs(y0 + 0.12) < 1e-12
+    assert np.allclose(x0 + dx * node[:, 0], x) and np.allclose(y0 + dy * node[:, 1], y)
+    with pytest.raises(ValueError):
+        alg2.regular_grid(x[1:], y[1:])                     # one node missing
+    with pytest.raises(ValueError):
+        alg2.regular_grid(x * (1 + 0.1 * (x > 0)), y)      # uneven spacing
+
+
+def test_alg2_bilinear_reproduces_bilinear_functions():
+    """B1..B4 of Section 3.4 interpolate a + b x + c y + e x y exactly, return the node
+    values at nodes, and 0 outside the grid."""
+    from oracle import alg2
+    grid = (-0.375, 0.125, 7, -0.25, 0.0625, 9)            # binary-exact nodes
+    xs = grid[0] + grid[1] * np.arange(7)
+    ys = grid[3] + grid[4] * np.arange(9)
+    f = lambda x, y: 1.5 - 2.0 * x + 0.7 * y + 3.0 * x * y
+    dh = f(xs[:, None], ys[None, :])[:, :, None].astype(np.complex128) * (1 - 2j)
+    rng = np.random.default_rng(2)
+    for _ in range(50):
+        px, py = rng.uniform(xs[0], xs[-1]), rng.uniform(ys[0], ys[-1])
+        assert abs(alg2.bilinear(dh, grid, px, py)[0] - f(px, py) * (1 - 2j)) < 1e-12
+    assert abs(alg2.bilinear(dh, grid, xs[3], ys[4])[0] - dh[3, 4, 0]) < 1e-13
+    assert abs(alg2.bilinear(dh, grid, xs[-1], ys[-1])[0] - dh[-1, -1, 0]) < 1e-12   # last grid line
+    assert alg2.bilinear(dh, grid, xs[-1] + 1e-6, 0.0)[0] == 0
+    assert alg2.bilinear(dh, grid, 0.0, ys[0] - 1e-6)[0] == 0
+
+
+def test_alg2_stretch_steps_are_exact_on_linear_signals():
+    """Step 1 is exact on data linear in t, step 5 on a model linear in tau'."""
+    from oracle import alg2
+    w, g = _tiny(nt=40, ntr=3, nq=4, ntheta=2, dt=0.01)
+    t = np.arange(g.nt) * g.dt
+    d = np.stack([0.3 + 2.0 * t, -1.0 + 0.5 * t, np.ones_like(t)])
+    dp = alg2.stretch_data(d, g)
+    tr = np.sqrt(np.arange(g.nt_str) * g.dt_str)
+    ok = tr <= t[-1]
+    assert np.allclose(dp[0, ok], 0.3 + 2.0 * tr[ok], atol=1e-12)
+    assert np.allclose(dp[2, ok], 1.0, atol=1e-12)
+    tp = np.arange(g.nt_str) * g.dt_str
+    mp = np.stack([0.2 - 1.5 * tp, 4.0 + 0 * tp])
+    m = alg2.unstretch_model(mp, g)
+    tau = np.arange(g.ntau) * g.dtau
+    ok = tau ** 2 <= tp[-1]
+    assert np.allclose(m[0, ok], 0.2 - 1.5 * tau[ok] ** 2, atol=1e-12)
+    assert np.allclose(m[1, ok], 4.0, atol=1e-12)
+
+
+def test_alg2_inverse_2d_matches_numpy_ffts():
+    """Step 4 against numpy's inverse FFT over k (with the q_min shift) and an explicit
+    cosine/sine sum over f'."""
+    from oracle import alg2
+    w, g = _tiny(nt=24, ntr=3, nq=6, ntheta=2, dt=0.02, q_min=-0.1, q_max=0.4)
+    rng = np.random.default_rng(3)
+    mh = rng.standard_normal((2, 6, g.nf)) + 1j * rng.standard_normal((2, 6, g.nf))
+    k = alg2.k_axis(g)
+    assert np.allclose(np.sort(k * 6 * (g.q[1] - g.q[0])), np.arange(-3, 3))
+    G = np.fft.ifft(mh * np.exp(2j * np.pi * k * g.q_min)[None, :, None], axis=1)
+    r = np.arange(g.nt_str)
+    f = np.arange(1, g.nf)
+    ph = 2 * np.pi * np.outer(f, r) / g.nfft
+    ref = (G[..., :1].real + 2 * (np.einsum('jlf,fr->jlr', G[..., 1:].real, np.cos(ph))
+                                   - np.einsum('jlf,fr->jlr', G[..., 1:].imag, np.sin(ph)))) / g.nfft
+    assert np.allclose(alg2.inverse_2d(mh, g), ref, atol=1e-12)
+
+
+@pytest.mark.parametrize('Wq', [np.diag([0.25, 0.25]), np.diag([0.16, 0.36])])
+def test_alg2_focuses_an_event_at_its_curvature_per_azimuth(Wq):
+    """Physics pin: an event t^2 = tau0^2 + h^T W h on a dense regular grid stacks, at every
+    azimuth theta, at tau0 and at q(theta) = (cos, sin) W (cos, sin)^T within one q-sample."""
+    from oracle import alg2
+    ax = wl.Axes(nt=200, dt=0.004, ntau=200, dtau=0.004, nq=32, q_min=0.04, q_max=0.49, ntheta=6)
+    x, y = _grid_gather(21, 0.05)
+    g = Geometry.build(ax, x, y)
+    d = wl.synth_data(ax, x, y, [dict(tau0=0.4, W=Wq, amp=1.0, f0=30.0)], None, None)
+    M = alg2.adjoint(d, g)
+    dq = g.q[1] - g.q[0]
+    for j in range(ax.ntheta):
+        th = np.pi * j / ax.ntheta
+        c = np.array([np.cos(th), np.sin(th)])
+        l, i = np.unravel_index(np.argmax(np.abs(M[j])), M[j].shape)
+        assert abs(i * ax.dtau - 0.4) <= ax.dtau
+        assert abs(g.q[l] - c @ Wq @ c) <= dq
