@@ -265,6 +265,11 @@ def table1_scan(reps: int):
         prof = {k: round(ms / n, 4) for k, (ms, n) in plan.profile_read().items() if n}
         plan.profile(False)
         t_direct = _timed(lambda: plan.adjoint_direct(d, m_d), max(1, reps // 5))
+        m_a = torch.empty(plan.model_shape, dtype=torch.float32, device=dev)
+        t_grid = _timed(lambda: plan.adjoint_grid(d, m_a), reps)
+        # Algorithm 2 is not the transpose of L (its step 3 reads one offset per (f', k, theta),
+        # without the Jacobian of the polar change of variables): compared by correlation
+        corr = (torch.sum(m_a * m_g) / (torch.linalg.norm(m_a) * torch.linalg.norm(m_g))).item()
         diff = (torch.linalg.norm(m_g - m_d) / torch.linalg.norm(m_d)).item()
         # the t^2 stretch at twice nt samples undersamples the first few hundred ms (the
         # stretched spacing in t is dt'/2t), so the two discretisations part mostly there
@@ -275,6 +280,7 @@ def table1_scan(reps: int):
                'nt': nt, 'nx': nxy, 'ny': nxy, 'np': np_, 'ntheta': w.axes.ntheta, 'traces': plan.ntraces,
                'gfst_adjoint_s': round(t_gfst, 6), 'direct_adjoint_s': round(t_direct, 6),
                'speedup_direct_over_gfst': round(t_direct / t_gfst, 1),
+               'algorithm2_adjoint_s': round(t_grid, 6), 'algorithm2_corr_with_gfst_adjoint': round(corr, 4),
                'gfst_vs_direct_rel_diff': round(diff, 4), 'gfst_vs_direct_rel_diff_tau_ge_0.4s': round(diff_late, 4),
                'paper_direct_s': paper[0], 'paper_proposed_s': paper[1],
                'paper_speedup': round(paper[0] / paper[1], 1),
@@ -283,7 +289,7 @@ def table1_scan(reps: int):
                'kernel_width': plan.info['kernel_width'], 'dtype': 'f32', 'data': 'synthetic'}
         print(json.dumps(out), flush=True)
         plan.close()
-        del d, m_g, m_d
+        del d, m_g, m_d, m_a
         torch.cuda.empty_cache()
 
 

@@ -196,6 +196,24 @@ int aahrt_sparse_solve(aahrt_plan* plan, const float* d, float* m, const float* 
                        aahrt_stream stream);
 
 /*
+ * Algorithm 2 of Section 3.2, the paper's fast velocity stack, for gathers whose traces
+ * fill a regular offset grid x_m = x0 + m dx, y_n = y0 + n dy (each node once, any order):
+ *   1. stretch every trace by interpolation, D'(t') = D(t = sqrt(t'));
+ *   2. real DFT along t' (bins below N/2);
+ *   3. the model spectrum at (f', k_p, theta_j) is the data spectrum at the offset
+ *      x = sqrt(k_p/f') cos(theta_j), y = sqrt(k_p/f') sin(theta_j), interpolated with the
+ *      bilinear coefficients B1..B4 of Section 3.4 (0 for k_p < 0, f' = 0 or outside the grid);
+ *      k_p = p/(nq dq), p = -nq/2 .. nq/2-1;
+ *   4. inverse DFT along k (1/nq, onto q_l = q_min + l dq) and along f' (1/N, real);
+ *   5. unstretch by interpolation, M(tau_i) = M'(tau' = tau_i^2).
+ * Not the transpose of aahrt_forward (that is aahrt_adjoint): the paper's approximation, for
+ * comparison.  Layouts as aahrt_adjoint; m is overwritten.  Returns AAHRT_E_UNSUPPORTED when a
+ * gather is not a complete regular grid (a gather with no traces gives zeros), when nq has a
+ * prime factor above 5 or exceeds 3856, or when a wavelet is set.
+ */
+int aahrt_adjoint_grid(aahrt_plan* plan, const float* d, float* m, aahrt_stream stream);
+
+/*
  * Conventional time-domain adjoint (Section 5's direct summation, the method the
  * paper's timing table compares against): for every gather b, azimuth theta_j,
  * curvature q_l and intercept tau_i, the Riemann sum over the traces n of

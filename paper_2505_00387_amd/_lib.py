@@ -20,7 +20,7 @@ SOLVE_NO_GRAPH = 2
 EXPORTED = ['aahrt_version', 'aahrt_last_error', 'aahrt_plan_create', 'aahrt_plan_destroy',
             'aahrt_plan_query', 'aahrt_forward', 'aahrt_adjoint', 'aahrt_lambda_max',
             'aahrt_operator_norm2', 'aahrt_sparse_solve', 'aahrt_velocity', 'aahrt_set_wavelet',
-            'aahrt_adjoint_direct',
+            'aahrt_adjoint_direct', 'aahrt_adjoint_grid',
             'aahrt_profile_enable', 'aahrt_profile_read']
 
 KERNELS = ['model_r2c', 'nufft_interp', 'data_c2r', 'data_r2c', 'nufft_spread', 'model_c2r',
@@ -78,6 +78,7 @@ def load() -> ctypes.CDLL:
     lib.aahrt_velocity.argtypes = [P, P, P, P, P]
     lib.aahrt_set_wavelet.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32]
     lib.aahrt_adjoint_direct.argtypes = [P, P, P, P]
+    lib.aahrt_adjoint_grid.argtypes = [P, P, P, P]
     lib.aahrt_sparse_solve.argtypes = [P, P, P, P, P, ctypes.c_int32, ctypes.c_int32, P, P]
     lib.aahrt_profile_enable.argtypes = [P, ctypes.c_int32]
     lib.aahrt_profile_read.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),

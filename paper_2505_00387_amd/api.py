@@ -129,6 +129,16 @@ class Plan:
         check(self._lib.aahrt_adjoint_direct(self._h, d.data_ptr(), m.data_ptr(), _stream(stream)))
         return m
 
+    def adjoint_grid(self, d, m=None, stream=None):
+        """Algorithm 2 of Section 3.2 on regular offset grids (aahrt_adjoint_grid)."""
+        import torch
+        self._check(d, self.data_shape, 'd')
+        if m is None:
+            m = torch.empty(self.model_shape, dtype=torch.float32, device=d.device)
+        self._check(m, self.model_shape, 'm')
+        check(self._lib.aahrt_adjoint_grid(self._h, d.data_ptr(), m.data_ptr(), _stream(stream)))
+        return m
+
     def lambda_max(self, d, stream=None):
         import torch
         self._check(d, self.data_shape, 'd')

@@ -92,6 +92,27 @@ struct Dims {
   int nw, wc;   // wavelet of the deconvolutive operator: taps and origin (nw = 0: none)
 };
 
+// Algorithm 2 of Section 3.2 on a regular offset grid x_m = x0 + m dx, y_n = y0 + n dy.
+struct GridGather {
+  double x0, dx, y0, dy;
+  int mx, my;  // grid lines along x and y (0 for an empty gather)
+  int node0;   // first entry of the gather in the node table
+  int pad;
+};
+
+struct GridTables {
+  const Tap* dtap;      // [nt'] data stretch by interpolation: D'(r) = D(t = sqrt(r dt'))
+  const Tap* vtap;      // [ntau] model unstretch by interpolation: M(tau_i) = M'(tau' = tau_i^2)
+  const float* one;     // [1] = 1 (unit row scale of the data-side transform)
+  const float2* phase;  // [nq] exp(2 pi i k_p q_min) / nq
+  const float2* tw;     // [nq] exp(-2 pi i t / nq)
+  const double* kp;     // [nq] k_p = p / (nq dq), FFT order, signed
+  const double2* cs;    // [ntheta] (cos, sin) of theta_j
+  const GridGather* g;  // [batch]
+  const int* node;      // trace row of node (m, n): node[g.node0 + m * my + n]
+  double fscale;        // f' of bin f is f * fscale = f / (N dt')
+};
+
 struct Plan {
   Dims dm;
   aahrt_params prm;
@@ -143,6 +164,12 @@ struct Plan {
   hipGraph_t graph = nullptr;
   hipStream_t cap_stream = nullptr;
   std::string graph_key;
+  // Algorithm 2 on regular offset grids (aahrt_adjoint_grid)
+  bool grid_ok = false;
+  std::string grid_why;
+  GridTables gt{};
+  FftPlan fft_q{};  // nq complex
+  int grid_ft = 1;  // frequencies per workgroup of the polar interpolation
 };
 
 // LDS of the GFST kernels in float2 units (q-grid transforms run in place).
@@ -175,6 +202,7 @@ hipError_t launch_model_c2r_update(const Plan& p, float2* mhat, float* y, float*
                                    hipStream_t s);
 hipError_t launch_velocity(const Plan& p, const float* m, float* qbar, float* vel, hipStream_t s);
 hipError_t launch_direct_adjoint(const Plan& p, const float* d, float* m, hipStream_t s);
+hipError_t launch_grid_adjoint(const Plan& p, const float* d, float* m, hipStream_t s);
 hipError_t launch_fill(float* p, float v, size_t n, hipStream_t s);
 hipError_t launch_copy(float* dst, const float* src, size_t n, hipStream_t s);
 hipError_t launch_seed_vector(float* v, size_t n, unsigned seed, hipStream_t s);

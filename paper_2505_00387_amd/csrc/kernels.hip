@@ -946,6 +946,82 @@ __global__ __launch_bounds__(kBlock) void k_direct_adjoint(const float* __restri
   m[((size_t)bj * dm.nq + l) * dm.ntau + i] = acc;
 }
 
+// ------------------------------------------------------------------ Algorithm 2 (Section 3.2)
+// Step 3 and the k-half of step 4 on a regular offset grid.  Workgroup (f tile, j, b):
+// for every bin f of the tile and every k_p, the data spectrum is read at the offset
+//   x = sqrt(k_p / f') cos(theta_j),  y = sqrt(k_p / f') sin(theta_j)
+// by the bilinear coefficients B1..B4 of Section 3.4 (0 for k_p < 0, f = 0 or outside the
+// grid), times exp(2 pi i k_p q_min) / nq; an inverse DFT over k in LDS then gives the
+// q_l = q_min + l dq rows of the model spectrum.  Positions are computed in FP64.
+__global__ __launch_bounds__(kBlock) void k_grid_polar(const float2* __restrict__ dhat,
+                                                       float2* __restrict__ mhat, GridTables gt,
+                                                       Dims dm, FftPlan fq, int ft, int ftl) {
+  extern __shared__ float2 lds[];
+  const int nq = dm.nq;
+  const int ld = pad16(nq - 1) + 1;
+  float2* A = lds;
+  float2* B = lds + ft * ld;
+  const int f0 = blockIdx.x * ft;
+  const int j = blockIdx.y;
+  const int b = blockIdx.z;
+  const GridGather G = gt.g[b];
+  const double2 cs = gt.cs[j];
+  for (int it = threadIdx.x; it < nq * ft; it += kBlock) {
+    const int p = it >> ftl;
+    const int fl = it & (ft - 1);
+    const int f = f0 + fl;
+    float2 v = make_float2(0.f, 0.f);
+    const double kp = gt.kp[p];
+    if (f >= 1 && f < dm.nf && kp >= 0.0 && G.mx >= 2 && G.my >= 2) {
+      const double r = sqrt(kp / ((double)f * gt.fscale));
+      const double u = (r * cs.x - G.x0) / G.dx;
+      const double w = (r * cs.y - G.y0) / G.dy;
+      if (u >= 0.0 && u <= (double)(G.mx - 1) && w >= 0.0 && w <= (double)(G.my - 1)) {
+        const int m = min((int)u, G.mx - 2);
+        const int n = min((int)w, G.my - 2);
+        const float a = (float)(u - m);
+        const float c = (float)(w - n);
+        const int* nd = gt.node + G.node0 + m * G.my + n;
+        const float2 d00 = dhat[(size_t)nd[0] * dm.nf + f];
+        const float2 d01 = dhat[(size_t)nd[1] * dm.nf + f];
+        const float2 d10 = dhat[(size_t)nd[G.my] * dm.nf + f];
+        const float2 d11 = dhat[(size_t)nd[G.my + 1] * dm.nf + f];
+        const float b00 = (1.f - a) * (1.f - c), b01 = (1.f - a) * c, b10 = a * (1.f - c), b11 = a * c;
+        v.x = b00 * d00.x + b01 * d01.x + b10 * d10.x + b11 * d11.x;
+        v.y = b00 * d00.y + b01 * d01.y + b10 * d10.y + b11 * d11.y;
+        v = cmul(v, gt.phase[p]);
+      }
+    }
+    A[fl * ld + p] = v;
+  }
+  __syncthreads();
+  const float2* R = fft_lds<true, kBlock>(A, B, fq, ft, ld, gt.tw);
+  float2* out = mhat + ((size_t)b * dm.ntheta + j) * nq * dm.nf;
+  for (int it = threadIdx.x; it < nq * ft; it += kBlock) {
+    const int l = it >> ftl;
+    const int fl = it & (ft - 1);
+    const int f = f0 + fl;
+    if (f < dm.nf) out[(size_t)l * dm.nf + f] = R[fl * ld + l];
+  }
+}
+
+// The f'-half of step 4 (inverse real DFT, 1/N) and step 5, the unstretch by
+// interpolation M(tau_i) = M'(tau_i^2).
+template <bool IP>
+__global__ __launch_bounds__(kBlock) void k_model_c2r_grid(const float2* __restrict__ mhat,
+                                                           float* __restrict__ m, Tables tb, Dims dm,
+                                                           FftPlan fp, const Tap* __restrict__ vtap) {
+  extern __shared__ float2 lds[];
+  const size_t rid = blockIdx.x;
+  const float* xs = model_c2r_core<IP>(mhat, lds, lds + dm.nhp, tb, dm, fp, rid);
+  const float sc = 1.0f / (float)dm.nfft;
+  float* dst = m + rid * dm.ntau;
+  for (int i = threadIdx.x; i < dm.ntau; i += kBlock) {
+    const Tap t = vtap[i];
+    dst[i] = sc * (t.w0 * xs[t.i0] + t.w1 * xs[t.i1]);
+  }
+}
+
 // ------------------------------------------------------------------ launchers
 
 static size_t interp_lds_bytes(const Dims& dm) {
@@ -1177,6 +1253,34 @@ hipError_t launch_direct_adjoint(const Plan& p, const float* d, float* m, hipStr
   hipLaunchKernelGGL(k_direct_adjoint, grid, dim3(kBlock), 0, s, d, m, p.tb, dm, p.prm.dtau, p.prm.dt, p.prm.q_min,
                      dq);
   return hipGetLastError();
+}
+
+// Algorithm 2: steps 1-2 through the model-side row kernel (data rows of nt samples,
+// interpolation taps of the data stretch, unit scale), then the polar interpolation with
+// the k-transform, then the f'-transform with the unstretch.
+hipError_t launch_grid_adjoint(const Plan& p, const float* d, float* m, hipStream_t s) {
+  Dims dd = p.dm;
+  dd.ntau = p.dm.nt;
+  dd.nq = 1;
+  Tables td = p.tb;
+  td.s_tap = p.gt.dtap;
+  td.deapod = p.gt.one;
+  hipError_t e = launch_row(k_model_r2c<true>, k_model_r2c<false>, dd, dd.ntau, (unsigned)p.dm.ntr, s, d, p.dhat,
+                            td, dd, p.fft_half);
+  if (e != hipSuccess) return e;
+  const Dims& dm = p.dm;
+  const int ft = p.grid_ft;
+  int ftl = 0;
+  while ((1 << ftl) < ft) ++ftl;
+  const size_t lds = 2 * (size_t)ft * (pad16(dm.nq - 1) + 1) * sizeof(float2);
+  e = set_lds(k_grid_polar, lds);
+  if (e != hipSuccess) return e;
+  const dim3 grid((unsigned)((dm.nf + ft - 1) / ft), (unsigned)dm.ntheta, (unsigned)dm.batch);
+  hipLaunchKernelGGL(k_grid_polar, grid, dim3(kBlock), lds, s, p.dhat, p.mhat, p.gt, dm, p.fft_q, ft, ftl);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_row(k_model_c2r_grid<true>, k_model_c2r_grid<false>, dm, 0, model_rows(dm), s, p.mhat, m, p.tb,
+                    dm, p.fft_half, p.gt.vtap);
 }
 
 }  // namespace aahrt

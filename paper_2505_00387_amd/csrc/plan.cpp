@@ -456,6 +456,124 @@ int autotune_nufft(Plan& P, const std::vector<NufftChoice>& cands) {
   return AAHRT_OK;
 }
 
+// One axis of a regular offset grid: the distinct values (closer than 1e-9 km count as one)
+// must be v0 + i step, i = 0..count-1, to 1e-6 of the step.
+static bool grid_axis(const double* v, int64_t lo, int64_t hi, double& v0, double& step, int& count) {
+  std::vector<double> u(v + lo, v + hi);
+  std::sort(u.begin(), u.end());
+  std::vector<double> q;
+  for (double a : u)
+    if (q.empty() || a - q.back() > 1e-9) q.push_back(a);
+  if (q.size() < 2) return false;
+  step = (q.back() - q.front()) / (double)(q.size() - 1);
+  if (!(step > 0.0)) return false;
+  for (size_t i = 0; i < q.size(); ++i)
+    if (std::fabs(q[i] - (q.front() + step * (double)i)) > 1e-6 * step) return false;
+  v0 = q.front();
+  count = (int)q.size();
+  return true;
+}
+
+// Tables of Algorithm 2 (aahrt_adjoint_grid).  A plan whose gathers are not complete
+// regular grids, or whose nq has a prime factor above 5, records why and keeps going.
+int build_grid_tables(Plan& P, const int64_t* trace_ptr, const double* x, const double* y) {
+  const Dims& dm = P.dm;
+  const aahrt_params& prm = P.prm;
+  P.grid_ok = false;
+  if (!make_fft_plan(dm.nq, P.fft_q)) {
+    P.grid_why = "nq must have no prime factor above 5 for the grid adjoint";
+    return AAHRT_OK;
+  }
+  const int ld = (dm.nq - 1) + ((dm.nq - 1) >> 4) + 1;  // padded sequence stride of the LDS transform
+  int ft = 16;
+  while (ft > 1 && 2 * (size_t)ft * ld * sizeof(float2) > 65536) ft >>= 1;
+  if (2 * (size_t)ft * ld * sizeof(float2) > 65536) {
+    P.grid_why = "nq is too large for the grid adjoint";
+    return AAHRT_OK;
+  }
+  P.grid_ft = ft;
+  std::vector<GridGather> gg(dm.batch);
+  std::vector<int> node;
+  for (int b = 0; b < dm.batch; ++b) {
+    const int64_t lo = trace_ptr[b], hi = trace_ptr[b + 1];
+    GridGather G{0.0, 1.0, 0.0, 1.0, 0, 0, (int)node.size(), 0};
+    if (hi > lo) {
+      int mx = 0, my = 0;
+      if (!grid_axis(x, lo, hi, G.x0, G.dx, mx) || !grid_axis(y, lo, hi, G.y0, G.dy, my) ||
+          (int64_t)mx * my != hi - lo) {
+        P.grid_why = "gather " + std::to_string(b) + " is not a complete regular offset grid";
+        return AAHRT_OK;
+      }
+      G.mx = mx;
+      G.my = my;
+      node.resize(node.size() + (size_t)mx * my, -1);
+      for (int64_t n = lo; n < hi; ++n) {
+        const long m = std::lround((x[n] - G.x0) / G.dx);
+        const long k = std::lround((y[n] - G.y0) / G.dy);
+        const bool inside = m >= 0 && m < mx && k >= 0 && k < my;
+        if (!inside || node[G.node0 + (size_t)m * my + k] >= 0) {
+          P.grid_why = "gather " + std::to_string(b) + " does not fill its offset grid exactly once";
+          return AAHRT_OK;
+        }
+        node[G.node0 + (size_t)m * my + k] = (int)n;
+      }
+    }
+    gg[b] = G;
+  }
+  const double dts = P.dt_str;
+  std::vector<Tap> dtap(dm.nts), vtap(dm.ntau);
+  for (int r = 0; r < dm.nts; ++r) {
+    const double pos = std::sqrt(r * dts) / prm.dt;
+    const long i = (long)std::floor(pos);
+    const double a = pos - (double)i;
+    Tap t{0, 0, 0.f, 0.f};
+    if (i >= 0 && i < dm.nt) { t.i0 = (int)i; t.w0 = (float)(1.0 - a); }
+    if (i + 1 >= 0 && i + 1 < dm.nt) { t.i1 = (int)(i + 1); t.w1 = (float)a; }
+    dtap[r] = t;
+  }
+  for (int i = 0; i < dm.ntau; ++i) {
+    const double tau = i * prm.dtau;
+    const double pos = tau * tau / dts;
+    const long r = (long)std::floor(pos);
+    const double a = pos - (double)r;
+    Tap t{0, 0, 0.f, 0.f};
+    if (r >= 0 && r < dm.nts) { t.i0 = (int)r; t.w0 = (float)(1.0 - a); }
+    if (r + 1 >= 0 && r + 1 < dm.nts) { t.i1 = (int)(r + 1); t.w1 = (float)a; }
+    vtap[i] = t;
+  }
+  const double dq = (prm.q_max - prm.q_min) / (prm.nq - 1);
+  std::vector<double> kp(dm.nq);
+  std::vector<float2> phase(dm.nq), tw(dm.nq);
+  for (int p = 0; p < dm.nq; ++p) {
+    const int ps = p < (dm.nq + 1) / 2 ? p : p - dm.nq;
+    kp[p] = ps / (dm.nq * dq);
+    // exp(2 pi i k_p q_min) with the revolutions reduced in FP64
+    double rev = (double)ps * prm.q_min / (dm.nq * dq);
+    rev -= std::floor(rev);
+    phase[p] = make_float2((float)(std::cos(2.0 * M_PI * rev) / dm.nq), (float)(std::sin(2.0 * M_PI * rev) / dm.nq));
+    tw[p] = make_float2((float)std::cos(-2.0 * M_PI * p / dm.nq), (float)std::sin(-2.0 * M_PI * p / dm.nq));
+  }
+  std::vector<double2> cs(dm.ntheta);
+  for (int j = 0; j < dm.ntheta; ++j) {
+    const double th = M_PI * j / dm.ntheta;
+    cs[j] = make_double2(std::cos(th), std::sin(th));
+  }
+  const std::vector<float> one(1, 1.0f);
+  GridTables& gt = P.gt;
+  TRY(upload(P, dtap, &gt.dtap));
+  TRY(upload(P, vtap, &gt.vtap));
+  TRY(upload(P, one, &gt.one));
+  TRY(upload(P, phase, &gt.phase));
+  TRY(upload(P, tw, &gt.tw));
+  TRY(upload(P, kp, &gt.kp));
+  TRY(upload(P, cs, &gt.cs));
+  TRY(upload(P, gg, &gt.g));
+  TRY(upload(P, node, &gt.node));
+  gt.fscale = 1.0 / ((double)dm.nfft * dts);
+  P.grid_ok = true;
+  return AAHRT_OK;
+}
+
 int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* trace_ptr,
                const double* x, const double* y) {
   P.prm = prm;
@@ -650,6 +768,7 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
   TRY(alloc(P, (size_t)dm.ntr, &P.tr_bound));
   TRY(alloc(P, (size_t)batch * dm.ntheta, &P.slice_scale));
 
+  TRY(build_grid_tables(P, trace_ptr, x, y));
   TRY(set_nufft(P, cands[0]));
   if (cands.size() > 1) TRY(autotune_nufft(P, cands));
   return AAHRT_OK;
@@ -926,6 +1045,20 @@ int aahrt_adjoint_direct(aahrt_plan* plan, const float* d, float* m, aahrt_strea
   if ((long)P.dm.batch * P.dm.ntau == 0) return AAHRT_OK;
   HIP_TRY(hipSetDevice(P.device));
   HIP_TRY(launch_direct_adjoint(P, d, m, as_stream(stream)));
+  return AAHRT_OK;
+}
+
+int aahrt_adjoint_grid(aahrt_plan* plan, const float* d, float* m, aahrt_stream stream) {
+  TRY(check_plan(plan));
+  Plan& P = P_of(plan);
+  if (!m) return fail(AAHRT_E_INVALID, "m is NULL");
+  if (!d && P.dm.ntr > 0) return fail(AAHRT_E_INVALID, "d is NULL");
+  if (!P.grid_ok) return fail(AAHRT_E_UNSUPPORTED, P.grid_why);
+  if (P.dm.nw > 0) return fail(AAHRT_E_UNSUPPORTED, "the grid adjoint covers the plain operator (no wavelet)");
+  if (P.dm.batch > 65535 || P.dm.ntheta > 65535)
+    return fail(AAHRT_E_UNSUPPORTED, "batch and ntheta must each be at most 65535 for the grid adjoint");
+  HIP_TRY(hipSetDevice(P.device));
+  HIP_TRY(launch_grid_adjoint(P, d, m, as_stream(stream)));
   return AAHRT_OK;
 }
 

@@ -103,6 +103,7 @@ def test_null_arguments_are_rejected():
     assert lib.aahrt_set_wavelet(None, None, 0, 0) == -1
     assert lib.aahrt_velocity(None, None, None, None, None) == -1
     assert lib.aahrt_adjoint_direct(None, None, None, None) == -1
+    assert lib.aahrt_adjoint_grid(None, None, None, None) == -1
     assert lib.aahrt_plan_destroy(None) == 0
     assert lib.aahrt_plan_create(None, None, 1, None, None, None, 0) == -1
 

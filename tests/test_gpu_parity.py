@@ -606,3 +606,79 @@ def test_direct_adjoint_rejects_a_wavelet():
         plan.adjoint_direct(to_dev(wl.random_data(plan.ntraces, w.axes.nt, 0)))
     assert e.value.code == AAHRT_E_UNSUPPORTED
     plan.close()
+
+
+def _grid_parity(w, seed):
+    """Algorithm 2 (aahrt_adjoint_grid) against the oracle, gather by gather."""
+    from oracle import alg2
+    gs = geoms(w)
+    plan = make_plan(w)
+    d = wl.random_data(plan.ntraces, w.axes.nt, seed)
+    got = to_host(plan.adjoint_grid(to_dev(d)))
+    tp = w.trace_ptr
+    errs = []
+    for b, g in enumerate(gs):
+        if g.x.size == 0:
+            assert np.all(got[b] == 0)
+            continue
+        errs.append(rel(got[b], alg2.adjoint(d[tp[b]:tp[b + 1]], g)))
+    plan.close()
+    return errs
+
+
+def _grid(nx, ny, dx, dy, x0, y0, seed=None):
+    X, Y = np.meshgrid(x0 + dx * np.arange(nx), y0 + dy * np.arange(ny), indexing='ij')
+    x, y = X.ravel(), Y.ravel()
+    if seed is not None:
+        p = np.random.default_rng(seed).permutation(x.size)
+        x, y = x[p], y[p]
+    return wl.Gather(x=x, y=y)
+
+
+def test_grid_adjoint_parity_small():
+    ax = wl.Axes(nt=64, dt=0.008, ntau=64, dtau=0.008, nq=8, q_min=0.05, q_max=0.45, ntheta=5)
+    w = wl.Workload('grid9', ax, [_grid(9, 9, 0.05, 0.05, -0.2, -0.2, seed=1)], 0, 'grid')
+    for e in _grid_parity(w, seed=11):
+        print(f'grid adjoint {e:.2e}')
+        assert e < TOL
+
+
+def test_grid_adjoint_parity_batch_with_empty_and_shifted_grids():
+    """Three grids (one off-centre, one rectangular with unequal spacing), an empty gather,
+    nq = 12 (radices 4 and 3), ntau != nt."""
+    ax = wl.Axes(nt=90, dt=0.006, ntau=80, dtau=0.007, nq=12, q_min=0.04, q_max=0.49, ntheta=4)
+    gs = [_grid(12, 10, 0.06, 0.04, -0.33, -0.18, seed=2), wl.Gather(x=np.zeros(0), y=np.zeros(0)),
+          _grid(7, 7, 0.1, 0.1, 0.0, 0.0), _grid(5, 16, 0.08, 0.03, -0.16, -0.2, seed=3)]
+    errs = _grid_parity(wl.Workload('grids', ax, gs, 0, 'grids'), seed=12)
+    assert len(errs) == 3
+    for e in errs:
+        print(f'grid adjoint {e:.2e}')
+        assert e < TOL
+
+
+def test_grid_adjoint_parity_velocity_scan_shape():
+    """A reduced velocity-scan shape: 24 x 24 offsets at 40 m, 90 azimuths, nq = 16."""
+    w = wl.table1(nt=128, nxy=24, np_=16, with_data=False)
+    for e in _grid_parity(w, seed=13):
+        print(f'grid adjoint (24x24, 90 azimuths) {e:.2e}')
+        assert e < TOL
+
+
+def test_grid_adjoint_rejects_irregular_geometry_and_unsupported_nq():
+    from paper_2505_00387_amd._lib import AahrtError, AAHRT_E_UNSUPPORTED
+    for w in (wl.config1(with_data=False), wl.config3(with_data=False)):
+        plan = make_plan(w)
+        d = to_dev(wl.random_data(plan.ntraces, w.axes.nt, 0))
+        if w.gathers[0].x.size == 256:      # config1 is a 16 x 16 grid: accepted
+            plan.adjoint_grid(d)
+        else:
+            with pytest.raises(AahrtError) as e:
+                plan.adjoint_grid(d)
+            assert e.value.code == AAHRT_E_UNSUPPORTED
+        plan.close()
+    ax = wl.Axes(nt=32, dt=0.01, ntau=32, dtau=0.01, nq=7, q_min=0.05, q_max=0.4, ntheta=2)
+    plan = make_plan(wl.Workload('g', ax, [_grid(4, 4, 0.1, 0.1, 0.0, 0.0)], 0, 'g'))
+    with pytest.raises(AahrtError) as e:
+        plan.adjoint_grid(to_dev(wl.random_data(16, 32, 0)))
+    assert e.value.code == AAHRT_E_UNSUPPORTED
+    plan.close()
