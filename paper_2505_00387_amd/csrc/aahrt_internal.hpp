@@ -13,6 +13,7 @@ namespace aahrt {
 
 constexpr int kMaxPasses = 12;
 constexpr int kBlock = 256;     // threads per workgroup of the row kernels and small kernels
+constexpr int kPrefetch = 4;    // samples per thread a row kernel loads before its transform
 constexpr int kBlockG = 512;    // threads per workgroup of the GFST (nonuniform FFT) kernels
 constexpr int kPrefetchCells = 4 * 512;  // q-coefficients (nq * ft) a GFST workgroup holds in registers
 

@@ -226,6 +226,17 @@ __global__ __launch_bounds__(kBlock) void k_model_c2r_update(float2* __restrict_
   const int b = (int)(rid / ((size_t)dm.nq * dm.ntheta));
   float2* A = lds;
   float2* B = lds + dm.nhp;
+  float* yr = y + rid * dm.ntau;
+  float* xr = x + rid * dm.ntau;
+  // the first kPrefetch samples of this thread's y and x are loaded before the
+  // transform, so that their latency overlaps it
+  float yv[kPrefetch], xv[kPrefetch];
+#pragma unroll
+  for (int k = 0; k < kPrefetch; ++k) {
+    const int i = threadIdx.x + k * kBlock;
+    yv[k] = i < dm.ntau ? yr[i] : 0.f;
+    xv[k] = i < dm.ntau ? xr[i] : 0.f;
+  }
   const float* xs = model_c2r_core<IP>(mhat, A, B, tb, dm, fp, rid);
   // the new y row is staged after A (in place) or in the buffer not holding xs
   float* stage = IP ? reinterpret_cast<float*>(B)
@@ -233,20 +244,23 @@ __global__ __launch_bounds__(kBlock) void k_model_c2r_update(float2* __restrict_
   const float sc = tb.deapod[l] / (float)dm.nfft;
   const float g = gam[b];
   const float thr = g * lam[b];
-  float* yr = y + rid * dm.ntau;
-  float* xr = x + rid * dm.ntau;
   float s1 = 0.f;
-  for (int i = threadIdx.x; i < dm.ntau; i += kBlock) {
-    const float v = yr[i] + g * (sc * lerp_transpose(i, tb.s_start, tb.s_w, xs));
+  auto step = [&](int i, float yo, float xo) {
+    const float v = yo + g * (sc * lerp_transpose(i, tb.s_start, tb.s_w, xs));
     const float a = fabsf(v) - thr;
     const float xn = a > 0.f ? copysignf(a, v) : 0.f;
-    const float xo = xr[i];
     const float yn = ista ? xn : xn + beta * (xn - xo);
     yr[i] = yn;
     xr[i] = xn;
     if (NEXT) stage[i] = yn;
     s1 += fabsf(xn);
+  };
+#pragma unroll
+  for (int k = 0; k < kPrefetch; ++k) {
+    const int i = threadIdx.x + k * kBlock;
+    if (i < dm.ntau) step(i, yv[k], xv[k]);
   }
+  for (int i = threadIdx.x + kPrefetch * kBlock; i < dm.ntau; i += kBlock) step(i, yr[i], xr[i]);
   if (l1) {
     const float t = block_sum<kBlock>(s1, red);
     if (threadIdx.x == 0) l1[rid] = t;
@@ -357,6 +371,13 @@ __global__ __launch_bounds__(kBlock) void k_residual_r2c(float2* __restrict__ dh
   float2* A = lds;
   float2* B = lds + dm.nhp;
   const size_t n = blockIdx.x;
+  const float* ob = dobs + n * dm.nt;
+  float ov[kPrefetch];  // observed samples loaded before the transform
+#pragma unroll
+  for (int k = 0; k < kPrefetch; ++k) {
+    const int s = threadIdx.x + k * kBlock;
+    ov[k] = (!WAV && s < dm.nt) ? ob[s] : 0.f;
+  }
   load_packed_c2r(A, dhat + n * dm.nf, tb, dm);
   __syncthreads();
   float2* X = row_fft<true, IP>(A, B, fp, tb, dm);
@@ -364,17 +385,21 @@ __global__ __launch_bounds__(kBlock) void k_residual_r2c(float2* __restrict__ dh
   const float* xs = reinterpret_cast<const float*>(X);
   float* g = reinterpret_cast<float*>(Y);
   const float invN = 1.0f / (float)dm.nfft;
-  const float* ob = dobs + n * dm.nt;
   float ss = 0.f;
   if (!WAV) {
-#pragma unroll 4
-    for (int s = threadIdx.x; s < dm.nt; s += kBlock) {
+    auto res = [&](int s, float o) {
       const Tap t = tb.u_tap[s];
       const float v = invN * (t.w0 * xs[t.i0] + t.w1 * xs[t.i1]);
-      const float r = ob[s] - v;
+      const float r = o - v;
       g[s] = r;
       ss += r * r;
+    };
+#pragma unroll
+    for (int k = 0; k < kPrefetch; ++k) {
+      const int s = threadIdx.x + k * kBlock;
+      if (s < dm.nt) res(s, ov[k]);
     }
+    for (int s = threadIdx.x + kPrefetch * kBlock; s < dm.nt; s += kBlock) res(s, ob[s]);
   } else {
     // v = S^-1 F1^-1 Dh into g; r = d_obs - W v into X (its spectrum is consumed); g = W^T r
     for (int s = threadIdx.x; s < dm.nt; s += kBlock) {
