@@ -203,7 +203,7 @@ int aahrt_sparse_solve(aahrt_plan* plan, const float* d, float* m, const float* 
  *   3. the model spectrum at (f', k_p, theta_j) is the data spectrum at the offset
  *      x = sqrt(k_p/f') cos(theta_j), y = sqrt(k_p/f') sin(theta_j), interpolated with the
  *      bilinear coefficients B1..B4 of Section 3.4 (0 for k_p < 0, f' = 0 or outside the grid);
- *      k_p = p/(nq dq), p = -nq/2 .. nq/2-1;
+ *      k_p = p/(nq dq), p = -nq/2 .. nq/2-1 (odd nq: -(nq-1)/2 .. (nq-1)/2);
  *   4. inverse DFT along k (1/nq, onto q_l = q_min + l dq) and along f' (1/N, real);
  *   5. unstretch by interpolation, M(tau_i) = M'(tau' = tau_i^2).
  * Not the transpose of aahrt_forward (that is aahrt_adjoint): the paper's approximation, for
