@@ -44,6 +44,17 @@ def test_operator_parity_small(nq, ntheta, ntr, nt):
         assert ef < TOL and ea < TOL
 
 
+@pytest.mark.parametrize('nt,ntau,nq,ntheta,ntr', [(2, 1, 2, 1, 1), (3, 2, 2, 2, 1), (8, 3, 3, 1, 2),
+                                                    (5, 7, 2, 3, 3)])
+def test_operator_parity_minimal_sizes(nt, ntau, nq, ntheta, ntr):
+    """The smallest axes the plan accepts (nt = 2, ntau = 1, nq = 2, ntheta = 1, one trace)."""
+    w = wl.small_case(nt=nt, ntr=ntr, nq=nq, ntheta=ntheta, seed=nt * 10 + ntau, dt=0.02, ntau=ntau,
+                      dtau=0.015, radius=0.1)
+    for ef, ea in _op_parity(w, seed=5):
+        print(f'minimal {nt},{ntau},{nq},{ntheta},{ntr}: forward {ef:.2e} adjoint {ea:.2e}')
+        assert ef < TOL and ea < TOL
+
+
 def test_operator_parity_config1():
     for ef, ea in _op_parity(wl.config1(with_data=False), seed=1):
         print(f'config1 forward {ef:.2e} adjoint {ea:.2e}')
