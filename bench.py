@@ -112,6 +112,23 @@ def cpu_baseline(w, sample_gather: int):
                       f'scaled to {w.n_iter} iterations + lambda rule per gather'}
 
 
+def cpu_baseline_pair(w):
+    """FP64 oracle, one forward + adjoint pair on gather 0, one core."""
+    import workloads as wl
+    from oracle import gfst
+    from oracle.geometry import Geometry
+    from threadpoolctl import threadpool_limits
+    g0 = w.gathers[0]
+    geo = Geometry.build(w.axes, g0.x, g0.y)
+    mo = wl.random_model(w.axes, 1, 0)[0]
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        gfst.adjoint(gfst.forward(mo, geo), geo)
+        t = time.perf_counter() - t0
+    return {'pair_s': round(t, 2), 'pairs_per_s': round(1.0 / t, 4), 'cores': 1, 'kind': 'oracle',
+            'sample': f'one L + L^T pair on gather 0 ({g0.x.size} traces), FP64 NumPy, 1 thread'}
+
+
 class PlainOperator:
     """Plain per-gather FP32 operator on the GPU with torch ops, for the speed-up comparison.
 
@@ -293,6 +310,53 @@ def table1_scan(reps: int):
         torch.cuda.empty_cache()
 
 
+def configs_scan(pairs: int, oracle: bool):
+    """Forward + adjoint pairs on the other workloads (single CMP, realistic CMP, 8-CMP batch,
+    32-CMP large batch with each q-grid storage type): pair time, algorithmic GB/s, per-kernel
+    times, the plain per-gather FP32 operator and, for the single and realistic CMP, the FP64
+    oracle's pair on one core.  One JSON line per (workload, storage)."""
+    import numpy as np
+    import torch
+    import workloads as wl
+    from paper_2505_00387_amd import plan_from_workload
+    dev = torch.device('cuda:0')
+    for c in (1, 2, 3, 5):
+        w = wl.CONFIGS[c](with_data=False)
+        a = w.axes
+        for gd in ((0, 1, 2) if c == 5 else (0,)):
+            plan = plan_from_workload(w, device=0, grid_dtype=gd)
+            m = torch.randn(plan.model_shape, dtype=torch.float32, device=dev)
+            dd = torch.empty(plan.data_shape, dtype=torch.float32, device=dev)
+            ma = torch.empty(plan.model_shape, dtype=torch.float32, device=dev)
+
+            def pair():
+                plan.forward(m, dd)
+                plan.adjoint(dd, ma)
+            t_pair = _timed(pair, pairs)
+            plan.profile(True)
+            pair()
+            torch.cuda.synchronize()
+            prof = {k: round(ms / n, 4) for k, (ms, n) in plan.profile_read().items() if n}
+            plan.profile(False)
+            nf = plan.info['nfreq']
+            rows = w.batch * a.ntheta * a.nq
+            bop = 4 * rows * a.ntau + 16 * rows * nf + 16 * plan.ntraces * nf + 4 * plan.ntraces * a.nt
+            out = {'metric': 'fwd+adj pair', 'workload': w.name, 'gathers': w.batch, 'traces': plan.ntraces,
+                   'grid_dtype': ('f32', 'f16', 'bf16')[gd], 'pair_ms': round(1e3 * t_pair, 4),
+                   'pairs_per_s': round(w.batch / t_pair, 1), 'alg_GBs': round(2 * bop / t_pair / 1e9, 1),
+                   'hbm_frac': round(2 * bop / t_pair / 1e9 / HBM_PEAK_GBS, 4), 'kernel_ms': prof,
+                   'nfft': plan.info['nfft'], 'grid': plan.info['grid_size'],
+                   'kernel_width': plan.info['kernel_width'], 'freq_tile': plan.info['freq_tile']}
+            if gd == 0 and c in (1, 2, 3):
+                out['plain_per_gather_fp32'] = plain_comparison(w, plan, t_pair, min(w.batch, 16), dev)
+            if gd == 0 and c in (1, 2) and oracle:
+                out['cpu_baseline'] = cpu_baseline_pair(w)
+            print(json.dumps(out), flush=True)
+            plan.close()
+            del m, dd, ma
+            torch.cuda.empty_cache()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument('--gpus', type=int, default=1)
@@ -302,6 +366,8 @@ def main():
     ap.add_argument('--no-cpu', action='store_true', help='skip the oracle CPU-baseline leg')
     ap.add_argument('--pairs', type=int, default=5, help='timed fwd+adj pairs')
     ap.add_argument('--plain-sample', type=int, default=16, help='gathers of the plain-operator comparison (0: skip)')
+    ap.add_argument('--configs', action='store_true',
+                    help='instead of the solve: fwd+adj pairs on the other workloads')
     ap.add_argument('--table1', action='store_true',
                     help='instead of the solve: the velocity-scan timing at the paper\'s table shapes')
     args = ap.parse_args()
@@ -318,6 +384,9 @@ def main():
     assert torch.cuda.is_available(), 'bench.py needs a GPU'
     if args.table1:
         table1_scan(max(args.steps, 5))
+        return
+    if args.configs:
+        configs_scan(max(args.pairs, 5), not args.no_cpu)
         return
     dev = torch.device('cuda:0')
     t0 = time.perf_counter()

@@ -35,6 +35,10 @@ struct FftPlan {
   FftPass pass[kMaxPasses];
 };
 
+// Butterflies of one in-place row-transform pass a thread may hold in registers
+// (passes with more butterflies than threads), by radix.
+__host__ __device__ constexpr int row_kmax(int r) { return r >= 15 ? 2 : (r == 5 ? 5 : 3); }
+
 // Two-tap linear interpolation entry: value = w0 * x[i0] + w1 * x[i1] (dropped taps have weight 0).
 struct __attribute__((aligned(16))) Tap {
   int i0, i1;
@@ -80,7 +84,7 @@ struct Dims {
   int nts;      // nt'
   int nfft, nh, nf;  // N, N/2, bins carried (= N/2)
   int nhp;      // LDS cells of one row FFT buffer: room for the padded first pass
-  int row_ip;   // 1: every pass of the row FFT has at most kBlock butterflies (in-place row kernels)
+  int row_ip;   // row FFT in place: 1 = one butterfly per thread per pass, 2 = up to row_kmax; 0 = ping-pong
   int mg;       // q-grid length
   int ldr;      // LDS row length of a q-grid slot: mg + w - 1 ghost cells, padded to odd
   int w;        // kernel width

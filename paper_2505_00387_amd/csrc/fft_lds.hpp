@@ -382,4 +382,97 @@ __device__ __forceinline__ void fft_lds_ip(float2* buf, const FftPlan& pl, int n
   }
 }
 
+// In-place pass of one sequence in which a thread owns K butterflies (j = thread + k NT).
+// Level k reads and transforms butterfly k into registers of its own, then the next level
+// runs; the innermost level synchronises the block, and each level writes on the way back.
+template <int R, bool INV, int NT, bool PIN, bool POUT, int KK, int K>
+__device__ __forceinline__ void fft_pass_ipk_level(float2* buf, const FftPass& ps, const float2* __restrict__ tw) {
+  float2 v[R];
+  const int j = threadIdx.x + KK * NT;
+  const bool act = j < ps.nb;
+  int o = 0;
+  if (act) {
+    const int jq = (int)fdiv((unsigned)j, ps.dns);
+    const int k = j - jq * ps.ns;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = j + r * ps.nb;
+      v[r] = buf[PIN ? pad16(i) : i];
+    }
+    if (ps.ns > 1) apply_twiddles<R, INV>(v, tw, k * ps.stride);
+    Dft<R, INV>::run(v);
+    o = jq * ps.ns * R + k;
+  }
+  if constexpr (KK + 1 < K) fft_pass_ipk_level<R, INV, NT, PIN, POUT, KK + 1, K>(buf, ps, tw);
+  else __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = o + r * ps.ns;
+      buf[POUT ? pad16(i) : i] = v[r];
+    }
+  }
+}
+
+template <int R, bool INV, int NT, bool PIN, bool POUT, int K>
+__device__ __forceinline__ void fft_pass_ipk(float2* buf, const FftPass& ps, const float2* __restrict__ tw) {
+  fft_pass_ipk_level<R, INV, NT, PIN, POUT, 0, K>(buf, ps, tw);
+  __syncthreads();
+}
+
+template <int R, bool INV, int NT, bool PIN, bool POUT>
+__device__ __forceinline__ void fft_pass_ipk_k(float2* buf, const FftPass& ps, const float2* tw) {
+  const int K = (ps.nb + NT - 1) / NT;  // at most row_kmax(R), by the plan
+  if (K <= 1) {
+    fft_pass_ip<R, INV, NT, PIN, POUT>(buf, ps, 1, 0, tw);
+    return;
+  }
+  if constexpr (row_kmax(R) >= 2) {
+    if (K == 2) {
+      fft_pass_ipk<R, INV, NT, PIN, POUT, 2>(buf, ps, tw);
+      return;
+    }
+  }
+  if constexpr (row_kmax(R) >= 3) {
+    if (K == 3) {
+      fft_pass_ipk<R, INV, NT, PIN, POUT, 3>(buf, ps, tw);
+      return;
+    }
+  }
+  if constexpr (row_kmax(R) >= 4) {
+    if (K == 4) {
+      fft_pass_ipk<R, INV, NT, PIN, POUT, 4>(buf, ps, tw);
+      return;
+    }
+  }
+  if constexpr (row_kmax(R) >= 5) fft_pass_ipk<R, INV, NT, PIN, POUT, 5>(buf, ps, tw);
+}
+
+template <int R, bool INV, int NT>
+__device__ __forceinline__ void fft_pass_ipk_sel(float2* buf, const FftPass& ps, const float2* tw, int mode) {
+  if (mode == 1) fft_pass_ipk_k<R, INV, NT, false, true>(buf, ps, tw);
+  else if (mode == 2) fft_pass_ipk_k<R, INV, NT, true, false>(buf, ps, tw);
+  else fft_pass_ipk_k<R, INV, NT, false, false>(buf, ps, tw);
+}
+
+// In-place transform of one sequence whose passes may have more butterflies than
+// threads, up to row_kmax(radix) per thread (the plan guarantees it).
+template <bool INV, int NT>
+__device__ __forceinline__ void fft_lds_ipk(float2* buf, const FftPlan& pl, const float2* __restrict__ tw) {
+  for (int s = 0; s < pl.npass; ++s) {
+    const FftPass ps = pl.pass[s];  // by value: keeps the plan argument out of private memory
+    const int mode = pl.npass < 2 ? 0 : (s == 0 ? 1 : (s == 1 ? 2 : 0));
+    switch (ps.r) {
+      case 2: fft_pass_ipk_sel<2, INV, NT>(buf, ps, tw, mode); break;
+      case 3: fft_pass_ipk_sel<3, INV, NT>(buf, ps, tw, mode); break;
+      case 4: fft_pass_ipk_sel<4, INV, NT>(buf, ps, tw, mode); break;
+      case 5: fft_pass_ipk_sel<5, INV, NT>(buf, ps, tw, mode); break;
+      case 8: fft_pass_ipk_sel<8, INV, NT>(buf, ps, tw, mode); break;
+      case 9: fft_pass_ipk_sel<9, INV, NT>(buf, ps, tw, mode); break;
+      case 15: fft_pass_ipk_sel<15, INV, NT>(buf, ps, tw, mode); break;
+      default: fft_pass_ipk_sel<16, INV, NT>(buf, ps, tw, mode); break;
+    }
+  }
+}
+
 }  // namespace aahrt

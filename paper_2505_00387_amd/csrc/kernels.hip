@@ -128,11 +128,14 @@ __device__ __forceinline__ void pack_transpose(float2* buf, const float* g, cons
 // staging area after it for a real input row; IP = false (long rows whose FFT
 // passes have more butterflies than threads): two ping-pong buffers, the staged
 // input row aliasing the second one before the first pass.
-template <bool INV, bool IP>
+template <bool INV, int IP>
 __device__ __forceinline__ float2* row_fft(float2* A, float2* B, const FftPlan& fp, const Tables& tb,
                                            const Dims& dm) {
-  if (IP) {
+  if constexpr (IP == 1) {
     fft_lds_ip<INV, kBlock>(A, fp, 1, 0, tb.tw_half);
+    return A;
+  } else if constexpr (IP == 2) {
+    fft_lds_ipk<INV, kBlock>(A, fp, tb.tw_half);
     return A;
   }
   return fft_lds<INV, kBlock>(A, B, fp, 1, dm.nh, tb.tw_half);
@@ -160,7 +163,7 @@ __device__ __forceinline__ void stretch_pack(float2* A, const float* row, float 
 
 // Steps 1-2 of L: M'(tau') = S M, times the deapodisation of its curvature
 // index, real DFT of length N, bins 0..N/2-1 stored as mhat[row][f].
-template <bool IP>
+template <int IP>
 __global__ __launch_bounds__(kBlock) void k_model_r2c(const float* __restrict__ m,
                                                       float2* __restrict__ mhat, Tables tb, Dims dm,
                                                       FftPlan fp) {
@@ -181,7 +184,7 @@ __global__ __launch_bounds__(kBlock) void k_model_r2c(const float* __restrict__ 
 
 // Transpose of steps 1-2: inverse real DFT (1/N, doubled positive bins), first
 // nt' samples, times the deapodisation, then S^T.
-template <bool IP>
+template <int IP>
 __device__ __forceinline__ const float* model_c2r_core(const float2* mhat, float2* A,
                                                        float2* B, const Tables& tb, const Dims& dm,
                                                        const FftPlan& fp, size_t rid) {
@@ -190,7 +193,7 @@ __device__ __forceinline__ const float* model_c2r_core(const float2* mhat, float
   return reinterpret_cast<const float*>(row_fft<true, IP>(A, B, fp, tb, dm));
 }
 
-template <bool IP>
+template <int IP>
 __global__ __launch_bounds__(kBlock) void k_model_c2r(const float2* __restrict__ mhat,
                                                       float* __restrict__ m, Tables tb, Dims dm,
                                                       FftPlan fp) {
@@ -210,7 +213,7 @@ __global__ __launch_bounds__(kBlock) void k_model_c2r(const float2* __restrict__
 // (ISTA: y <- x_new).  l1[row] receives sum |x_new| when l1 is not null.  NEXT: the
 // row then goes on through steps 1-2 of L for the next iteration, S y_new -> R2C,
 // written over its own spectrum row (each row is read and written by one block).
-template <bool IP, bool NEXT>
+template <int IP, bool NEXT>
 __global__ __launch_bounds__(kBlock) void k_model_c2r_update(float2* __restrict__ mhat,
                                                              float* __restrict__ y,
                                                              float* __restrict__ x, Tables tb,
@@ -297,7 +300,7 @@ __device__ __forceinline__ float wav_corr(const float* r, int s, const Tables& t
 }
 
 // Steps 4-5 of L: inverse real DFT of Dh[n][0..N/2-1], unstretch (then W).
-template <bool IP, bool WAV>
+template <int IP, bool WAV>
 __global__ __launch_bounds__(kBlock) void k_data_c2r(const float2* __restrict__ dhat,
                                                      float* __restrict__ d, Tables tb, Dims dm,
                                                      FftPlan fp) {
@@ -330,7 +333,7 @@ __global__ __launch_bounds__(kBlock) void k_data_c2r(const float2* __restrict__ 
 
 // (W^T, then) transpose of step 5, then the forward real DFT (the data side of L^T).
 // tr_bound[n] = max_f (|Re Dh[n,f]| + |Im Dh[n,f]|) (the spreading scale bound).
-template <bool IP, bool WAV>
+template <int IP, bool WAV>
 __global__ __launch_bounds__(kBlock) void k_data_r2c(const float* __restrict__ d,
                                                      float2* __restrict__ dhat,
                                                      float* __restrict__ tr_bound, Tables tb, Dims dm,
@@ -360,7 +363,7 @@ __global__ __launch_bounds__(kBlock) void k_data_r2c(const float* __restrict__ d
 
 // Solver data side, in place on dhat[n]: r = d_obs - (W) S^-1 F1^-1 Dh (steps 4-5),
 // then the data side of L^T applied to r.  rss[n] = sum r^2 when not null.
-template <bool IP, bool WAV>
+template <int IP, bool WAV>
 __global__ __launch_bounds__(kBlock) void k_residual_r2c(float2* __restrict__ dhat,
                                                          const float* __restrict__ dobs,
                                                          float* __restrict__ rss,
@@ -1032,7 +1035,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_polar(const float2* __restrict_
 
 // The f'-half of step 4 (inverse real DFT, 1/N) and step 5, the unstretch by
 // interpolation M(tau_i) = M'(tau_i^2).
-template <bool IP>
+template <int IP>
 __global__ __launch_bounds__(kBlock) void k_model_c2r_grid(const float2* __restrict__ mhat,
                                                            float* __restrict__ m, Tables tb, Dims dm,
                                                            FftPlan fp, const Tap* __restrict__ vtap) {
@@ -1069,15 +1072,21 @@ static hipError_t set_lds(K kernel, size_t bytes) {
 
 // Launch one row kernel: in place (every FFT pass fits the block) with `stage`
 // real samples of staging after the buffer, else the two-buffer form.
-template <typename KIP, typename KPP, typename... Args>
-static hipError_t launch_row(KIP kip, KPP kpp, const Dims& dm, int stage, unsigned grid, hipStream_t s,
+// kip: in place, one butterfly per thread per pass; kipk: in place, several; kpp: ping-pong.
+template <typename KIP, typename KIPK, typename KPP, typename... Args>
+static hipError_t launch_row(KIP kip, KIPK kipk, KPP kpp, const Dims& dm, int stage, unsigned grid, hipStream_t s,
                              Args... args) {
   if (grid == 0) return hipSuccess;
-  if (dm.row_ip) {
+  if (dm.row_ip == 1) {
     const size_t lds = ((size_t)dm.nhp + (size_t)(stage + 5) / 2) * sizeof(float2);  // staging + 4 spare
     hipError_t e = set_lds(kip, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kip, dim3(grid), dim3(kBlock), lds, s, args...);
+  } else if (dm.row_ip == 2) {
+    const size_t lds = ((size_t)dm.nhp + (size_t)(stage + 5) / 2) * sizeof(float2);
+    hipError_t e = set_lds(kipk, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kipk, dim3(grid), dim3(kBlock), lds, s, args...);
   } else {
     const size_t lds = 2 * (size_t)dm.nhp * sizeof(float2);
     hipError_t e = set_lds(kpp, lds);
@@ -1091,13 +1100,13 @@ static unsigned model_rows(const Dims& dm) { return (unsigned)((size_t)dm.batch 
 
 hipError_t launch_model_r2c(const Plan& p, const float* m, float2* mhat, hipStream_t s) {
   const Dims& dm = p.dm;
-  return launch_row(k_model_r2c<true>, k_model_r2c<false>, dm, dm.ntau, model_rows(dm), s, m, mhat, p.tb, dm,
+  return launch_row(k_model_r2c<1>, k_model_r2c<2>, k_model_r2c<0>, dm, dm.ntau, model_rows(dm), s, m, mhat, p.tb, dm,
                     p.fft_half);
 }
 
 hipError_t launch_model_c2r(const Plan& p, const float2* mhat, float* m, hipStream_t s) {
   const Dims& dm = p.dm;
-  return launch_row(k_model_c2r<true>, k_model_c2r<false>, dm, 0, model_rows(dm), s, mhat, m, p.tb, dm,
+  return launch_row(k_model_c2r<1>, k_model_c2r<2>, k_model_c2r<0>, dm, 0, model_rows(dm), s, mhat, m, p.tb, dm,
                     p.fft_half);
 }
 
@@ -1106,27 +1115,27 @@ hipError_t launch_model_c2r_update(const Plan& p, float2* mhat, float* y, float*
                                    hipStream_t s) {
   const Dims& dm = p.dm;
   if (next)
-    return launch_row(k_model_c2r_update<true, true>, k_model_c2r_update<false, true>, dm, dm.ntau,
+    return launch_row(k_model_c2r_update<1, true>, k_model_c2r_update<2, true>, k_model_c2r_update<0, true>, dm, dm.ntau,
                       model_rows(dm), s, mhat, y, x, p.tb, dm, p.fft_half, gam, lam, beta, ista, l1);
-  return launch_row(k_model_c2r_update<true, false>, k_model_c2r_update<false, false>, dm, 0, model_rows(dm), s,
+  return launch_row(k_model_c2r_update<1, false>, k_model_c2r_update<2, false>, k_model_c2r_update<0, false>, dm, 0, model_rows(dm), s,
                     mhat, y, x, p.tb, dm, p.fft_half, gam, lam, beta, ista, l1);
 }
 
 hipError_t launch_data_c2r(const Plan& p, const float2* dhat, float* d, hipStream_t s) {
   const Dims& dm = p.dm;
   if (dm.nw > 0)
-    return launch_row(k_data_c2r<true, true>, k_data_c2r<false, true>, dm, dm.nt, (unsigned)dm.ntr, s, dhat, d,
+    return launch_row(k_data_c2r<1, true>, k_data_c2r<2, true>, k_data_c2r<0, true>, dm, dm.nt, (unsigned)dm.ntr, s, dhat, d,
                       p.tb, dm, p.fft_half);
-  return launch_row(k_data_c2r<true, false>, k_data_c2r<false, false>, dm, 0, (unsigned)dm.ntr, s, dhat, d, p.tb,
+  return launch_row(k_data_c2r<1, false>, k_data_c2r<2, false>, k_data_c2r<0, false>, dm, 0, (unsigned)dm.ntr, s, dhat, d, p.tb,
                     dm, p.fft_half);
 }
 
 hipError_t launch_data_r2c(const Plan& p, const float* d, float2* dhat, hipStream_t s) {
   const Dims& dm = p.dm;
   if (dm.nw > 0)
-    return launch_row(k_data_r2c<true, true>, k_data_r2c<false, true>, dm, dm.nt, (unsigned)dm.ntr, s, d, dhat,
+    return launch_row(k_data_r2c<1, true>, k_data_r2c<2, true>, k_data_r2c<0, true>, dm, dm.nt, (unsigned)dm.ntr, s, d, dhat,
                       p.tr_bound, p.tb, dm, p.fft_half);
-  return launch_row(k_data_r2c<true, false>, k_data_r2c<false, false>, dm, dm.nt, (unsigned)dm.ntr, s, d, dhat,
+  return launch_row(k_data_r2c<1, false>, k_data_r2c<2, false>, k_data_r2c<0, false>, dm, dm.nt, (unsigned)dm.ntr, s, d, dhat,
                     p.tr_bound, p.tb, dm, p.fft_half);
 }
 
@@ -1134,9 +1143,9 @@ hipError_t launch_residual_r2c(const Plan& p, float2* dhat, const float* dobs, f
                                hipStream_t s) {
   const Dims& dm = p.dm;
   if (dm.nw > 0)
-    return launch_row(k_residual_r2c<true, true>, k_residual_r2c<false, true>, dm, dm.nt, (unsigned)dm.ntr, s,
+    return launch_row(k_residual_r2c<1, true>, k_residual_r2c<2, true>, k_residual_r2c<0, true>, dm, dm.nt, (unsigned)dm.ntr, s,
                       dhat, dobs, rss, p.tr_bound, p.tb, dm, p.fft_half);
-  return launch_row(k_residual_r2c<true, false>, k_residual_r2c<false, false>, dm, dm.nt, (unsigned)dm.ntr, s,
+  return launch_row(k_residual_r2c<1, false>, k_residual_r2c<2, false>, k_residual_r2c<0, false>, dm, dm.nt, (unsigned)dm.ntr, s,
                     dhat, dobs, rss, p.tr_bound, p.tb, dm, p.fft_half);
 }
 
@@ -1290,7 +1299,7 @@ hipError_t launch_grid_adjoint(const Plan& p, const float* d, float* m, hipStrea
   Tables td = p.tb;
   td.s_tap = p.gt.dtap;
   td.deapod = p.gt.one;
-  hipError_t e = launch_row(k_model_r2c<true>, k_model_r2c<false>, dd, dd.ntau, (unsigned)p.dm.ntr, s, d, p.dhat,
+  hipError_t e = launch_row(k_model_r2c<1>, k_model_r2c<2>, k_model_r2c<0>, dd, dd.ntau, (unsigned)p.dm.ntr, s, d, p.dhat,
                             td, dd, p.fft_half);
   if (e != hipSuccess) return e;
   const Dims& dm = p.dm;
@@ -1304,7 +1313,7 @@ hipError_t launch_grid_adjoint(const Plan& p, const float* d, float* m, hipStrea
   hipLaunchKernelGGL(k_grid_polar, grid, dim3(kBlock), lds, s, p.dhat, p.mhat, p.gt, dm, p.fft_q, ft, ftl);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return launch_row(k_model_c2r_grid<true>, k_model_c2r_grid<false>, dm, 0, model_rows(dm), s, p.mhat, m, p.tb,
+  return launch_row(k_model_c2r_grid<1>, k_model_c2r_grid<2>, k_model_c2r_grid<0>, dm, 0, model_rows(dm), s, p.mhat, m, p.tb,
                     dm, p.fft_half, p.gt.vtap);
 }
 

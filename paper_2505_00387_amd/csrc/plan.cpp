@@ -199,6 +199,49 @@ bool make_grid_fft_plan(int n, FftPlan& pl) {
   return true;
 }
 
+// Row transforms run in place when every pass fits the threads of a row workgroup:
+// 1 = one butterfly per thread, 2 = up to row_kmax(radix) per thread, 0 = ping-pong.
+int row_plan_kind(const FftPlan& pl) {
+  int kind = 1;
+  for (int i = 0; i < pl.npass; ++i) {
+    const int k = (pl.pass[i].nb + kBlock - 1) / kBlock;
+    if (k > row_kmax(pl.pass[i].r)) return 0;
+    if (k > 1) kind = 2;
+  }
+  return kind;
+}
+
+// A radix order for a long row transform that runs in place: the fewest passes, then the
+// fewest butterflies per thread in the busiest pass.  False if there is none.
+bool make_row_fft_plan(int n, FftPlan& pl) {
+  std::vector<int> best, cur;
+  int best_np = kMaxPasses + 1, best_k = 1 << 30;
+  const int radices[] = {16, 15, 9, 8, 5, 4, 3, 2};
+  std::function<void(int)> search = [&](int m) {
+    if ((int)cur.size() >= best_np && m > 1) return;
+    if (m == 1) {
+      int kmax = 0;
+      for (int r : cur) kmax = std::max(kmax, (n / r + kBlock - 1) / kBlock);
+      if ((int)cur.size() < best_np || kmax < best_k) {
+        best_np = (int)cur.size();
+        best_k = kmax;
+        best = cur;
+      }
+      return;
+    }
+    for (int r : radices)
+      if (m % r == 0 && (n / r + kBlock - 1) / kBlock <= row_kmax(r)) {
+        cur.push_back(r);
+        search(m / r);
+        cur.pop_back();
+      }
+  };
+  search(n);
+  if (best.empty()) return false;
+  fill_fft_plan(n, best, pl);
+  return true;
+}
+
 template <typename T>
 int upload(Plan& p, const std::vector<T>& h, const T** out) {
   void* d = nullptr;
@@ -611,9 +654,18 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
   dm.nhp = (dm.nh - 1) + ((dm.nh - 1) >> 4) + 1;
   if (!make_fft_plan(dm.nh, P.fft_half))
     return fail(AAHRT_E_UNSUPPORTED, "FFT length N/2 = " + std::to_string(dm.nh) + " exceeds the LDS FFT limits");
-  dm.row_ip = 1;
-  for (int i = 0; i < P.fft_half.npass; ++i)
-    if (P.fft_half.pass[i].nb > kBlock) dm.row_ip = 0;
+  // Rows whose passes exceed the threads stay ping-pong while its two buffers leave room
+  // for four or more workgroups per CU; longer rows run in place with several butterflies
+  // per thread (half the LDS), which measured faster there.
+  dm.row_ip = row_plan_kind(P.fft_half);
+  if (dm.row_ip != 1) {
+    dm.row_ip = 0;
+    FftPlan alt;
+    if (2 * (size_t)dm.nhp * sizeof(float2) > 32 * 1024 && make_row_fft_plan(dm.nh, alt)) {
+      P.fft_half = alt;
+      dm.row_ip = row_plan_kind(alt);
+    }
+  }
 
   // nonuniform FFT parameters: the candidate (sigma, w, ft) list; the first one
   // is built now, the others are timed by the autotuner once the plan is complete

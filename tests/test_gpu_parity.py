@@ -55,6 +55,30 @@ def test_operator_parity_minimal_sizes(nt, ntau, nq, ntheta, ntr):
         assert ef < TOL and ea < TOL
 
 
+@pytest.mark.parametrize('nfft', [2880, 5184, 7290, 12000])
+def test_long_rows_in_place_parity(nfft):
+    """Row transforms whose passes have more butterflies than threads: N/2 = 1440 in the
+    two-buffer form, N/2 = 2592, 3645 and 6000 in place with several butterflies per thread.
+    L, L^T and 5 FISTA iterations against the oracle at that FFT length."""
+    from oracle.geometry import Geometry
+    w = wl.small_case(nt=64, ntr=24, nq=6, ntheta=3, seed=nfft % 97, dt=0.01)
+    g0 = w.gathers[0]
+    g = Geometry.build(w.axes, g0.x, g0.y, nfft=nfft)
+    plan = make_plan(w, nfft=nfft)
+    assert plan.info['nfft'] == nfft
+    m = wl.random_model(w.axes, 1, 7)
+    d = wl.random_data(plan.ntraces, w.axes.nt, 7)
+    ef = rel(to_host(plan.forward(to_dev(m)))[:g0.x.size], gfst.forward(m[0], g))
+    ea = rel(to_host(plan.adjoint(to_dev(d)))[0], gfst.adjoint(d, g))
+    lam, gam, _ = oracle_solver_params(g, d)
+    x, _ = plan.sparse_solve(to_dev(d), 5, lam=to_dev(np.array([lam])), step=to_dev(np.array([gam])))
+    ref = fista.solve(lambda v: gfst.forward(v, g), lambda v: gfst.adjoint(v, g), d, lam, gam, 5)
+    ex = rel(to_host(x)[0], ref)
+    print(f'N {nfft}: forward {ef:.2e} adjoint {ea:.2e} fista(5) {ex:.2e}')
+    plan.close()
+    assert ef < TOL and ea < TOL and ex < TOL
+
+
 def test_operator_parity_config1():
     for ef, ea in _op_parity(wl.config1(with_data=False), seed=1):
         print(f'config1 forward {ef:.2e} adjoint {ea:.2e}')
