@@ -242,7 +242,7 @@ def plain_comparison(w, plan, lib_pair_s, n_sample, dev):
 
 
 # seconds printed in the paper's timing table (Section 5) for (nt, nx = ny, np): direct sum, proposed
-PAPER_TABLE1 = {(512, 128, 128): (218, 0.87), (512, 128, 256): (421, 1.14), (512, 256, 128): (915, 3.80),
+TIMING_TABLE_SECONDS = {(512, 128, 128): (218, 0.87), (512, 128, 256): (421, 1.14), (512, 256, 128): (915, 3.80),
                 (512, 256, 256): (1685, 3.98), (1024, 128, 128): (497, 1.97), (1024, 128, 256): (875, 2.78),
                 (1024, 256, 128): (1806, 8.57), (1024, 256, 256): (3416, 8.82)}
 
@@ -292,7 +292,7 @@ def table1_scan(reps: int):
         # stretched spacing in t is dt'/2t), so the two discretisations part mostly there
         i0 = int(round(0.4 / w.axes.dtau))
         diff_late = (torch.linalg.norm(m_g[..., i0:] - m_d[..., i0:]) / torch.linalg.norm(m_d[..., i0:])).item()
-        paper = PAPER_TABLE1[(nt, nxy, np_)]
+        paper = TIMING_TABLE_SECONDS[(nt, nxy, np_)]
         out = {'metric': 'velocity scan seconds (adjoint, one CMP)', 'workload': w.name,
                'nt': nt, 'nx': nxy, 'ny': nxy, 'np': np_, 'ntheta': w.axes.ntheta, 'traces': plan.ntraces,
                'gfst_adjoint_s': round(t_gfst, 6), 'direct_adjoint_s': round(t_direct, 6),
