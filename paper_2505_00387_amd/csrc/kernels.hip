@@ -597,8 +597,10 @@ __device__ __forceinline__ float2 dec_cell(typename GridCell<GD>::T c) {
 // gather and a tile of ft frequencies.  Two slots hold the q-grids of slices j
 // and j+1 while bin j is interpolated; slice j+2 (mod ntheta, so slice 0 is
 // built again for the last bin) then replaces slice j.
+// Registers are capped for six waves per SIMD: with two 32-frequency slots (46 KB of LDS)
+// three workgroups then fit a CU instead of two (measured 8-11% faster, same results).
 template <int W, int GD>
-__global__ __launch_bounds__(kBlockG) void k_nufft_interp(const float2* __restrict__ mhat,
+__global__ __launch_bounds__(kBlockG) __attribute__((amdgpu_waves_per_eu(6))) void k_nufft_interp(const float2* __restrict__ mhat,
                                                           float2* __restrict__ dhat, Tables tb,
                                                           Dims dm, FftPlan fpg, int ftl) {
   using Cell = typename GridCell<GD>::T;
