@@ -51,7 +51,7 @@ def source_hash() -> str:
     """Hash of the kernel sources with comments and blank space removed (comment edits keep it)."""
     import re
     h = hashlib.sha256()
-    for f in ('kernels.hip', 'fft_lds.hpp', 'aahrt_internal.hpp'):
+    for f in ('gfst.hip', 'rows.hip', 'misc.hip', 'kernel_common.hpp', 'fft_lds.hpp', 'aahrt_internal.hpp'):
         with open(os.path.join(ROOT, 'paper_2505_00387_amd', 'csrc', f)) as fh:
             text = fh.read()
         text = re.sub(r'/\*.*?\*/', '', text, flags=re.S)

@@ -78,8 +78,11 @@ typedef struct aahrt_params {
                             >= nt' + ceil(max(q_max,0) h2max/dt') + ceil(max(-q_min,0) h2max/dt');
                             otherwise it must be even, 2^a3^b5^c and >= nt' */
   double nufft_tol;      /* target relative error of the q nonuniform FFT; 0 -> 1e-6 */
-  double sigma;          /* q-grid oversampling in [1.25, 4]; 0 -> autotune among 2, 1.5 and 1.25 */
-  int32_t kernel_width;  /* spreading kernel width w (3..12); 0 -> chosen from nufft_tol and sigma;
+  double sigma;          /* q-grid oversampling in [1.25, 4]; 0 -> autotune among those of 2, 1.5 and 1.25
+                            that some width brings within nufft_tol */
+  int32_t kernel_width;  /* spreading kernel width w (3..12); 0 -> the narrowest whose estimated error
+                            (kernel truncation and FP32 rounding, see aahrt_plan_create) meets nufft_tol,
+                            or, where none does at a requested sigma, the one of smallest estimate;
                             2 -> the paper's own step 3 (Section 3.4): linear interpolation in k on the
                             sigma-oversampled grid, no deapodisation (low accuracy, reported only) */
   int32_t freq_tile;     /* frequencies per work item of the GFST stage (power of 2, 1..64); 0 -> autotune */
@@ -106,6 +109,8 @@ typedef struct aahrt_plan_info {
   int32_t autotune_candidates; /* GFST settings timed at plan creation (0: none, the setting was fixed) */
   double autotune_seconds;     /* wall time of that autotuning */
   int32_t freq_tile_adjoint;   /* frequencies per work item of the adjoint GFST kernel (spreading) */
+  double nufft_error_estimate; /* estimated relative error of one q nonuniform FFT at the chosen setting
+                                  (kernel truncation and FP32 rounding; 1 for kernel_width = 2) */
 } aahrt_plan_info;
 
 /* Version string of the library. */
@@ -124,13 +129,18 @@ const char* aahrt_last_error(void);
  *   device     : HIP device ordinal the plan lives on
  * Computes the FP64 tables (stretch taps, azimuth weights, 64-bit fixed-point
  * phase increments, kernel deapodisation), allocates the device tables and the
- * workspace (hipMalloc).  When sigma or freq_tile is 0 it then autotunes the
- * GFST stage: every admissible (sigma in {2, 1.5, 1.25}, freq_tile in {4, 8, 16, 32})
- * setting, with the kernel width that meets nufft_tol at that sigma, is timed
- * on the interpolation and on the spreading launch over the batch (on zeroed
- * spectra, in a stream of its own, synchronously); each kernel keeps its fastest
- * tile and the sigma with the smallest sum is kept.  The tiles change no
- * result; sigma changes results within the tolerance.
+ * workspace (hipMalloc).  The kernel width at an oversampling sigma is the narrowest
+ * whose estimated error meets nufft_tol.  The estimate is the root sum of squares of the
+ * kernel's truncation error (computed in FP64 for white mode coefficients) and an FP32
+ * rounding term that grows with the range of the deapodisation; in FP32 it keeps
+ * sigma = 1.25 above about 6e-6 and sigma = 1.5 above about 1.1e-6, so at the default
+ * tolerance only sigma = 2 is admitted.  When sigma or freq_tile is 0 it then autotunes
+ * the GFST stage: every admissible (sigma in {2, 1.5, 1.25}, freq_tile in {4, 8, 16, 32})
+ * setting is timed on the interpolation and on the spreading launch over the batch (on
+ * zeroed spectra, in a stream of its own, synchronously); each kernel keeps its fastest
+ * tile and the sigma with the smallest sum is kept, the default sigma = 2 unless another
+ * is at least 5% faster.  The tiles change no result; sigma changes results within the
+ * tolerance.
  */
 int aahrt_plan_create(aahrt_plan** out, const aahrt_params* p, int32_t batch,
                       const int64_t* trace_ptr, const double* x_km, const double* y_km,

@@ -44,7 +44,8 @@ class PlanInfo(ctypes.Structure):
                 ('kernel_width', ctypes.c_int32), ('sigma', ctypes.c_double), ('beta', ctypes.c_double),
                 ('freq_tile', ctypes.c_int32), ('workspace_bytes', ctypes.c_int64),
                 ('q_alias_ok', ctypes.c_int32), ('autotune_candidates', ctypes.c_int32),
-                ('autotune_seconds', ctypes.c_double), ('freq_tile_adjoint', ctypes.c_int32)]
+                ('autotune_seconds', ctypes.c_double), ('freq_tile_adjoint', ctypes.c_int32),
+                ('nufft_error_estimate', ctypes.c_double)]
 
 
 class AahrtError(RuntimeError):

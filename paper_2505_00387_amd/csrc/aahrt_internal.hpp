@@ -124,6 +124,7 @@ struct Plan {
   int device = 0;
   double dt_str = 0.0;
   double sigma = 2.0;
+  double nufft_est = 0.0;  // estimated relative error of the current q nonuniform FFT setting
   int q_alias_ok = 0;
   FftPlan fft_half{};   // N/2 complex
   FftPlan fft_grid{};   // Mg complex
@@ -195,12 +196,17 @@ __host__ __device__ inline size_t spread_lds_f2(int ft, int ldr, int mg) {
 
 // ---- kernels (kernels.hip) ----
 hipError_t launch_model_r2c(const Plan& p, const float* m, float2* mhat, hipStream_t s);
+// steps 1-2 of L on nrows rows of dm.ntau samples with the given tables (rows of dm.ntau in,
+// dm.nf bins out), for Algorithm 2's data-side stretch and transform
+hipError_t launch_rows_r2c(const Dims& dm, const Tables& tb, const FftPlan& fp, const float* in, float2* out,
+                           unsigned nrows, hipStream_t s);
 hipError_t launch_nufft_interp(const Plan& p, const float2* mhat, float2* dhat, hipStream_t s);
 hipError_t launch_data_c2r(const Plan& p, const float2* dhat, float* d, hipStream_t s);
-hipError_t launch_data_r2c(const Plan& p, const float* d, float2* dhat, hipStream_t s);
+hipError_t launch_data_r2c(const Plan& p, const float* d, float2* dhat, float* tr_bound, hipStream_t s);
 hipError_t launch_residual_r2c(const Plan& p, float2* dhat, const float* dobs, float* rss,
                                hipStream_t s);
-hipError_t launch_nufft_spread(const Plan& p, const float2* dhat, float2* mhat, hipStream_t s);
+hipError_t launch_nufft_spread(const Plan& p, const float2* dhat, const float* tr_bound, float* slice_scale,
+                               float2* mhat, hipStream_t s);
 hipError_t launch_model_c2r(const Plan& p, const float2* mhat, float* m, hipStream_t s);
 hipError_t launch_model_c2r_update(const Plan& p, float2* mhat, float* y, float* x, const float* gam,
                                    const float* lam, float beta, int ista, float* l1, bool next,

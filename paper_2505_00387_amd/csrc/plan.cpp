@@ -316,19 +316,85 @@ size_t grid_lds(int ft, int ldr, int ntheta, int mg, int gdt) {
 }
 
 // One setting of the q nonuniform FFT: oversampled grid length mg (sigma = mg/nq),
-// kernel width w, frequencies per GFST workgroup ft.
+// kernel width w, frequencies per GFST workgroup ft, and its estimated relative error.
 struct NufftChoice {
   int mg, w, ft;
+  double est;
 };
 
-// Kernel width for a target relative error: measured error of the exponential-of-
-// semicircle kernel is about 0.9 * 10^-(w-1) at sigma = 2; narrower grids need
-// wider kernels (about two more cells at sigma = 1.5, three at 1.25).
-int width_for(double tol, double sigma) {
-  int w = (int)std::ceil(-std::log10(tol / 0.9)) + 1;
-  if (sigma < 1.5 - 1e-9) w += 3;
-  else if (sigma < 2.0 - 1e-9) w += 2;
-  return std::min(12, std::max(3, w));
+// Shape parameter of the exponential-of-semicircle kernel, beta = 0.98 pi (1 - 1/(2 sigma)) w:
+// the rule of Barnett, Magland and af Klinteberg (SIAM J. Sci. Comput. 41, 2019) for the
+// width of the kernel's spectrum at oversampling sigma (2.31 w at sigma = 2).
+double es_beta(double sigma, int w) { return 0.98 * M_PI * (1.0 - 1.0 / (2.0 * sigma)) * w; }
+
+// Estimated relative error of one q nonuniform FFT (white mode coefficients) at grid length
+// mg, kernel width w and shape beta, as the root sum of squares of two parts:
+//  * truncation: mode k interpolated by the w kernel taps around a point d of a cell past a
+//    grid node, deapodised, against the exact exponential.  It depends on d alone, so its
+//    root mean square is taken over 32 offsets in [0, 1) and over (at most 256 of) the modes;
+//  * FP32 rounding: the grid transform rounds relative to the grid's content, which the
+//    deapodisation scales up towards the band edge, so this part grows with the ratio r of
+//    its largest to smallest factor: 7e-8 (r + 5), fitted to an FP32 emulation of the
+//    transform and the interpolation at nq = 32, 64 and 128 (within 20%).
+double nufft_error_estimate(int nq, int mg, int w, double beta) {
+  const int qh = nq / 2;
+  const int kstep = std::max(1, nq / 256);
+  std::vector<int> modes;
+  for (int l = 0; l < nq; l += kstep) modes.push_back(l - qh);
+  if (modes.back() != nq - 1 - qh) modes.push_back(nq - 1 - qh);
+  std::vector<double> deap(modes.size());
+  double dmin = 1e300, dmax = 0.0;
+  for (size_t i = 0; i < modes.size(); ++i) {
+    deap[i] = 1.0 / es_transform(2.0 * M_PI * modes[i] / mg, w, beta);
+    dmin = std::min(dmin, std::fabs(deap[i]));
+    dmax = std::max(dmax, std::fabs(deap[i]));
+  }
+  const int nd = 32;
+  double acc = 0.0;
+  for (int id = 0; id < nd; ++id) {
+    const double d = (id + 0.5) / nd;
+    const int off = (w % 2 == 0) ? -w / 2 : (d < 0.5 ? -(w + 1) / 2 : -(w - 1) / 2);
+    for (size_t i = 0; i < modes.size(); ++i) {
+      double re = 0.0, im = 0.0;
+      for (int t = 0; t < w; ++t) {
+        const int j = off + 1 + t;
+        const double ph = es_kernel_host(d - j, w, beta);
+        const double a = -2.0 * M_PI * modes[i] * j / mg;
+        re += ph * std::cos(a);
+        im += ph * std::sin(a);
+      }
+      const double a0 = -2.0 * M_PI * modes[i] * d / mg;
+      const double er = re * deap[i] - std::cos(a0), ei = im * deap[i] - std::sin(a0);
+      acc += er * er + ei * ei;
+    }
+  }
+  const double trunc = std::sqrt(acc / (nd * (double)modes.size()));
+  const double fp32 = 7e-8 * (dmax / dmin + 5.0);
+  return std::sqrt(trunc * trunc + fp32 * fp32);
+}
+
+// Kernel width for a target error at grid length mg (mg grows to 2w when w needs it): the
+// narrowest w in 3..12 whose estimate meets tol.  When none does, best is false and the
+// width with the smallest estimate is returned.
+void width_for(double tol, int nq, int mg0, int* w_out, int* mg_out, double* est_out, bool* best_out) {
+  int bw = 12, bmg = mg0;
+  double best = 1e300;
+  for (int w = 3; w <= 12; ++w) {
+    const int mg = std::max(mg0, next_smooth_even(2 * w));
+    const double e = nufft_error_estimate(nq, mg, w, es_beta((double)mg / nq, w));
+    if (e <= tol) {
+      *w_out = w;
+      *mg_out = mg;
+      *est_out = e;
+      *best_out = true;
+      return;
+    }
+    if (e < best) { best = e; bw = w; bmg = mg; }
+  }
+  *w_out = bw;
+  *mg_out = bmg;
+  *est_out = best;
+  *best_out = false;
 }
 
 // Row length of a q-grid slot: the ghost cells, and room for the padded first FFT pass.
@@ -347,9 +413,12 @@ bool choice_fits(const Dims& dm, int mg, int w, int ft) {
   return grid_lds(ft, slot_row(mg, w), dm.ntheta, mg, dm.gdt) <= 160 * 1024 && dm.nq * ft <= kPrefetchCells;
 }
 
-// Candidates: the requested sigma (or 2 and 1.5 when it is free) with the width from
-// the tolerance (or the requested width), and the requested tile (or 4..32 when
-// free).  The first candidate is the default setting.
+// Candidates: the requested sigma (or 2, 1.5 and 1.25 when it is free) with the narrowest
+// width whose estimated error meets the tolerance (or the requested width), and the
+// requested tile (or 4..32 when free).  A free sigma that no width brings within the
+// tolerance is left out (in FP32 the deapodisation range of sigma = 1.25 holds it near 6e-6);
+// a requested sigma, or the last one when all miss, keeps the width of smallest estimate.
+// The first candidate is the default setting.
 int nufft_candidates(const aahrt_params& prm, const Dims& dm, std::vector<NufftChoice>& out) {
   const double tol = prm.nufft_tol == 0.0 ? 1e-6 : prm.nufft_tol;
   if (dm.nq > kPrefetchCells) return fail(AAHRT_E_UNSUPPORTED, "nq too large for the q-coefficient prefetch");
@@ -361,10 +430,22 @@ int nufft_candidates(const aahrt_params& prm, const Dims& dm, std::vector<NufftC
   else fts = {16, 8, 32, 4};
   out.clear();
   std::vector<int> seen_mg;
+  NufftChoice fallback{0, 0, 0, 1e300};
   for (double sg : sig) {
-    int w = prm.kernel_width != 0 ? prm.kernel_width : width_for(tol, sg);
-    int mg = next_smooth_even((long)std::ceil(sg * dm.nq));
-    if (mg < 2 * w) mg = next_smooth_even(2 * w);
+    const int mg0 = next_smooth_even((long)std::ceil(sg * dm.nq));
+    int w = prm.kernel_width, mg = mg0;
+    double est = 0.0;
+    if (w != 0) {
+      if (mg < 2 * w) mg = next_smooth_even(2 * w);
+      est = w == 2 ? 1.0 : nufft_error_estimate(dm.nq, mg, w, es_beta((double)mg / dm.nq, w));
+    } else {
+      bool meets = false;
+      width_for(tol, dm.nq, mg0, &w, &mg, &est, &meets);
+      if (!meets && prm.sigma == 0.0) {
+        if (est < fallback.est) fallback = NufftChoice{mg, w, 0, est};
+        continue;
+      }
+    }
     if (std::find(seen_mg.begin(), seen_mg.end(), mg) != seen_mg.end()) continue;
     seen_mg.push_back(mg);
     FftPlan fp;
@@ -373,16 +454,22 @@ int nufft_candidates(const aahrt_params& prm, const Dims& dm, std::vector<NufftC
       // a requested tile is halved until it fits
       int ft = prm.freq_tile;
       while (ft > 1 && !choice_fits(dm, mg, w, ft)) ft /= 2;
-      if (choice_fits(dm, mg, w, ft)) out.push_back({mg, w, ft});
+      if (choice_fits(dm, mg, w, ft)) out.push_back({mg, w, ft, est});
     } else {
       for (int ft : fts)
-        if (choice_fits(dm, mg, w, ft)) out.push_back({mg, w, ft});
+        if (choice_fits(dm, mg, w, ft)) out.push_back({mg, w, ft, est});
       if (out.empty() || out.back().mg != mg) {
         int ft = 16;
         while (ft > 1 && !choice_fits(dm, mg, w, ft)) ft /= 2;
-        if (choice_fits(dm, mg, w, ft)) out.push_back({mg, w, ft});
+        if (choice_fits(dm, mg, w, ft)) out.push_back({mg, w, ft, est});
       }
     }
+  }
+  if (out.empty() && fallback.mg != 0) {
+    // no free sigma meets the tolerance: the setting with the smallest estimate
+    int ft = prm.freq_tile != 0 ? prm.freq_tile : 16;
+    while (ft > 1 && !choice_fits(dm, fallback.mg, fallback.w, ft)) ft /= 2;
+    if (choice_fits(dm, fallback.mg, fallback.w, ft)) out.push_back({fallback.mg, fallback.w, ft, fallback.est});
   }
   if (out.empty()) return fail(AAHRT_E_UNSUPPORTED, "q-grid too large for LDS");
   return AAHRT_OK;
@@ -396,7 +483,8 @@ int set_nufft(Plan& P, const NufftChoice& c) {
   dm.mg = c.mg;
   dm.w = c.w;
   P.sigma = (double)c.mg / dm.nq;
-  const double beta = 0.98 * M_PI * (1.0 - 1.0 / (2.0 * P.sigma)) * c.w;
+  P.nufft_est = c.est;
+  const double beta = es_beta(P.sigma, c.w);
   dm.beta = (float)beta;
   dm.cbeta = (float)(beta / std::log(2.0));
   dm.ldr = slot_row(c.mg, c.w);
@@ -424,7 +512,8 @@ int set_nufft(Plan& P, const NufftChoice& c) {
 
 // Time the GFST stage for every candidate, on zeroed spectra: the interpolation
 // and the spreading kernels are timed separately, each keeps its fastest tile for
-// a given oversampling, and the oversampling with the smallest sum is kept.  The
+// a given oversampling, and the oversampling with the smallest sum is kept (the first,
+// default one unless another is at least 5% faster).  The
 // oversamplings give the same result to within the tolerance; the tiles change no
 // result.
 int autotune_nufft(Plan& P, const std::vector<NufftChoice>& cands) {
@@ -440,7 +529,7 @@ int autotune_nufft(Plan& P, const std::vector<NufftChoice>& cands) {
       HIP_TRY(hipEventRecord(e0, s));
       for (int r = 0; r < reps; ++r) {
         if (which == 0) HIP_TRY(launch_nufft_interp(P, P.mhat, P.dhat, s));
-        else HIP_TRY(launch_nufft_spread(P, P.dhat, P.mhat, s));
+        else HIP_TRY(launch_nufft_spread(P, P.dhat, P.tr_bound, P.slice_scale, P.mhat, s));
       }
       HIP_TRY(hipEventRecord(e1, s));
       HIP_TRY(hipEventSynchronize(e1));
@@ -449,9 +538,9 @@ int autotune_nufft(Plan& P, const std::vector<NufftChoice>& cands) {
     }
     return AAHRT_OK;
   };
-  NufftChoice best{0, 0, 0};
+  NufftChoice best{0, 0, 0, 0.0};
   int best_fi = 0, best_fs = 0;
-  float best_total = 0.f;
+  float best_total = 0.f, default_total = 0.f;
   do {
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
       rc = fail(AAHRT_E_HIP, "hipEventCreate failed");
@@ -479,7 +568,10 @@ int autotune_nufft(Plan& P, const std::vector<NufftChoice>& cands) {
         if (j == i || ts < bs) { bs = ts; fs = cands[j].ft; }
       }
       if (rc != AAHRT_OK) break;
-      if (best.mg == 0 || bi + bs < best_total) {
+      // another oversampling (which changes results within the tolerance) replaces the
+      // default only when it is at least 5% faster, so that timing noise rarely flips it
+      if (i == 0) default_total = bi + bs;
+      if (best.mg == 0 || (bi + bs < best_total && bi + bs < 0.95f * default_total)) {
         best = cands[i];
         best_fi = fi;
         best_fs = fs;
@@ -881,8 +973,8 @@ int do_forward(Plan& P, const float* m, float* d, hipStream_t s) {
 }
 
 int do_adjoint(Plan& P, const float* d, float* m, hipStream_t s) {
-  KCALL(AAHRT_K_DATA_R2C, launch_data_r2c(P, d, P.dhat, s));
-  KCALL(AAHRT_K_NUFFT_SPREAD, launch_nufft_spread(P, P.dhat, P.mhat, s));
+  KCALL(AAHRT_K_DATA_R2C, launch_data_r2c(P, d, P.dhat, P.tr_bound, s));
+  KCALL(AAHRT_K_NUFFT_SPREAD, launch_nufft_spread(P, P.dhat, P.tr_bound, P.slice_scale, P.mhat, s));
   KCALL(AAHRT_K_MODEL_C2R, launch_model_c2r(P, P.mhat, m, s));
   return AAHRT_OK;
 }
@@ -934,7 +1026,7 @@ int enqueue_iterations(Plan& P, const float* d, float* m, int n_iter, bool ista,
     const bool next = k + 1 < n_iter;
     KCALL(AAHRT_K_NUFFT_INTERP, launch_nufft_interp(P, P.mhat, P.dhat, s));
     KCALL(AAHRT_K_RESIDUAL_R2C, launch_residual_r2c(P, P.dhat, d, objective ? P.rss : nullptr, s));
-    KCALL(AAHRT_K_NUFFT_SPREAD, launch_nufft_spread(P, P.dhat, P.mhat, s));
+    KCALL(AAHRT_K_NUFFT_SPREAD, launch_nufft_spread(P, P.dhat, P.tr_bound, P.slice_scale, P.mhat, s));
     KCALL(next ? AAHRT_K_MODEL_UPDATE_R2C : AAHRT_K_MODEL_C2R_UPDATE,
           launch_model_c2r_update(P, P.mhat, P.ybuf, m, P.gam, P.lam, (float)betas[k], ista ? 1 : 0,
                                   objective ? P.l1row : nullptr, next, s));
@@ -1014,6 +1106,7 @@ int aahrt_plan_query(const aahrt_plan* plan, aahrt_plan_info* info) {
   info->q_alias_ok = P.q_alias_ok;
   info->autotune_candidates = (int32_t)P.tune_ms.size();
   info->autotune_seconds = P.autotune_s;
+  info->nufft_error_estimate = P.nufft_est;
   return AAHRT_OK;
 }
 

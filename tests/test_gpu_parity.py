@@ -14,9 +14,10 @@ from gpu_common import TOL, rel, geoms, make_plan, to_dev, to_host, split_data, 
 pytestmark = pytest.mark.gpu
 
 
-def _op_parity(w, seed=0, **plan_kw):
+def _op_parity(w, seed=0, with_info=False, **plan_kw):
     gs = geoms(w)
     plan = make_plan(w, **plan_kw)
+    info = dict(plan.info)
     assert plan.info['nfft'] == gs[0].nfft           # independent N rules agree
     m = wl.random_model(w.axes, w.batch, seed)
     d = wl.random_data(plan.ntraces, w.axes.nt, seed)
@@ -32,7 +33,7 @@ def _op_parity(w, seed=0, **plan_kw):
         ref_m = gfst.adjoint(d[tp[b]:tp[b + 1]], g)
         errs.append((rel(got_d[tp[b]:tp[b + 1]], ref_d), rel(got_m[b], ref_m)))
     plan.close()
-    return errs
+    return (errs, info) if with_info else errs
 
 
 @pytest.mark.parametrize('nq,ntheta,ntr,nt', [(8, 5, 37, 64), (7, 1, 20, 50), (6, 2, 11, 40),
@@ -150,31 +151,39 @@ def test_dot_product_fp32_config1():
     plan.close()
 
 
-def test_operator_parity_config4_full_size_sampled():
-    """All 256 uneven gathers on the GPU; sampled traces and model rows checked by the oracle."""
+def test_operator_parity_config4_all_gathers():
+    """L and L^T over all 256 uneven gathers in one autotuned plan (the benchmark's launch
+    configuration).  Every gather is checked on two seeded traces of L m and two seeded model
+    rows of L^T d against stored oracle values (tests/golden/config4_operators.npz, written by
+    tests/golden/make_config4_operators.py from the oracle alone)."""
+    import hashlib
+    import os
+    import torch
+    z = np.load(os.path.join(os.path.dirname(__file__), 'golden', 'config4_operators.npz'), allow_pickle=False)
     w = wl.config4(with_data=False)
+    seed = int(z['seed'])
+    m = wl.random_model(w.axes, w.batch, seed)
+    d = wl.random_data(int(w.trace_ptr[-1]), w.axes.nt, seed)
+    assert hashlib.sha256(m.tobytes()).hexdigest() == str(z['model_sha']), 'stale reference'
+    assert hashlib.sha256(d.tobytes()).hexdigest() == str(z['data_sha']), 'stale reference'
     plan = make_plan(w)
-    gsall = geoms(w)
-    assert plan.info['nfft'] == gsall[0].nfft == 4320
-    m = wl.random_model(w.axes, w.batch, 21)
-    d = wl.random_data(plan.ntraces, w.axes.nt, 21)
-    got_d = to_host(plan.forward(to_dev(m)))
-    got_m = to_host(plan.adjoint(to_dev(d)))
+    assert plan.info['nfft'] == int(z['nfft']) == 4320
+    got_d = plan.forward(to_dev(m))
+    got_m = plan.adjoint(to_dev(d))
+    del m, d
     tp = w.trace_ptr
-    folds = np.diff(tp)
-    rng = np.random.default_rng(0)
-    picks = sorted({int(np.argmin(folds)), int(np.argmax(folds)), int(rng.integers(w.batch)), 255})
-    for b in picks:
-        g = gsall[b]
-        idx = sorted(rng.choice(g.x.size, 4, replace=False))
-        ref = gfst.forward_traces(m[b], g, idx)
-        ef = rel(got_d[tp[b] + np.array(idx)], ref)
-        rows = [(int(rng.integers(g.ntheta)), int(rng.integers(g.nq))) for _ in range(3)]
-        refm = gfst.adjoint(d[tp[b]:tp[b + 1]], g, rows=rows)
-        ea = rel(np.stack([got_m[b, j, l] for j, l in rows]), refm)
-        print(f'gather {b} fold {folds[b]}: forward {ef:.2e} adjoint {ea:.2e}')
-        assert ef < TOL and ea < TOL
+    tr = torch.as_tensor(z['trace_idx'] + tp[:-1, None], device='cuda:0')
+    rows = z['row_idx']
+    gd = to_host(got_d[tr.reshape(-1)]).reshape(z['forward'].shape)
+    bidx = torch.arange(w.batch, device='cuda:0')[:, None].expand(-1, rows.shape[1])
+    gm = to_host(got_m[bidx, torch.as_tensor(rows[..., 0], device='cuda:0'),
+                       torch.as_tensor(rows[..., 1], device='cuda:0')])
+    ef = np.array([rel(gd[b], z['forward'][b]) for b in range(w.batch)])
+    ea = np.array([rel(gm[b], z['adjoint'][b]) for b in range(w.batch)])
+    print(f'256 gathers, sigma {plan.info["sigma"]} w {plan.info["kernel_width"]}: forward max {ef.max():.2e} '
+          f'median {np.median(ef):.2e}; adjoint max {ea.max():.2e} median {np.median(ea):.2e}')
     plan.close()
+    assert ef.max() < TOL and ea.max() < TOL
 
 
 def test_operator_parity_config5_large_sampled():
@@ -255,13 +264,44 @@ def test_grid_precision_sweep_large():
     assert rel(adj['fp32'][b, rows[b][0], rows[b][1]][None], refm) < TOL
 
 
-@pytest.mark.parametrize('sigma,freq_tile', [(1.5, 4), (1.25, 32), (3.0, 1), (2.0, 64)])
-def test_operator_parity_grid_settings(sigma, freq_tile):
-    """Every oversampling and tile the autotuner may pick (and the extremes) meets the bound."""
-    errs = _op_parity(wl.config3(with_data=False), seed=4, sigma=sigma, freq_tile=freq_tile)
-    print(f'sigma {sigma} tile {freq_tile}', [f'{a:.1e}/{b:.1e}' for a, b in errs])
+# The FP32 floor of everything but the nonuniform FFT (row transforms of length <= 1000, the
+# stretch interpolations) measured on these workloads is below 3e-7.
+FP32_FLOOR = 3e-7
+
+
+@pytest.mark.parametrize('sigma,tol,freq_tile', [(2.0, 1e-6, 64), (3.0, 1e-6, 1), (1.5, 2e-6, 4),
+                                                 (1.25, 1e-5, 32), (2.0, 1e-4, 16), (1.25, 1e-6, 8)])
+def test_operator_error_meets_nufft_tol(sigma, tol, freq_tile):
+    """Every (sigma, width) the width rule admits for a tolerance meets it against the oracle, to
+    twice the tolerance above the FP32 floor of the rest of the pipeline.  A requested sigma that no
+    width brings within the tolerance (1.25 at 1e-6: the FP32 rounding of its grid transform,
+    amplified by the deapodisation, sits near 6e-6) reports an estimate above the tolerance and
+    stays within twice that estimate.  Extremes of the tile (1 and 64) are covered too."""
+    w = wl.config3(with_data=False)
+    errs, info = _op_parity(w, seed=4, with_info=True, sigma=sigma, freq_tile=freq_tile, nufft_tol=tol)
+    est = info['nufft_error_estimate']
+    bound = 2.0 * max(tol, est) + FP32_FLOOR
+    print(f'sigma {info["sigma"]} w {info["kernel_width"]} tol {tol:.0e} estimate {est:.2e}:',
+          [f'{a:.1e}/{b:.1e}' for a, b in errs], f'bound {bound:.1e}')
+    if est <= tol:
+        assert bound <= 2.0 * tol + FP32_FLOOR
+    else:
+        assert sigma == 1.25 and tol == 1e-6
     for ef, ea in errs:
-        assert ef < TOL and ea < TOL
+        assert ef < bound and ea < bound
+
+
+def test_width_rule_admits_only_settings_that_meet_the_tolerance():
+    """At the default tolerance (1e-6) only sigma = 2 is admitted for nq = 64 (width 7); sigma = 1.5
+    enters at 2e-6 (width 8) and sigma = 1.25 at 1e-5 (width 9).  Host-side rule, seen through
+    the plan."""
+    w = wl.config2(with_data=False)
+    for tol, sigma, width in ((1e-6, 2.0, 7), (2e-6, 1.5, 8), (1e-5, 1.25, 9)):
+        plan = make_plan(w, nufft_tol=tol, sigma=sigma, freq_tile=16)
+        info = plan.info
+        print(tol, sigma, {k: info[k] for k in ('kernel_width', 'grid_size', 'nufft_error_estimate')})
+        assert info['kernel_width'] == width and info['nufft_error_estimate'] <= tol
+        plan.close()
 
 
 def test_frequency_tile_changes_no_result():
@@ -280,15 +320,21 @@ def test_frequency_tile_changes_no_result():
 
 
 def test_autotuner_times_the_candidates():
+    """At the default tolerance the autotuner times the tiles of the one admitted oversampling
+    (sigma = 2; width 8 at nq = 32, whose estimate for width 7 is 1.03e-6)."""
     w = wl.config3(with_data=False)
     plan = make_plan(w)
     info = plan.info
     print('autotuned', {k: info[k] for k in ('sigma', 'kernel_width', 'freq_tile', 'autotune_candidates',
-                                             'autotune_seconds')})
-    assert info['autotune_candidates'] >= 6          # three oversamplings x several tiles
-    widths = {2.0: 7, 1.5: 9, 1.25: 10}               # tolerance 1e-6
-    assert info['sigma'] in widths and info['kernel_width'] == widths[info['sigma']]
+                                             'autotune_seconds', 'nufft_error_estimate')})
+    assert info['autotune_candidates'] >= 6          # interpolation and spreading, three tiles or more
+    assert info['sigma'] == 2.0 and info['kernel_width'] == 8
+    assert info['nufft_error_estimate'] <= 1e-6
     assert info['freq_tile'] in (4, 8, 16, 32) and info['freq_tile_adjoint'] in (4, 8, 16, 32)
+    plan.close()
+    # a looser tolerance admits the narrower grids, which are then timed as well
+    plan = make_plan(w, nufft_tol=1e-4)
+    assert plan.info['autotune_candidates'] > info['autotune_candidates']
     plan.close()
 
 
@@ -556,30 +602,41 @@ def test_deconv_fista_parity_config1():
 
 
 # ------------------------------------------------------------------ the paper's linear k-interpolation
-def test_linear_k_interpolation_mode():
-    """kernel_width = 2: the paper's step 3 (Section 3.4), linear interpolation in k on the
-    sigma-oversampled grid without deapodisation.  The GPU pair is an exact transpose pair (FP32
-    dot test); its error against the exact operator is reported, and falls as the grid is refined."""
-    w = wl.config1(with_data=False)
-    g = geoms(w)[0]
-    m = wl.random_model(w.axes, 1, 51)
-    d = wl.random_data(256, w.axes.nt, 51)
-    ref_d, ref_m = gfst.forward(m[0], g), gfst.adjoint(d, g)
-    errs = {}
+@pytest.mark.parametrize('config', [1, 3])
+def test_linear_k_interpolation_mode(config):
+    """kernel_width = 2 is the paper's own step 3 (Section 3.4, eq. thli): the bilinear A1..A4
+    interpolation in (k, theta) on the sigma-oversampled k grid, without deapodisation.  Held to
+    the 1e-4 bound against the oracle of that step (oracle/lineark.py) on the plan's grid, at two
+    oversamplings; the FP32 dot test of the pair; its error against the exact operator is reported
+    and falls by about four when the grid is refined twofold (second order)."""
+    from oracle import lineark
+    w = wl.CONFIGS[config](with_data=False)
+    gs = geoms(w)
+    tp = w.trace_ptr
+    m = wl.random_model(w.axes, w.batch, 51)
+    d = wl.random_data(int(tp[-1]), w.axes.nt, 51)
+    exact = {}
     for sigma in (2.0, 4.0):
         plan = make_plan(w, kernel_width=2, sigma=sigma)
         assert plan.info['kernel_width'] == 2
+        mg = plan.info['grid_size']
         got_d = to_host(plan.forward(to_dev(m)))
         got_m = to_host(plan.adjoint(to_dev(d)))
         lhs, rhs = float(np.sum(got_d * d)), float(np.sum(m * got_m))
-        scale = np.linalg.norm(got_d) * np.linalg.norm(d)
-        assert abs(lhs - rhs) < 1e-5 * scale
-        errs[sigma] = (rel(got_d, ref_d), rel(got_m[0], ref_m))
+        assert abs(lhs - rhs) < 1e-5 * np.linalg.norm(got_d) * np.linalg.norm(d)
+        ep, ex = [], []
+        for b, g in enumerate(gs):
+            db = d[tp[b]:tp[b + 1]]
+            ref_d, ref_m = lineark.forward(m[b], g, mg), lineark.adjoint(db, g, mg)
+            ep.append(max(rel(got_d[tp[b]:tp[b + 1]], ref_d), rel(got_m[b], ref_m)))
+            if b == 0:
+                ex.append((rel(got_d[:tp[1]], gfst.forward(m[0], g)), rel(got_m[0], gfst.adjoint(db, g))))
+        exact[sigma] = ex[0]
+        print(f'config {config} sigma {sigma} grid {mg}: parity with the step-3 oracle max {max(ep):.2e}; '
+              f'error against the exact operator (forward, adjoint) {ex[0][0]:.2e}, {ex[0][1]:.2e}')
         plan.close()
-    print('linear k-interpolation, relative error (forward, adjoint) by oversampling:',
-          {k: (f'{a:.2e}', f'{b:.2e}') for k, (a, b) in errs.items()})
-    assert errs[4.0][0] < errs[2.0][0] and errs[4.0][1] < errs[2.0][1]
-    assert errs[2.0][0] < 1.0 and errs[4.0][0] > 1e-4
+        assert max(ep) < TOL
+    assert exact[4.0][0] < 0.4 * exact[2.0][0] and exact[4.0][1] < 0.4 * exact[2.0][1]
 
 
 def _direct_parity(w, seed):

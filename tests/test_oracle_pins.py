@@ -582,3 +582,80 @@ def test_alg2_focuses_an_event_at_its_curvature_per_azimuth(Wq):
         l, i = np.unravel_index(np.argmax(np.abs(M[j])), M[j].shape)
         assert abs(i * ax.dtau - 0.4) <= ax.dtau
         assert abs(g.q[l] - c @ Wq @ c) <= dq
+
+
+# ------------------------------------------------------------------ the paper's step 3 (Section 3.4)
+def _node_geometry(mg, nfft=240):
+    """Tiny axes and traces whose k = f' h^2 falls on a node of the mg-point k grid for every
+    frequency (h^2 = c N dt'/(dq mg), c integer) at azimuths on grid lines (0 and pi/2)."""
+    ax = wl.Axes(nt=32, dt=0.02, ntau=32, dtau=0.02, nq=8, q_min=0.05, q_max=0.4, ntheta=4)
+    T = (ax.nt - 1) * ax.dt
+    dts = T * T / (2 * ax.nt - 1)
+    unit = nfft * dts / (ax.dq * mg)
+    c = np.array([0, 1, 2, 3, 5, 8])
+    h = np.sqrt(c * unit)
+    x = np.concatenate([h, np.zeros(c.size - 1)])
+    y = np.concatenate([np.zeros(c.size), h[1:]])
+    return ax, Geometry.build(ax, x, y, nfft=nfft)
+
+
+@pytest.mark.parametrize('mg', [16, 24, 40])
+def test_lineark_is_exact_on_the_k_grid_nodes(mg):
+    """Where every k = f'h^2 is a node k_i of the grid and theta a grid azimuth, the A1..A4
+    interpolation reads node values only, so it equals the exact sum over q (oracle-1)."""
+    from oracle import lineark
+    ax, g = _node_geometry(mg)
+    rng = np.random.default_rng(mg)
+    m = rng.standard_normal((g.ntheta, g.nq, g.ntau))
+    np.testing.assert_allclose(lineark.forward(m, g, mg), gfst.forward(m, g), atol=1e-11, rtol=0)
+    d = rng.standard_normal((g.x.size, g.nt))
+    np.testing.assert_allclose(lineark.adjoint(d, g, mg), gfst.adjoint(d, g), atol=1e-11, rtol=0)
+
+
+def test_lineark_is_linear_in_k_between_nodes():
+    """Between two nodes the interpolated spectrum, with the centring phase exp(-2 pi i f' q_c h^2)
+    removed, is the straight line between the exact centred values at the nodes (Section 3.4,
+    A1..A4 with theta on a grid line); node values from oracle-1's exact sum."""
+    from oracle import lineark
+    mg = 20
+    ax, g0 = _node_geometry(mg)
+    rng = np.random.default_rng(3)
+    mh = rng.standard_normal((g0.ntheta, g0.nq, g0.nf)) + 1j * rng.standard_normal((g0.ntheta, g0.nq, g0.nf))
+    qc = lineark.q_centre(g0)
+    for f in (1, 7, 33, 119):
+        fp = f / (g0.nfft * g0.dt_str)
+        for u in (0.25, 3.6, 11.93):                # k/dk of the trace (not a node)
+            i = math.floor(u)
+            a = u - i
+            h2 = np.array([u, i, i + 1]) / (fp * ax.dq * mg)
+            gg = g0.subset([0, 0, 0])
+            gg.x = np.sqrt(h2)
+            gg.y = np.zeros(3)
+            lin = lineark.linear_map(mh, gg, mg)[:, f]
+            ex = gfst.gfst_map(mh, gg)[:, f] * np.exp(2j * np.pi * fp * qc * h2)   # centred exact values
+            want = (1 - a) * ex[1] + a * ex[2]
+            got = lin[0] * np.exp(2j * np.pi * fp * qc * h2[0])
+            assert abs(got - want) < 1e-10 * max(1.0, abs(want)), (f, u)
+
+
+def test_lineark_error_falls_with_the_k_grid_step():
+    """Against the exact sum over q the linear interpolation is second order in dk = 1/(mg dq):
+    doubling mg cuts the error by about four (config-1 axes, random model)."""
+    from oracle import lineark
+    w = wl.config1(with_data=False)
+    g = Geometry.build(w.axes, w.gathers[0].x[::5], w.gathers[0].y[::5])
+    m = np.random.default_rng(5).standard_normal((g.ntheta, g.nq, g.ntau))
+    ref = gfst.forward(m, g)
+    errs = [np.linalg.norm(lineark.forward(m, g, mg) - ref) / np.linalg.norm(ref) for mg in (64, 128, 256)]
+    assert errs[0] < 0.5
+    assert 0.15 < errs[1] / errs[0] < 0.35 and 0.15 < errs[2] / errs[1] < 0.35, errs
+
+
+@pytest.mark.parametrize('mg', [12, 30])
+def test_lineark_dot_test(mg):
+    from oracle import lineark
+    w, g = _tiny(4, ntheta=5, nq=6)
+    rng = np.random.default_rng(mg)
+    m = rng.standard_normal((g.ntheta, g.nq, g.ntau))
+    d = rng.standard_normal((g.x.size, g.nt))
+    assert _dot_test(lambda v: lineark.forward(v, g, mg), lambda v: lineark.adjoint(v, g, mg), m, d) < 1e-12
