@@ -28,10 +28,12 @@ from .geometry import Geometry
 _FCHUNK = 32
 
 
-def _phase(geom: Geometry, f_idx: np.ndarray, h2: np.ndarray) -> np.ndarray:
-    """exp(-2 pi i f'_f q_l h_n^2) as [len(f_idx), ntr, nq]."""
+def _phase(geom: Geometry, f_idx: np.ndarray, h2: np.ndarray, q=None) -> np.ndarray:
+    """exp(-2 pi i f'_f q_l h_n^2) as [len(f_idx), ntr, nq] (or [len(f_idx), ntr, len(q)] for
+    the curvatures q given)."""
     fp = f_idx / (geom.nfft * geom.dt_str)
-    arg = fp[:, None, None] * h2[None, :, None] * geom.q[None, None, :]
+    qv = geom.q if q is None else np.asarray(q, dtype=np.float64)
+    arg = fp[:, None, None] * h2[None, :, None] * qv[None, None, :]
     return np.exp(-2j * np.pi * arg)
 
 
@@ -107,13 +109,15 @@ def gfst_map_T(gh: np.ndarray, geom: Geometry, rows=None) -> np.ndarray:
         out = np.zeros((len(rows), geom.nf), dtype=np.complex128)
     for f0 in range(0, geom.nf, _FCHUNK):
         fi = np.arange(f0, min(f0 + _FCHUNK, geom.nf))
-        Ec = np.conj(_phase(geom, fi, h2))              # [fc, n, l]
-        B = Ec * gh[:, fi].T[:, :, None]                 # [fc, n, l]
         if rows is None:
+            Ec = np.conj(_phase(geom, fi, h2))          # [fc, n, l]
+            B = Ec * gh[:, fi].T[:, :, None]             # [fc, n, l]
             out[:, :, fi] = np.einsum('nj,fnl->jlf', W, B)
         else:
+            # only the curvatures of the requested rows: the same phases, fewer of them
             for k, (j, l) in enumerate(rows):
-                out[k, fi] = W[:, j] @ B[:, :, l].T
+                Ec = np.conj(_phase(geom, fi, h2, q=geom.q[l:l + 1]))[:, :, 0]   # [fc, n]
+                out[k, fi] = W[:, j] @ (Ec * gh[:, fi].T).T
     return out
 
 

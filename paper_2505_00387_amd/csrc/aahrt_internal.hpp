@@ -71,6 +71,7 @@ struct Tables {
   const unsigned long long* tr_b;      // frac(dq h^2/(N dt')) as 0.64 fixed point
   const unsigned long long* tr_a;      // frac(q_c h^2/(N dt')) as 0.64 fixed point
   const float* tr_alpha;               // azimuth weight on the upper bin
+  const float2* tr_rot;                // exp(-2 pi i frac(q_c h^2/(N dt'))), the pre-phase step per frequency
   const int* bin_ptr;                  // [batch][ntheta+1] positions into the bin-ordered arrays
   const int* gather_of_row;            // data row -> gather
   const float* wav;                    // wavelet taps (deconvolutive operator), or null

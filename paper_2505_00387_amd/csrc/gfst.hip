@@ -16,8 +16,9 @@ namespace aahrt {
 // distinct LDS banks).  Slices are visited in azimuth order; traces are grouped
 // by their lower azimuth bin j_n, so bin j needs slices j and j+1 (mod ntheta).
 // The (trace, frequency) items of a bin run with the frequency fastest across
-// threads; the per-trace tables are read straight from memory (the lanes of one
-// trace share the cache line), so a bin needs no barrier of its own.
+// threads, kFpt consecutive frequencies per thread; the per-trace tables are read
+// straight from memory (the lanes of one trace share the cache line), so a bin needs
+// no barrier of its own.
 //
 // Phases use 0.64 fixed point: frac(f b) for an integer frequency index f is the
 // wrapped 64-bit product, of which only the top 32 bits are formed
@@ -29,9 +30,18 @@ struct KernelPoint {
   float z0;   // 2 d0 / w, d0 = distance from the point to the first cell
 };
 
+// frac(f b) of a 0.64 fixed-point b for an integer frequency index f: the wrapped 64-bit
+// product f b, formed from 32-bit multiplies.
+__device__ __forceinline__ unsigned long long fix_mul(unsigned f, unsigned long long bfix) {
+  const unsigned lo = f * (unsigned)bfix;
+  const unsigned hi = f * (unsigned)(bfix >> 32) + __umulhi(f, (unsigned)bfix);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// Footprint of the point at grid position u = mg frac(f b), from the top 32 bits t32 of
+// the 0.64 phase (32 fractional bits of u are kept before the FP32 fraction is taken).
 template <int W>
-__device__ __forceinline__ KernelPoint kernel_point(unsigned f, unsigned long long bfix, int mg) {
-  const unsigned t32 = f * (unsigned)(bfix >> 32) + __umulhi(f, (unsigned)bfix);
+__device__ __forceinline__ KernelPoint kernel_point(unsigned t32, int mg) {
   const unsigned long long u = (unsigned long long)t32 * (unsigned)mg;
   const int ui = (int)(u >> 32);
   const float uf = (float)(unsigned)u * 2.3283064365386963e-10f;
@@ -54,6 +64,12 @@ __device__ __forceinline__ float2 pre_phase(unsigned f, unsigned long long afix)
   if (rev >= 0.5f) rev -= 1.0f;
   return make_float2(__builtin_amdgcn_cosf(rev), (float)SIGN * __builtin_amdgcn_sinf(rev));
 }
+
+// Consecutive frequencies per thread in the GFST kernels.  A thread takes kFpt neighbouring
+// frequencies of one trace: the per-trace tables are read once for all of them, the grid
+// position steps by the exact 64-bit increment b, and the pre-phase steps by the trace's
+// rotation exp(-+2 pi i frac(a)) from one exact start (at most kFpt - 1 FP32 products).
+constexpr int kFpt = 4;
 
 // Exponential-of-semicircle kernel at normalised distance z = 2 d / w:
 // exp(beta (sqrt(1 - z^2) - 1)) = exp2(cbeta sqrt(1 - z^2) - cbeta), cbeta = beta log2(e).
@@ -196,6 +212,10 @@ __global__ __launch_bounds__(kBlockG) __attribute__((amdgpu_waves_per_eu(6))) vo
   if (bp[dm.ntheta] == bp[0]) return;  // empty gather: nothing to write
   for (int i = threadIdx.x; i < dm.mg; i += kBlockG) twl[i] = tb.tw_grid[i];
   const int nt = dm.ntheta;
+  // thread items: kFpt consecutive frequencies of one trace (all ft when ft < kFpt)
+  const int fpt = ft >= kFpt ? kFpt : ft;
+  const int gpt = ft / fpt;
+  const int gpl = ft >= kFpt ? ftl - 2 : 0;
 
   // step -2 and -1 build slices 0 and 1; step j >= 0 interpolates bin j, then builds
   // slice (j + 2) mod ntheta into the slot of slice j (while j + 2 <= ntheta).  The
@@ -211,27 +231,39 @@ __global__ __launch_bounds__(kBlockG) __attribute__((amdgpu_waves_per_eu(6))) vo
       const Cell* G1 = slots + (nt == 1 ? 0 : ((j + 1) & 1)) * slot_sz;
       const int c0 = bp[j];
       const int cnt = bp[j + 1] - c0;
-      for (int it = threadIdx.x; it < cnt * ft; it += kBlockG) {
-        const int n = c0 + (it >> ftl);
-        const int fl = it & (ft - 1);
-        const unsigned f = (unsigned)(f0 + fl);
-        if (f >= (unsigned)dm.nf) continue;
-        const KernelPoint kp = kernel_point<W>(f, tb.tr_b[n], dm.mg);
-        const Cell* g0 = G0 + fl * ldr + kp.base;
-        const Cell* g1 = G1 + fl * ldr + kp.base;
-        float2 a0 = make_float2(0.f, 0.f), a1 = make_float2(0.f, 0.f);
-#pragma unroll
-        for (int t = 0; t < W; ++t) {
-          const float ph = grid_tap<W>(fmaf((float)t, -2.0f / (float)W, kp.z0), dm.cbeta);
-          const float2 v0 = dec_cell<GD>(g0[t]), v1 = dec_cell<GD>(g1[t]);
-          a0.x = fmaf(ph, v0.x, a0.x);
-          a0.y = fmaf(ph, v0.y, a0.y);
-          a1.x = fmaf(ph, v1.x, a1.x);
-          a1.y = fmaf(ph, v1.y, a1.y);
-        }
+      for (int it = threadIdx.x; it < cnt * gpt; it += kBlockG) {
+        const int n = c0 + (it >> gpl);
+        const int fl0 = (it & (gpt - 1)) * fpt;
+        const unsigned f1 = (unsigned)(f0 + fl0);
+        if (f1 >= (unsigned)dm.nf) continue;
+        const unsigned long long bfix = tb.tr_b[n];
+        unsigned long long t = fix_mul(f1, bfix);
+        float2 pre = pre_phase<-1>(f1, tb.tr_a[n]);
+        const float2 rot = tb.tr_rot[n];
         const float alpha = tb.tr_alpha[n];
-        const float2 v = make_float2(fmaf(alpha, a1.x - a0.x, a0.x), fmaf(alpha, a1.y - a0.y, a0.y));
-        dhat[(size_t)tb.tr_row[n] * dm.nf + f] = cmul(v, pre_phase<-1>(f, tb.tr_a[n]));
+        float2* dst = dhat + (size_t)tb.tr_row[n] * dm.nf + f1;
+#pragma unroll
+        for (int k = 0; k < kFpt; ++k) {
+          if (k < fpt && f1 + k < (unsigned)dm.nf) {
+            const KernelPoint kp = kernel_point<W>((unsigned)(t >> 32), dm.mg);
+            const Cell* g0 = G0 + (fl0 + k) * ldr + kp.base;
+            const Cell* g1 = G1 + (fl0 + k) * ldr + kp.base;
+            float2 a0 = make_float2(0.f, 0.f), a1 = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int tp = 0; tp < W; ++tp) {
+              const float ph = grid_tap<W>(fmaf((float)tp, -2.0f / (float)W, kp.z0), dm.cbeta);
+              const float2 v0 = dec_cell<GD>(g0[tp]), v1 = dec_cell<GD>(g1[tp]);
+              a0.x = fmaf(ph, v0.x, a0.x);
+              a0.y = fmaf(ph, v0.y, a0.y);
+              a1.x = fmaf(ph, v1.x, a1.x);
+              a1.y = fmaf(ph, v1.y, a1.y);
+            }
+            const float2 v = make_float2(fmaf(alpha, a1.x - a0.x, a0.x), fmaf(alpha, a1.y - a0.y, a0.y));
+            dst[k] = cmul(v, pre);
+          }
+          pre = cmul(pre, rot);
+          t += bfix;
+        }
       }
       __syncthreads();
     }
@@ -260,9 +292,20 @@ __global__ __launch_bounds__(kBlockG) __attribute__((amdgpu_waves_per_eu(6))) vo
 // traces that reach the slice (bin s with weight 1 - alpha, bin s-1 mod ntheta
 // with weight alpha), the weight times max_f (|Re Dh| + |Im Dh|) of the trace:
 // an upper bound of every cell sum of the slice, the kernel being <= 1.
+//
+// The rounding is floor(x + 1/2) (one v_cvt_rpi_i32_f32), and the sign extension of the low
+// field is folded into the high field: (hi, lo) = (b + (a >> 31), a) is the 64-bit value
+// sext(a) + 2^32 b.
+__device__ __forceinline__ int round_half_up(float x) {
+  int r;
+  asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+  return r;
+}
+
 __device__ __forceinline__ unsigned long long pack_fix(float x, float y) {
-  const int a = __float2int_rn(x), b = __float2int_rn(y);
-  return (unsigned long long)(long long)a + ((unsigned long long)(unsigned)b << 32);
+  const int a = round_half_up(x), b = round_half_up(y);
+  const unsigned hi = (unsigned)b + (unsigned)(a >> 31);
+  return ((unsigned long long)hi << 32) | (unsigned)a;
 }
 
 __device__ __forceinline__ float2 unpack_fix(unsigned long long v, float inv_s) {
@@ -297,24 +340,44 @@ __device__ __forceinline__ void spread_bin(unsigned long long* lo, unsigned long
   const int ldr = dm.ldr;
   const int ft = dm.ft;
   const int cnt = c_end - c_begin;
-  for (int it = threadIdx.x; it < cnt * ft; it += kBlockG) {
-    const int n = c_begin + (it >> ftl);
-    const int fl = it & (ft - 1);
-    const unsigned f = (unsigned)(f0 + fl);
-    if (f >= (unsigned)dm.nf) continue;
-    const float2 dv = dhat[(size_t)tb.tr_row[n] * dm.nf + f];
-    const float2 s = cmul(dv, pre_phase<1>(f, tb.tr_a[n]));
-    const KernelPoint kp = kernel_point<W>(f, tb.tr_b[n], dm.mg);
-    const float alpha = tb.tr_alpha[n];
-    const float2 s1 = cscale(s, alpha * S_hi);
-    const float2 s0 = cscale(s, (1.0f - alpha) * S_lo);
-    unsigned long long* g0 = HAS_LO ? lo + fl * ldr + kp.base : nullptr;
-    unsigned long long* g1 = HAS_HI ? hi + fl * ldr + kp.base : nullptr;
+  const int fpt = ft >= kFpt ? kFpt : ft;
+  const int gpt = ft / fpt;
+  const int gpl = ft >= kFpt ? ftl - 2 : 0;
+  for (int it = threadIdx.x; it < cnt * gpt; it += kBlockG) {
+    const int n = c_begin + (it >> gpl);
+    const int fl0 = (it & (gpt - 1)) * fpt;
+    const unsigned f1 = (unsigned)(f0 + fl0);
+    if (f1 >= (unsigned)dm.nf) continue;
+    const float2* src = dhat + (size_t)tb.tr_row[n] * dm.nf + f1;
+    float2 dv[kFpt];
 #pragma unroll
-    for (int t = 0; t < W; ++t) {
-      const float ph = grid_tap<W>(fmaf((float)t, -2.0f / (float)W, kp.z0), dm.cbeta);
-      if (HAS_LO) atomicAdd(g0 + t, pack_fix(ph * s0.x, ph * s0.y));
-      if (HAS_HI) atomicAdd(g1 + t, pack_fix(ph * s1.x, ph * s1.y));
+    for (int k = 0; k < kFpt; ++k)
+      dv[k] = (k < fpt && f1 + k < (unsigned)dm.nf) ? src[k] : make_float2(0.f, 0.f);
+    const unsigned long long bfix = tb.tr_b[n];
+    unsigned long long t = fix_mul(f1, bfix);
+    float2 pre = pre_phase<1>(f1, tb.tr_a[n]);
+    const float2 r = tb.tr_rot[n];
+    const float2 rot = make_float2(r.x, -r.y);
+    const float alpha = tb.tr_alpha[n];
+    const float sh = alpha * S_hi, sl = (1.0f - alpha) * S_lo;
+#pragma unroll
+    for (int k = 0; k < kFpt; ++k) {
+      if (k < fpt && f1 + k < (unsigned)dm.nf) {
+        const float2 sv = cmul(dv[k], pre);
+        const KernelPoint kp = kernel_point<W>((unsigned)(t >> 32), dm.mg);
+        const float2 s1 = cscale(sv, sh);
+        const float2 s0 = cscale(sv, sl);
+        unsigned long long* g0 = HAS_LO ? lo + (fl0 + k) * ldr + kp.base : nullptr;
+        unsigned long long* g1 = HAS_HI ? hi + (fl0 + k) * ldr + kp.base : nullptr;
+#pragma unroll
+        for (int tp = 0; tp < W; ++tp) {
+          const float ph = grid_tap<W>(fmaf((float)tp, -2.0f / (float)W, kp.z0), dm.cbeta);
+          if (HAS_LO) atomicAdd(g0 + tp, pack_fix(ph * s0.x, ph * s0.y));
+          if (HAS_HI) atomicAdd(g1 + tp, pack_fix(ph * s1.x, ph * s1.y));
+        }
+      }
+      pre = cmul(pre, rot);
+      t += bfix;
     }
   }
   __syncthreads();

@@ -832,6 +832,7 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
   std::vector<int> tr_row(dm.ntr), bin_ptr((size_t)batch * (prm.ntheta + 1)), gather_of_row(dm.ntr);
   std::vector<unsigned long long> tr_b(dm.ntr), tr_a(dm.ntr);
   std::vector<float> tr_alpha(dm.ntr);
+  std::vector<float2> tr_rot(dm.ntr);
   std::vector<double> tr_h2(dm.ntr);
   std::vector<int> jbin(dm.ntr);
   std::vector<double> alpha(dm.ntr);
@@ -862,6 +863,11 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
       tr_row[pos] = n;
       tr_b[pos] = to_fix64(dq * h2 / (dm.nfft * dts));
       tr_a[pos] = to_fix64(qc * h2 / (dm.nfft * dts));
+      {
+        const double fa = qc * h2 / (dm.nfft * dts);
+        const double rev = fa - std::floor(fa);
+        tr_rot[pos] = make_float2((float)std::cos(2.0 * M_PI * rev), (float)-std::sin(2.0 * M_PI * rev));
+      }
       tr_alpha[pos] = (float)alpha[n];
       tr_h2[pos] = h2;
       gather_of_row[n] = b;
@@ -886,6 +892,7 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
   }
   TRY(upload(P, tr_row, &tb.tr_row)); TRY(upload(P, tr_b, &tb.tr_b)); TRY(upload(P, tr_a, &tb.tr_a));
   TRY(upload(P, tr_alpha, &tb.tr_alpha)); TRY(upload(P, bin_ptr, &tb.bin_ptr));
+  TRY(upload(P, tr_rot, &tb.tr_rot));
   TRY(upload(P, tr_h2, &tb.tr_h2));
   TRY(upload(P, gather_of_row, &tb.gather_of_row));
   std::vector<int64_t> tp(P.trace_ptr);

@@ -59,3 +59,36 @@ def oracle_solver_params(geom: Geometry, d: np.ndarray, seed: int = 0):
     rng = np.random.default_rng(seed)
     n2 = fista.power_norm2(L, Lt, rng.standard_normal((geom.ntheta, geom.nq, geom.ntau)), 30)
     return fista.lambda_rule(Lt, d), fista.step_from_norm2(n2), n2
+
+
+# ------------------------------------------------------------------ oracle work in worker processes
+# The oracle's work for independent gathers runs in a pool of fresh interpreters (spawned, so they
+# hold no GPU state), one BLAS thread each, so that the GPU tests' host time stays bounded.
+def _one_thread():
+    from threadpoolctl import threadpool_limits
+    threadpool_limits(1)
+
+
+def oracle_pool(fn, cases, workers: int = 8):
+    """[fn(*case) for case in cases], computed in up to `workers` spawned processes."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    cases = list(cases)
+    if len(cases) <= 1:
+        return [fn(*c) for c in cases]
+    ctx = mp.get_context('spawn')
+    with ProcessPoolExecutor(max_workers=min(workers, len(cases)), mp_context=ctx, initializer=_one_thread) as ex:
+        return list(ex.map(fn, *zip(*cases)))
+
+
+def oracle_pair(geom: Geometry, m: np.ndarray, d: np.ndarray):
+    """(L m, L^T d) of one gather by the oracle."""
+    return gfst.forward(m, geom), gfst.adjoint(d, geom)
+
+
+def oracle_fista_case(geom: Geometry, d: np.ndarray, n_iter: int, ista: bool, seed: int = 0):
+    """Oracle lambda, gamma and the n_iter-th FISTA (or ISTA) iterate of one gather."""
+    lam, gam, _ = oracle_solver_params(geom, d, seed)
+    L = lambda v: gfst.forward(v, geom)
+    Lt = lambda v: gfst.adjoint(v, geom)
+    return lam, gam, fista.solve(L, Lt, d, lam, gam, n_iter, momentum=not ista)
