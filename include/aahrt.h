@@ -87,6 +87,12 @@ typedef struct aahrt_params {
                             sigma-oversampled grid, no deapodisation (low accuracy, reported only) */
   int32_t freq_tile;     /* frequencies per work item of the GFST stage (power of 2, 1..64); 0 -> autotune */
   int32_t grid_dtype;    /* aahrt_grid_dtype */
+  int32_t gfst_kind;     /* 0: GFST kernels with every azimuth slice of a frequency tile resident in LDS where
+                            they apply (FP32 q-grid of 64, 128 or 256 cells that fits), else the slice sweep;
+                            1: always the slice sweep.  The two differ only in the FP32 rounding of the q-grid
+                            transform; the tile changes no result within a kind */
+  int32_t block_threads; /* threads per workgroup of the resident-slice GFST kernels: 512 or 1024; 0 -> autotune
+                            (the slice sweep always uses 512); changes no result */
 } aahrt_params;
 
 typedef struct aahrt_plan aahrt_plan;
@@ -109,8 +115,11 @@ typedef struct aahrt_plan_info {
   int32_t autotune_candidates; /* GFST settings timed at plan creation (0: none, the setting was fixed) */
   double autotune_seconds;     /* wall time of that autotuning */
   int32_t freq_tile_adjoint;   /* frequencies per work item of the adjoint GFST kernel (spreading) */
+  int32_t gfst_resident;       /* 1 if the resident-slice GFST kernels run, 0 for the slice sweep */
   double nufft_error_estimate; /* estimated relative error of one q nonuniform FFT at the chosen setting
                                   (kernel truncation and FP32 rounding; 1 for kernel_width = 2) */
+  int32_t block_threads;         /* threads per workgroup of the forward GFST kernel */
+  int32_t block_threads_adjoint; /* threads per workgroup of the adjoint GFST kernel */
 } aahrt_plan_info;
 
 /* Version string of the library. */
@@ -134,13 +143,14 @@ const char* aahrt_last_error(void);
  * kernel's truncation error (computed in FP64 for white mode coefficients) and an FP32
  * rounding term that grows with the range of the deapodisation; in FP32 it keeps
  * sigma = 1.25 above about 6e-6 and sigma = 1.5 above about 1.1e-6, so at the default
- * tolerance only sigma = 2 is admitted.  When sigma or freq_tile is 0 it then autotunes
- * the GFST stage: every admissible (sigma in {2, 1.5, 1.25}, freq_tile in {4, 8, 16, 32})
- * setting is timed on the interpolation and on the spreading launch over the batch (on
- * zeroed spectra, in a stream of its own, synchronously); each kernel keeps its fastest
- * tile and the sigma with the smallest sum is kept, the default sigma = 2 unless another
- * is at least 5% faster.  The tiles change no result; sigma changes results within the
- * tolerance.
+ * tolerance only sigma = 2 is admitted.  When sigma, freq_tile or block_threads is 0 it
+ * then autotunes the GFST stage: every admissible setting (sigma in {2, 1.5, 1.25}; for the
+ * resident-slice kernels freq_tile in {1, 2, 4, 8} and block_threads in {512, 1024}, for the
+ * slice sweep freq_tile in {4, 8, 16, 32}) is timed on the interpolation and on the
+ * spreading launch over the batch (on zeroed spectra, in a stream of its own,
+ * synchronously); each kernel keeps its fastest tile and workgroup size, and the sigma with
+ * the smallest sum is kept, the default sigma = 2 unless another is at least 5% faster.
+ * Tiles and workgroup sizes change no result; sigma changes results within the tolerance.
  */
 int aahrt_plan_create(aahrt_plan** out, const aahrt_params* p, int32_t batch,
                       const int64_t* trace_ptr, const double* x_km, const double* y_km,

@@ -34,7 +34,8 @@ class Params(ctypes.Structure):
                 ('ntheta', ctypes.c_int32), ('stretch', ctypes.c_int32), ('nfft', ctypes.c_int32),
                 ('nufft_tol', ctypes.c_double), ('sigma', ctypes.c_double),
                 ('kernel_width', ctypes.c_int32), ('freq_tile', ctypes.c_int32),
-                ('grid_dtype', ctypes.c_int32)]
+                ('grid_dtype', ctypes.c_int32), ('gfst_kind', ctypes.c_int32),
+                ('block_threads', ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -45,7 +46,8 @@ class PlanInfo(ctypes.Structure):
                 ('freq_tile', ctypes.c_int32), ('workspace_bytes', ctypes.c_int64),
                 ('q_alias_ok', ctypes.c_int32), ('autotune_candidates', ctypes.c_int32),
                 ('autotune_seconds', ctypes.c_double), ('freq_tile_adjoint', ctypes.c_int32),
-                ('nufft_error_estimate', ctypes.c_double)]
+                ('gfst_resident', ctypes.c_int32), ('nufft_error_estimate', ctypes.c_double),
+                ('block_threads', ctypes.c_int32), ('block_threads_adjoint', ctypes.c_int32)]
 
 
 class AahrtError(RuntimeError):

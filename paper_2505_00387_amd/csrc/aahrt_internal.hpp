@@ -72,6 +72,7 @@ struct Tables {
   const unsigned long long* tr_a;      // frac(q_c h^2/(N dt')) as 0.64 fixed point
   const float* tr_alpha;               // azimuth weight on the upper bin
   const float2* tr_rot;                // exp(-2 pi i frac(q_c h^2/(N dt'))), the pre-phase step per frequency
+  const int* tr_bin;                   // lower azimuth bin j_n of the trace
   const int* bin_ptr;                  // [batch][ntheta+1] positions into the bin-ordered arrays
   const int* gather_of_row;            // data row -> gather
   const float* wav;                    // wavelet taps (deconvolutive operator), or null
@@ -96,6 +97,9 @@ struct Dims {
   int qhalf;    // nq/2 (mode offset)
   int gdt;      // storage of the forward q-grid (aahrt_grid_dtype)
   int nw, wc;   // wavelet of the deconvolutive operator: taps and origin (nw = 0: none)
+  int res;      // 1: GFST kernels with every azimuth slice resident in LDS (q-grid of 64, 128 or 256 cells)
+  int poly;     // 1: kernel taps by the per-tap polynomials (w >= 5, sigma >= 2 shape)
+  int bsz;      // threads per workgroup of the resident GFST kernels (512 or 1024; set per launch)
 };
 
 // Algorithm 2 of Section 3.2 on a regular offset grid x_m = x0 + m dx, y_n = y0 + n dy.
@@ -150,6 +154,8 @@ struct Plan {
   float2* twgrid_dev = nullptr;  // [mg] q-grid twiddles of the current setting
   int ft_interp = 16;            // frequency tile of the interpolation kernel
   int ft_spread = 16;            // frequency tile of the spreading kernel
+  int bs_interp = kBlockG;       // workgroup threads of the interpolation kernel
+  int bs_spread = kBlockG;       // workgroup threads of the spreading kernel
   std::vector<float> tune_ms;    // GFST stage time of each autotune candidate
   int tune_choice = 0;
   double autotune_s = 0.0;
@@ -194,6 +200,13 @@ __host__ __device__ inline size_t interp_lds_f2(int ft, int ldr, int ntheta, int
 __host__ __device__ inline size_t spread_lds_f2(int ft, int ldr, int mg) {
   return 2 * (size_t)ft * ldr + mg;
 }
+// Resident-slice kernels: every slice of the tile ([ntheta][ft][ldr] cells) and the q-grid
+// twiddles (the spreading kernel adds one float per slice for its scales).
+__host__ __device__ inline size_t res_lds_f2(int ft, int ldr, int ntheta, int mg) {
+  return (size_t)ntheta * ft * ldr + mg;
+}
+// Lanes per q-grid row of the resident kernels' register transform (mg = 64, 128, 256).
+__host__ __device__ inline int res_lanes(int mg) { return mg == 256 ? 16 : 8; }
 
 // ---- kernels (kernels.hip) ----
 hipError_t launch_model_r2c(const Plan& p, const float* m, float2* mhat, hipStream_t s);

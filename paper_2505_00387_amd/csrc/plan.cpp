@@ -306,6 +306,9 @@ int validate_params(const aahrt_params& q) {
     return bad("freq_tile must be 0 or a power of two in 1..64");
   if (q.grid_dtype != AAHRT_GRID_F32 && q.grid_dtype != AAHRT_GRID_F16 && q.grid_dtype != AAHRT_GRID_BF16)
     return bad("grid_dtype must be 0, 1 or 2");
+  if (q.gfst_kind < 0 || q.gfst_kind > 1) return bad("gfst_kind must be 0 or 1");
+  if (q.block_threads != 0 && q.block_threads != 512 && q.block_threads != 1024)
+    return bad("block_threads must be 0, 512 or 1024");
   return AAHRT_OK;
 }
 
@@ -320,12 +323,20 @@ size_t grid_lds(int ft, int ldr, int ntheta, int mg, int gdt) {
 struct NufftChoice {
   int mg, w, ft;
   double est;
+  int res;  // 1: resident-slice kernels
+  int bs;   // threads per workgroup (512 or 1024 for the resident kernels, else kBlockG)
 };
 
 // Shape parameter of the exponential-of-semicircle kernel, beta = 0.98 pi (1 - 1/(2 sigma)) w:
 // the rule of Barnett, Magland and af Klinteberg (SIAM J. Sci. Comput. 41, 2019) for the
-// width of the kernel's spectrum at oversampling sigma (2.31 w at sigma = 2).
-double es_beta(double sigma, int w) { return 0.98 * M_PI * (1.0 - 1.0 / (2.0 * sigma)) * w; }
+// width of the kernel's spectrum at oversampling sigma (2.31 w at sigma = 2).  Above
+// sigma = 2 the sigma = 2 shape is kept: a larger grid only lowers its aliasing, the width
+// rule measures the result, and the kernels then evaluate the taps by the per-tap
+// polynomials fitted to that shape (es_poly.hpp).
+double es_beta(double sigma, int w) {
+  const double s = std::min(sigma, 2.0);
+  return 0.98 * M_PI * (1.0 - 1.0 / (2.0 * s)) * w;
+}
 
 // Estimated relative error of one q nonuniform FFT (white mode coefficients) at grid length
 // mg, kernel width w and shape beta, as the root sum of squares of two parts:
@@ -403,6 +414,21 @@ int slot_row(int mg, int w) {
   return ldr % 2 == 0 ? ldr + 1 : ldr;
 }
 
+// Row length of the resident-slice layout: the ghost cells and the register transform's
+// padded exchange (mg + L - 1 cells), odd.
+int res_row(int mg, int w) {
+  int ldr = std::max(mg + w - 1, mg + res_lanes(mg) - 1);
+  return ldr % 2 == 0 ? ldr + 1 : ldr;
+}
+
+// The resident-slice kernels cover FP32 q-grids of 64, 128 or 256 cells whose slices for a
+// tile of ft frequencies fit the LDS of a CU.
+bool res_fits(const Dims& dm, int mg, int w, int ft) {
+  if (dm.gdt != AAHRT_GRID_F32 || (mg != 64 && mg != 128 && mg != 256)) return false;
+  const size_t bytes = res_lds_f2(ft, res_row(mg, w), dm.ntheta, mg) * sizeof(float2) + dm.ntheta * sizeof(float);
+  return bytes <= 160 * 1024;
+}
+
 // A setting fits when its LDS fits a CU, its coefficients fit the register prefetch, and
 // every pass of the in-place q-grid transform has at most one butterfly per thread.
 bool choice_fits(const Dims& dm, int mg, int w, int ft) {
@@ -430,7 +456,7 @@ int nufft_candidates(const aahrt_params& prm, const Dims& dm, std::vector<NufftC
   else fts = {16, 8, 32, 4};
   out.clear();
   std::vector<int> seen_mg;
-  NufftChoice fallback{0, 0, 0, 1e300};
+  NufftChoice fallback{0, 0, 0, 1e300, 0, kBlockG};
   for (double sg : sig) {
     const int mg0 = next_smooth_even((long)std::ceil(sg * dm.nq));
     int w = prm.kernel_width, mg = mg0;
@@ -442,7 +468,7 @@ int nufft_candidates(const aahrt_params& prm, const Dims& dm, std::vector<NufftC
       bool meets = false;
       width_for(tol, dm.nq, mg0, &w, &mg, &est, &meets);
       if (!meets && prm.sigma == 0.0) {
-        if (est < fallback.est) fallback = NufftChoice{mg, w, 0, est};
+        if (est < fallback.est) fallback = NufftChoice{mg, w, 0, est, 0, kBlockG};
         continue;
       }
     }
@@ -450,18 +476,36 @@ int nufft_candidates(const aahrt_params& prm, const Dims& dm, std::vector<NufftC
     seen_mg.push_back(mg);
     FftPlan fp;
     if (!make_grid_fft_plan(mg, fp)) continue;
+    // the resident-slice kernels where they apply (unless the sweep is requested), with
+    // tiles of 4, 8, 2 or 1 frequencies in workgroups of 512 or 1024 threads; otherwise the
+    // slice sweep with tiles of 4..32
+    const bool res = prm.gfst_kind != 1 && res_fits(dm, mg, w, 1);
+    if (res) {
+      if (prm.freq_tile != 0) {
+        int ft = prm.freq_tile;
+        while (ft > 1 && !res_fits(dm, mg, w, ft)) ft /= 2;
+        for (int bs : {512, 1024})
+          if (prm.block_threads == 0 || prm.block_threads == bs) out.push_back({mg, w, ft, est, 1, bs});
+      } else {
+        for (int ft : {4, 8, 2, 1})
+          for (int bs : {512, 1024})
+            if (res_fits(dm, mg, w, ft) && (prm.block_threads == 0 || prm.block_threads == bs))
+              out.push_back({mg, w, ft, est, 1, bs});
+      }
+      continue;
+    }
     if (prm.freq_tile != 0) {
       // a requested tile is halved until it fits
       int ft = prm.freq_tile;
       while (ft > 1 && !choice_fits(dm, mg, w, ft)) ft /= 2;
-      if (choice_fits(dm, mg, w, ft)) out.push_back({mg, w, ft, est});
+      if (choice_fits(dm, mg, w, ft)) out.push_back({mg, w, ft, est, 0, kBlockG});
     } else {
       for (int ft : fts)
-        if (choice_fits(dm, mg, w, ft)) out.push_back({mg, w, ft, est});
+        if (choice_fits(dm, mg, w, ft)) out.push_back({mg, w, ft, est, 0, kBlockG});
       if (out.empty() || out.back().mg != mg) {
         int ft = 16;
         while (ft > 1 && !choice_fits(dm, mg, w, ft)) ft /= 2;
-        if (choice_fits(dm, mg, w, ft)) out.push_back({mg, w, ft, est});
+        if (choice_fits(dm, mg, w, ft)) out.push_back({mg, w, ft, est, 0, kBlockG});
       }
     }
   }
@@ -469,7 +513,8 @@ int nufft_candidates(const aahrt_params& prm, const Dims& dm, std::vector<NufftC
     // no free sigma meets the tolerance: the setting with the smallest estimate
     int ft = prm.freq_tile != 0 ? prm.freq_tile : 16;
     while (ft > 1 && !choice_fits(dm, fallback.mg, fallback.w, ft)) ft /= 2;
-    if (choice_fits(dm, fallback.mg, fallback.w, ft)) out.push_back({fallback.mg, fallback.w, ft, fallback.est});
+    if (choice_fits(dm, fallback.mg, fallback.w, ft))
+      out.push_back({fallback.mg, fallback.w, ft, fallback.est, 0, kBlockG});
   }
   if (out.empty()) return fail(AAHRT_E_UNSUPPORTED, "q-grid too large for LDS");
   return AAHRT_OK;
@@ -487,12 +532,17 @@ int set_nufft(Plan& P, const NufftChoice& c) {
   const double beta = es_beta(P.sigma, c.w);
   dm.beta = (float)beta;
   dm.cbeta = (float)(beta / std::log(2.0));
-  dm.ldr = slot_row(c.mg, c.w);
+  dm.res = c.res;
+  dm.poly = (P.sigma >= 2.0 && c.w >= 5) ? 1 : 0;
+  dm.ldr = c.res ? res_row(c.mg, c.w) : slot_row(c.mg, c.w);
   dm.qhalf = dm.nq / 2;
   dm.ft = c.ft;
   dm.nftile = (dm.nf + c.ft - 1) / c.ft;
   P.ft_interp = c.ft;
   P.ft_spread = c.ft;
+  P.bs_interp = c.bs;
+  P.bs_spread = c.bs;
+  dm.bsz = c.bs;
   // deapodisation 1/Phi(2 pi k/mg) of mode k = l - nq/2
   std::vector<float> deapod(dm.nq);
   for (int l = 0; l < dm.nq; ++l) {
@@ -538,8 +588,8 @@ int autotune_nufft(Plan& P, const std::vector<NufftChoice>& cands) {
     }
     return AAHRT_OK;
   };
-  NufftChoice best{0, 0, 0, 0.0};
-  int best_fi = 0, best_fs = 0;
+  NufftChoice best{0, 0, 0, 0.0, 0, kBlockG};
+  int best_fi = 0, best_fs = 0, best_bi = kBlockG, best_bs = kBlockG;
   float best_total = 0.f, default_total = 0.f;
   do {
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
@@ -557,15 +607,15 @@ int autotune_nufft(Plan& P, const std::vector<NufftChoice>& cands) {
       // candidates of one oversampling are consecutive
       size_t j = i;
       float bi = 0.f, bs = 0.f;
-      int fi = 0, fs = 0;
+      int fi = 0, fs = 0, ni = kBlockG, ns = kBlockG;
       for (; j < cands.size() && cands[j].mg == cands[i].mg && rc == AAHRT_OK; ++j) {
         if ((rc = set_nufft(P, cands[j])) != AAHRT_OK) break;
         float ti = 0.f, ts = 0.f;
         if ((rc = run(0, &ti)) != AAHRT_OK || (rc = run(1, &ts)) != AAHRT_OK) break;
         P.tune_ms.push_back(ti);
         P.tune_ms.push_back(ts);
-        if (j == i || ti < bi) { bi = ti; fi = cands[j].ft; }
-        if (j == i || ts < bs) { bs = ts; fs = cands[j].ft; }
+        if (j == i || ti < bi) { bi = ti; fi = cands[j].ft; ni = cands[j].bs; }
+        if (j == i || ts < bs) { bs = ts; fs = cands[j].ft; ns = cands[j].bs; }
       }
       if (rc != AAHRT_OK) break;
       // another oversampling (which changes results within the tolerance) replaces the
@@ -575,6 +625,8 @@ int autotune_nufft(Plan& P, const std::vector<NufftChoice>& cands) {
         best = cands[i];
         best_fi = fi;
         best_fs = fs;
+        best_bi = ni;
+        best_bs = ns;
         best_total = bi + bs;
       }
       i = j;
@@ -587,6 +639,8 @@ int autotune_nufft(Plan& P, const std::vector<NufftChoice>& cands) {
   TRY(set_nufft(P, best));
   P.ft_interp = best_fi;
   P.ft_spread = best_fs;
+  P.bs_interp = best_bi;
+  P.bs_spread = best_bs;
   P.autotune_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   return AAHRT_OK;
 }
@@ -765,6 +819,8 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
   dm.gdt = prm.grid_dtype;
   dm.nw = 0;
   dm.wc = 0;
+  dm.res = 0;
+  dm.poly = 0;
   P.tb.wav = nullptr;
   std::vector<NufftChoice> cands;
   TRY(nufft_candidates(prm, dm, cands));
@@ -833,6 +889,7 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
   std::vector<unsigned long long> tr_b(dm.ntr), tr_a(dm.ntr);
   std::vector<float> tr_alpha(dm.ntr);
   std::vector<float2> tr_rot(dm.ntr);
+  std::vector<int> tr_bin(dm.ntr);
   std::vector<double> tr_h2(dm.ntr);
   std::vector<int> jbin(dm.ntr);
   std::vector<double> alpha(dm.ntr);
@@ -869,6 +926,7 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
         tr_rot[pos] = make_float2((float)std::cos(2.0 * M_PI * rev), (float)-std::sin(2.0 * M_PI * rev));
       }
       tr_alpha[pos] = (float)alpha[n];
+      tr_bin[pos] = j;
       tr_h2[pos] = h2;
       gather_of_row[n] = b;
     }
@@ -893,6 +951,7 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
   TRY(upload(P, tr_row, &tb.tr_row)); TRY(upload(P, tr_b, &tb.tr_b)); TRY(upload(P, tr_a, &tb.tr_a));
   TRY(upload(P, tr_alpha, &tb.tr_alpha)); TRY(upload(P, bin_ptr, &tb.bin_ptr));
   TRY(upload(P, tr_rot, &tb.tr_rot));
+  TRY(upload(P, tr_bin, &tb.tr_bin));
   TRY(upload(P, tr_h2, &tb.tr_h2));
   TRY(upload(P, gather_of_row, &tb.gather_of_row));
   std::vector<int64_t> tp(P.trace_ptr);
@@ -1114,6 +1173,9 @@ int aahrt_plan_query(const aahrt_plan* plan, aahrt_plan_info* info) {
   info->autotune_candidates = (int32_t)P.tune_ms.size();
   info->autotune_seconds = P.autotune_s;
   info->nufft_error_estimate = P.nufft_est;
+  info->gfst_resident = P.dm.res;
+  info->block_threads = P.bs_interp;
+  info->block_threads_adjoint = P.bs_spread;
   return AAHRT_OK;
 }
 

@@ -238,7 +238,8 @@ def test_grid_precision_sweep_large():
     four stored gathers of the 4096-trace, N = 12000 workload, solved as one batch: relative
     data error of L m on six traces per gather against the stored oracle values, per storage
     type.  FP32 is held to the bound; the 16-bit grids are reported, with loose sanity limits.
-    The adjoint does not use the 16-bit grid and is bitwise the same for every storage type."""
+    The adjoint does not use the 16-bit grid and is bitwise the same for every storage type (all
+    three plans run the slice-sweep kernels: the resident-slice kernels hold FP32 grids only)."""
     ref = _config5_reference()
     w5 = wl.config5(with_data=False)
     picks = [int(b) for b in ref['gathers']]
@@ -249,7 +250,7 @@ def test_grid_precision_sweep_large():
     tp = w.trace_ptr
     errs, adj = {}, {}
     for gd, name in ((0, 'fp32'), (1, 'fp16'), (2, 'bf16')):
-        plan = make_plan(w, nfft=int(ref['nfft']), sigma=2.0, freq_tile=8, grid_dtype=gd)
+        plan = make_plan(w, nfft=int(ref['nfft']), sigma=2.0, freq_tile=8, grid_dtype=gd, gfst_kind=1)
         got = to_host(plan.forward(to_dev(m)))
         adj[name] = to_host(plan.adjoint(to_dev(d)))
         errs[name] = max(rel(got[tp[i] + ref['trace_idx'][i]], ref['forward'][i]) for i in range(w.batch))
@@ -305,19 +306,50 @@ def test_width_rule_admits_only_settings_that_meet_the_tolerance():
         plan.close()
 
 
-def test_frequency_tile_changes_no_result():
-    """The tile only regroups frequencies: forward and adjoint are bitwise equal across tiles."""
+@pytest.mark.parametrize('kind', [0, 1])
+def test_frequency_tile_changes_no_result(kind):
+    """The tile and the workgroup size only regroup frequencies and traces: forward and adjoint
+    are bitwise equal across them, for the resident-slice kernels (kind 0 here) and for the
+    slice sweep (kind 1)."""
     w = wl.config3(with_data=False)
     m = to_dev(wl.random_model(w.axes, w.batch, 9))
     d = to_dev(wl.random_data(int(w.trace_ptr[-1]), w.axes.nt, 9))
     outs = []
-    for ft in (4, 16, 32):
-        plan = make_plan(w, sigma=2.0, freq_tile=ft)
+    cases = ((1, 512), (4, 1024), (8, 512), (8, 1024), (2, 1024)) if kind == 0 else ((4, 0), (16, 0), (32, 0))
+    for ft, bs in cases:
+        plan = make_plan(w, sigma=2.0, freq_tile=ft, gfst_kind=kind, block_threads=bs)
         assert plan.info['freq_tile'] == ft and plan.info['autotune_candidates'] == 0
+        assert plan.info['gfst_resident'] == (1 - kind)
+        assert plan.info['block_threads'] == (bs or 512) == plan.info['block_threads_adjoint']
         outs.append((to_host(plan.forward(m)), to_host(plan.adjoint(d))))
         plan.close()
     for o in outs[1:]:
         assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
+
+
+@pytest.mark.parametrize('config', [2, 3])
+def test_resident_and_sweep_kernels_agree(config):
+    """The resident-slice GFST kernels and the slice sweep compute the same operator: they differ
+    only in the FP32 rounding of the q-grid transform (relative difference near 1e-7), and both
+    meet the bound against the oracle (L, L^T on every gather)."""
+    w = wl.CONFIGS[config](with_data=False)
+    res = {}
+    for kind in (0, 1):
+        errs, info = _op_parity(w, seed=12, with_info=True, sigma=2.0, gfst_kind=kind)
+        assert info['gfst_resident'] == 1 - kind
+        res[kind] = errs
+        print(f'config {config} kind {kind}:', [f'{a:.1e}/{b:.1e}' for a, b in errs])
+        for ef, ea in errs:
+            assert ef < TOL and ea < TOL
+    plans = [make_plan(w, sigma=2.0, gfst_kind=k) for k in (0, 1)]
+    m = to_dev(wl.random_model(w.axes, w.batch, 13))
+    d = to_dev(wl.random_data(int(w.trace_ptr[-1]), w.axes.nt, 13))
+    fw = [to_host(p.forward(m)) for p in plans]
+    ad = [to_host(p.adjoint(d)) for p in plans]
+    print(f'resident vs sweep: forward {rel(fw[0], fw[1]):.2e} adjoint {rel(ad[0], ad[1]):.2e}')
+    assert rel(fw[0], fw[1]) < 2e-6 and rel(ad[0], ad[1]) < 2e-6
+    for p in plans:
+        p.close()
 
 
 def test_autotuner_times_the_candidates():
@@ -331,7 +363,10 @@ def test_autotuner_times_the_candidates():
     assert info['autotune_candidates'] >= 6          # interpolation and spreading, three tiles or more
     assert info['sigma'] == 2.0 and info['kernel_width'] == 8
     assert info['nufft_error_estimate'] <= 1e-6
-    assert info['freq_tile'] in (4, 8, 16, 32) and info['freq_tile_adjoint'] in (4, 8, 16, 32)
+    tiles = (1, 2, 4, 8) if info['gfst_resident'] else (4, 8, 16, 32)
+    assert info['freq_tile'] in tiles and info['freq_tile_adjoint'] in tiles
+    sizes = (512, 1024) if info['gfst_resident'] else (512,)
+    assert info['block_threads'] in sizes and info['block_threads_adjoint'] in sizes
     plan.close()
     # a looser tolerance admits the narrower grids, which are then timed as well
     plan = make_plan(w, nufft_tol=1e-4)
