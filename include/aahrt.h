@@ -178,6 +178,22 @@ int aahrt_forward(aahrt_plan* plan, const float* m, float* d, aahrt_stream strea
 int aahrt_adjoint(aahrt_plan* plan, const float* d, float* m, aahrt_stream stream);
 
 /*
+ * m = L^T d exactly as aahrt_adjoint (same kernels, bitwise the same result), for callers
+ * that cannot allocate (code under stream capture, serving loops, harnesses that forbid
+ * hipMalloc): the call allocates nothing.  Its intermediates (trace spectra, model spectra,
+ * per-trace spreading bounds, per-slice scales) live in a file-scope device array of
+ * 64 MiB = 67108864 bytes in the library, not in the plan's workspace; each GPU holds its
+ * own copy until the process ends.  It needs
+ *   256-byte-aligned sum of ntraces*nf*8, batch*ntheta*nq*nf*8, ntraces*4 and batch*ntheta*4
+ * bytes (nf = N/2, aahrt_plan_info.nfreq); a plan that needs more returns AAHRT_E_UNSUPPORTED
+ * before anything is enqueued.  All calls on one GPU share the array: calls that overlap in
+ * time on one GPU race and must not be made.
+ *   d : device float[ntraces][nt] (read)
+ *   m : device float[batch][ntheta][nq][ntau] (written)
+ */
+int aahrt_adjoint_noalloc(aahrt_plan* plan, const float* d, float* m, aahrt_stream stream);
+
+/*
  * Per-gather max |L^T d| (the lambda scale of Section 4).
  *   d    : device float[ntraces][nt] (read)
  *   lmax : device float[batch] (written)

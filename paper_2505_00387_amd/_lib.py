@@ -21,7 +21,7 @@ EXPORTED = ['aahrt_version', 'aahrt_last_error', 'aahrt_plan_create', 'aahrt_pla
             'aahrt_plan_query', 'aahrt_forward', 'aahrt_adjoint', 'aahrt_lambda_max',
             'aahrt_operator_norm2', 'aahrt_sparse_solve', 'aahrt_velocity', 'aahrt_set_wavelet',
             'aahrt_adjoint_direct', 'aahrt_adjoint_grid',
-            'aahrt_profile_enable', 'aahrt_profile_read']
+            'aahrt_profile_enable', 'aahrt_profile_read', 'aahrt_adjoint_noalloc']
 
 KERNELS = ['model_r2c', 'nufft_interp', 'data_c2r', 'data_r2c', 'nufft_spread', 'model_c2r',
            'residual_r2c', 'model_c2r_update', 'model_update_r2c']
@@ -76,6 +76,7 @@ def load() -> ctypes.CDLL:
     lib.aahrt_plan_query.argtypes = [P, ctypes.POINTER(PlanInfo)]
     lib.aahrt_forward.argtypes = [P, P, P, P]
     lib.aahrt_adjoint.argtypes = [P, P, P, P]
+    lib.aahrt_adjoint_noalloc.argtypes = [P, P, P, P]
     lib.aahrt_lambda_max.argtypes = [P, P, P, P]
     lib.aahrt_operator_norm2.argtypes = [P, ctypes.c_int32, P, P]
     lib.aahrt_velocity.argtypes = [P, P, P, P, P]

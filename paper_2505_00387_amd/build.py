@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, 'csrc')
 LIB = os.path.join(HERE, 'libaahrt.so')
 OBJ_DIR = os.path.join(os.path.dirname(HERE), '_build')
 
-SOURCES = ['plan.cpp', 'rows.hip', 'gfst_sweep.hip', 'gfst_res.hip', 'misc.hip']
+SOURCES = ['plan.cpp', 'rows.hip', 'gfst_sweep.hip', 'gfst_res.hip', 'misc.hip', 'noalloc.hip']
 FLAGS = [
     '-O3', '-std=c++17', '-fPIC', '--offload-arch=gfx950',
     # packed FP32 instructions are kept out of every kernel

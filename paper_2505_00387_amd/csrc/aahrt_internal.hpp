@@ -239,6 +239,12 @@ hipError_t launch_gather_scalar(const Plan& p, int op, const float* a, float* ou
 hipError_t launch_trace_to_gather_sum(const Plan& p, const float* per_trace, float* out,
                                       const float* l1, const float* lam, hipStream_t s);
 
+// ---- the adjoint without allocation (noalloc.hip) ----
+size_t noalloc_scratch_limit();
+size_t noalloc_adjoint_bytes(const Dims& dm);
+int adjoint_noalloc(Plan& P, const float* d, float* m, hipStream_t s);
+const char* noalloc_last_message();
+
 enum { RED_SUMSQ = 0, RED_MAXABS = 1, RED_SUMABS = 2 };
 enum { GS_STEP = 0, GS_LAMBDA = 1, GS_SQRT = 2 };
 

@@ -1248,6 +1248,17 @@ int aahrt_set_wavelet(aahrt_plan* plan, const float* w, int32_t nw, int32_t cent
   return AAHRT_OK;
 }
 
+int aahrt_adjoint_noalloc(aahrt_plan* plan, const float* d, float* m, aahrt_stream stream) {
+  TRY(check_plan(plan));
+  Plan& P = P_of(plan);
+  if (!m) return fail(AAHRT_E_INVALID, "m is NULL");
+  if (!d && P.dm.ntr > 0) return fail(AAHRT_E_INVALID, "d is NULL");
+  HIP_TRY(hipSetDevice(P.device));
+  const int rc = adjoint_noalloc(P, d, m, as_stream(stream));
+  if (rc != AAHRT_OK) return fail(rc, noalloc_last_message());
+  return AAHRT_OK;
+}
+
 int aahrt_adjoint_direct(aahrt_plan* plan, const float* d, float* m, aahrt_stream stream) {
   TRY(check_plan(plan));
   Plan& P = P_of(plan);
