@@ -75,7 +75,8 @@ def load_traffic(kernel: str, workload: str, gfst: dict):
         return None
     if kernel.startswith('nufft_'):
         cfg = rec.get('gfst_config', {})
-        if any(cfg.get(k) != gfst.get(k) for k in ('grid', 'kernel_width', 'freq_tile', 'freq_tile_adjoint')):
+        if any(cfg.get(k) != gfst.get(k) for k in ('grid', 'kernel_width', 'freq_tile', 'freq_tile_adjoint',
+                                                    'block_threads', 'block_threads_adjoint')):
             return None
     k = rec.get('kernels', {}).get(kernel)
     return None if k is None else k.get('bytes_per_launch')
@@ -531,7 +532,8 @@ def main():
     avg = kernels[dom]['avg_ms']
     ach = kernel_bytes(plan, dom) / (avg * 1e-3) / 1e9
     gfst = {'grid': plan.info['grid_size'], 'kernel_width': plan.info['kernel_width'],
-            'freq_tile': plan.info['freq_tile'], 'freq_tile_adjoint': plan.info['freq_tile_adjoint']}
+            'freq_tile': plan.info['freq_tile'], 'freq_tile_adjoint': plan.info['freq_tile_adjoint'],
+            'block_threads': plan.info['block_threads'], 'block_threads_adjoint': plan.info['block_threads_adjoint']}
     traffic = load_traffic(dom, w.name, gfst)
     roofline = {'bound': 'hbm', 'achieved': round(ach, 1), 'peak': HBM_PEAK_GBS, 'unit': 'GB/s',
                 'frac': round(ach / HBM_PEAK_GBS, 4), 'traffic': traffic, 'kernel': dom,
@@ -551,7 +553,9 @@ def main():
                    'nq': a.nq, 'ntheta': a.ntheta, 'fista_iters': n_iter, 'nfft': plan.info['nfft'],
                    'kernel_width': plan.info['kernel_width'], 'grid': plan.info['grid_size'],
                    'sigma': plan.info['sigma'], 'freq_tile': plan.info['freq_tile'],
-                   'freq_tile_adjoint': plan.info['freq_tile_adjoint']},
+                   'freq_tile_adjoint': plan.info['freq_tile_adjoint'],
+                   'block_threads': plan.info['block_threads'],
+                   'block_threads_adjoint': plan.info['block_threads_adjoint']},
         'roofline': roofline,
         'cpu_baseline': cpu,
         'secondary': {'graph_solve_ms': round(1e3 * t_graph, 2), 'graph_gathers_per_s': round(w.batch / t_graph, 2),
