@@ -39,6 +39,14 @@ struct FftPlan {
 // (passes with more butterflies than threads), by radix.
 __host__ __device__ constexpr int row_kmax(int r) { return r >= 15 ? 2 : (r == 5 ? 5 : 3); }
 
+// Row transforms also compiled with their length and radices as constants (row_ip >= 3):
+// N/2 of the stretched axis and the radices in pass order (each pass one butterfly per thread).
+struct StaticRowSpec {
+  int ip, n, npass, r[3];
+};
+constexpr StaticRowSpec kStaticRows[] = {{3, 2160, 3, {16, 15, 9}}, {4, 480, 3, {16, 15, 2}}};
+constexpr int kRowKinds = 5;  // row_ip 0..4
+
 // Two-tap linear interpolation entry: value = w0 * x[i0] + w1 * x[i1] (dropped taps have weight 0).
 struct __attribute__((aligned(16))) Tap {
   int i0, i1;
@@ -86,7 +94,8 @@ struct Dims {
   int nts;      // nt'
   int nfft, nh, nf;  // N, N/2, bins carried (= N/2)
   int nhp;      // LDS cells of one row FFT buffer: room for the padded first pass
-  int row_ip;   // row FFT in place: 1 = one butterfly per thread per pass, 2 = up to row_kmax; 0 = ping-pong
+  int row_ip;   // row FFT in place: 1 = one butterfly per thread per pass, 2 = up to row_kmax; 0 = ping-pong;
+                // 3, 4: as 1 with the plan of kStaticRows compiled in
   int mg;       // q-grid length
   int ldr;      // LDS row length of a q-grid slot: mg + w - 1 ghost cells, padded to odd
   int w;        // kernel width

@@ -235,6 +235,35 @@ __device__ __forceinline__ void apply_twiddles(float2* v, const float2* __restri
   }
 }
 
+// apply_twiddles with its table reads done ahead: base[0] = tw[step], base[a] = tw[4 a step].
+template <int R, bool INV>
+__device__ __forceinline__ void apply_twiddle_bases(float2* v, const float2* base) {
+  float2 w1 = base[0];
+  if (INV) w1.y = -w1.y;
+  float2 wb[4];
+  wb[0] = make_float2(1.f, 0.f);
+  wb[1] = w1;
+  wb[2] = cmul(w1, w1);
+  wb[3] = cmul(wb[2], w1);
+  float2 w4a = make_float2(1.f, 0.f);
+#pragma unroll
+  for (int r = 1; r < R; ++r) {
+    if ((r & 3) == 0) {
+      w4a = base[r >> 2];
+      if (INV) w4a.y = -w4a.y;
+      v[r] = cmul(v[r], w4a);
+    } else if (r < 4) {
+      v[r] = cmul(v[r], wb[r]);
+    } else {
+      v[r] = cmul(v[r], cmul(w4a, wb[r & 3]));
+    }
+  }
+}
+template <int R>
+__host__ __device__ constexpr int twiddle_bases() {
+  return 1 + (R - 1) / 4;
+}
+
 // Index of element i in a padded buffer: one spare cell after every 16, so
 // the stride-R writes of a first pass (Ns = 1) spread over the LDS banks.
 __host__ __device__ __forceinline__ int pad16(int i) { return i + (i >> 4); }
@@ -381,6 +410,127 @@ __device__ __forceinline__ void fft_lds_ip(float2* buf, const FftPlan& pl, int n
     }
   }
 }
+
+// In-place transform of one sequence of length N with radices Rs... fixed at compile time:
+// the pass of fft_lds_ip with every count, stride and divisor a constant, so the index
+// arithmetic folds into LDS offsets.  Same butterflies and twiddle products as
+// fft_lds_ip, hence the same results.  Passes with a multiple of 16 between the
+// elements of a butterfly address the padded buffer as pad16(first) + r * (step + step/16).
+template <bool INV, int NT, int N, int NPASS, int S, int NS, int R, int... Rest>
+__device__ __forceinline__ void fft_static(float2* buf, const float2* twb) {
+  constexpr int NB = N / R;
+  constexpr bool PIN = NPASS >= 2 && S == 1;
+  constexpr bool POUT = NPASS >= 2 && S == 0;
+  static_assert(NB <= NT && N % R == 0, "one butterfly per thread");
+  const int j = threadIdx.x;
+  const bool act = NB == NT || j < NB;
+  float2 v[R];
+  int o = 0;
+  if (act) {
+    const int jq = j / NS;
+    const int k = j - jq * NS;
+    if constexpr (PIN && NB % 16 == 0) {
+      const float2* x = buf + pad16(j);
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = x[r * (NB + NB / 16)];
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = j + r * NB;
+        v[r] = buf[PIN ? pad16(i) : i];
+      }
+    }
+    if constexpr (NS > 1) apply_twiddle_bases<R, INV>(v, twb);
+    Dft<R, INV>::run(v);
+    o = jq * NS * R + k;
+  }
+  __syncthreads();
+  if (act) {
+    if constexpr (POUT && NS == 1 && R == 16) {
+      float2* y = buf + 17 * j;  // o = 16 j: pad16(o + r) = 17 j + r
+#pragma unroll
+      for (int r = 0; r < R; ++r) y[r] = v[r];
+    } else if constexpr (POUT && NS % 16 == 0) {
+      float2* y = buf + pad16(o);
+#pragma unroll
+      for (int r = 0; r < R; ++r) y[r * (NS + NS / 16)] = v[r];
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = o + r * NS;
+        buf[POUT ? pad16(i) : i] = v[r];
+      }
+    }
+  }
+  __syncthreads();
+  if constexpr (sizeof...(Rest) > 0)
+    fft_static<INV, NT, N, NPASS, S + 1, NS * R, Rest...>(buf, twb + (NS > 1 ? twiddle_bases<R>() : 0));
+}
+
+template <int N, int... Rs>
+struct RowPlan {};
+
+template <int IP>
+struct StaticRowPlan;
+template <>
+struct StaticRowPlan<3> {
+  using type = RowPlan<2160, 16, 15, 9>;
+};
+template <>
+struct StaticRowPlan<4> {
+  using type = RowPlan<480, 16, 15, 2>;
+};
+
+// Twiddle bases of one thread for every pass of a compiled plan (the passes after the
+// first), read from the table once, ahead of both transforms of a row kernel (the forward
+// and inverse transforms use the same bases, conjugated for the inverse).
+template <int N, int NS, int R, int... Rest>
+__host__ __device__ constexpr int plan_bases() {
+  constexpr int here = NS > 1 ? twiddle_bases<R>() : 0;
+  if constexpr (sizeof...(Rest) > 0) return here + plan_bases<N, NS * R, Rest...>();
+  else return here;
+}
+
+template <int N, int NS, int R, int... Rest>
+__device__ __forceinline__ void load_plan_bases(float2* b, const float2* __restrict__ tw, int j) {
+  if constexpr (NS > 1) {
+    constexpr int NB = N / R, STRIDE = N / (NS * R);
+    const int step = (j % NS) * STRIDE;
+    const bool act = NB >= 256 || j < NB;
+#pragma unroll
+    for (int a = 0; a < twiddle_bases<R>(); ++a) b[a] = act ? tw[(a == 0 ? 1 : 4 * a) * step] : make_float2(1.f, 0.f);
+  }
+  if constexpr (sizeof...(Rest) > 0) load_plan_bases<N, NS * R, Rest...>(b + (NS > 1 ? twiddle_bases<R>() : 0), tw, j);
+}
+
+template <typename P>
+struct RowTwiddles;
+template <int N, int... Rs>
+struct RowTwiddles<RowPlan<N, Rs...>> {
+  static constexpr int count = plan_bases<N, 1, Rs...>();
+  float2 b[count > 0 ? count : 1];
+  __device__ __forceinline__ void load(const float2* __restrict__ tw) {
+    load_plan_bases<N, 1, Rs...>(b, tw, threadIdx.x);
+  }
+};
+
+template <bool INV, int NT, int N, int... Rs>
+__device__ __forceinline__ void fft_row_static(float2* buf, const RowTwiddles<RowPlan<N, Rs...>>& twb) {
+  fft_static<INV, NT, N, (int)sizeof...(Rs), 0, 1, Rs...>(buf, twb.b);
+}
+
+// The compiled plans agree with the host's table.
+template <int IP, int N, int... Rs>
+constexpr bool static_row_matches(RowPlan<N, Rs...>) {
+  constexpr int rs[] = {Rs...};
+  const StaticRowSpec& sp = kStaticRows[IP - 3];
+  if (sp.ip != IP || sp.n != N || sp.npass != (int)sizeof...(Rs)) return false;
+  for (int i = 0; i < (int)sizeof...(Rs); ++i)
+    if (sp.r[i] != rs[i]) return false;
+  return true;
+}
+static_assert(static_row_matches<3>(StaticRowPlan<3>::type{}) && static_row_matches<4>(StaticRowPlan<4>::type{}),
+              "compiled row plans match kStaticRows");
 
 // In-place pass of one sequence in which a thread owns K butterflies (j = thread + k NT).
 // Level k reads and transforms butterfly k into registers of its own, then the next level

@@ -121,10 +121,37 @@ __device__ __forceinline__ void pack_transpose(float2* buf, const float* g, cons
 // staging area after it for a real input row; IP = false (long rows whose FFT
 // passes have more butterflies than threads): two ping-pong buffers, the staged
 // input row aliasing the second one before the first pass.
+// Per-thread twiddle bases a row kernel loads at its start for the compiled plans (IP >= 3);
+// nothing for the plans read at run time.
+struct NoRowTwiddles {
+  __device__ __forceinline__ void load(const float2*) {}
+};
+template <int IP>
+struct RowTw {
+  using type = NoRowTwiddles;
+};
+template <>
+struct RowTw<3> {
+  using type = RowTwiddles<StaticRowPlan<3>::type>;
+};
+template <>
+struct RowTw<4> {
+  using type = RowTwiddles<StaticRowPlan<4>::type>;
+};
+template <int IP>
+__device__ __forceinline__ typename RowTw<IP>::type row_twiddles(const Tables& tb) {
+  typename RowTw<IP>::type t;
+  t.load(tb.tw_half);
+  return t;
+}
+
 template <bool INV, int IP>
 __device__ __forceinline__ float2* row_fft(float2* A, float2* B, const FftPlan& fp, const Tables& tb,
-                                           const Dims& dm) {
-  if constexpr (IP == 1) {
+                                           const Dims& dm, const typename RowTw<IP>::type& twb) {
+  if constexpr (IP >= 3) {
+    fft_row_static<INV, kBlock>(A, twb);
+    return A;
+  } else if constexpr (IP == 1) {
     fft_lds_ip<INV, kBlock>(A, fp, 1, 0, tb.tw_half);
     return A;
   } else if constexpr (IP == 2) {
@@ -159,10 +186,11 @@ __device__ __forceinline__ void stretch_pack(float2* A, const float* row, float 
 template <int IP>
 __device__ __forceinline__ const float* model_c2r_core(const float2* mhat, float2* A,
                                                        float2* B, const Tables& tb, const Dims& dm,
-                                                       const FftPlan& fp, size_t rid) {
+                                                       const FftPlan& fp, size_t rid,
+                                                       const typename RowTw<IP>::type& twb) {
   load_packed_c2r(A, mhat + rid * dm.nf, tb, dm);
   __syncthreads();
-  return reinterpret_cast<const float*>(row_fft<true, IP>(A, B, fp, tb, dm));
+  return reinterpret_cast<const float*>(row_fft<true, IP>(A, B, fp, tb, dm, twb));
 }
 
 // ------------------------------------------------------------------ launch helpers
@@ -178,29 +206,32 @@ hipError_t set_lds(K kernel, size_t bytes) {
   return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-// Launch one row kernel: in place (every FFT pass fits the block) with `stage`
-// real samples of staging after the buffer, else the two-buffer form.
-// kip: in place, one butterfly per thread per pass; kipk: in place, several; kpp: ping-pong.
-template <typename KIP, typename KIPK, typename KPP, typename... Args>
-hipError_t launch_row(KIP kip, KIPK kipk, KPP kpp, const Dims& dm, int stage, unsigned grid, hipStream_t s,
-                             Args... args) {
+// The five instantiations of a row kernel, indexed by Dims::row_ip.
+template <typename K>
+struct RowKernels {
+  K k[kRowKinds];
+};
+template <typename K>
+RowKernels<K> row_kernels(K k0, K k1, K k2, K k3, K k4) {
+  return RowKernels<K>{{k0, k1, k2, k3, k4}};
+}
+// AAHRT_ROWK(k_data_c2r, true) -> the kernels k_data_c2r<IP, true> for IP = 0..4
+#define AAHRT_ROWK(K, ...) \
+  row_kernels(&K<0, ##__VA_ARGS__>, &K<1, ##__VA_ARGS__>, &K<2, ##__VA_ARGS__>, &K<3, ##__VA_ARGS__>, &K<4, ##__VA_ARGS__>)
+
+// Launch one row kernel: in place (every FFT pass fits the block) with `stage` real samples
+// of staging after the buffer, else the two-buffer form.
+template <typename K, typename... Args>
+hipError_t launch_row(const RowKernels<K>& ks, const Dims& dm, int stage, unsigned grid, hipStream_t s,
+                      Args... args) {
   if (grid == 0) return hipSuccess;
-  if (dm.row_ip == 1) {
-    const size_t lds = ((size_t)dm.nhp + (size_t)(stage + 5) / 2) * sizeof(float2);  // staging + 4 spare
-    hipError_t e = set_lds(kip, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kip, dim3(grid), dim3(kBlock), lds, s, args...);
-  } else if (dm.row_ip == 2) {
-    const size_t lds = ((size_t)dm.nhp + (size_t)(stage + 5) / 2) * sizeof(float2);
-    hipError_t e = set_lds(kipk, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kipk, dim3(grid), dim3(kBlock), lds, s, args...);
-  } else {
-    const size_t lds = 2 * (size_t)dm.nhp * sizeof(float2);
-    hipError_t e = set_lds(kpp, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kpp, dim3(grid), dim3(kBlock), lds, s, args...);
-  }
+  if (dm.row_ip < 0 || dm.row_ip >= kRowKinds) return hipErrorInvalidValue;
+  const K k = ks.k[dm.row_ip];
+  const size_t lds = dm.row_ip == 0 ? 2 * (size_t)dm.nhp * sizeof(float2)
+                                    : ((size_t)dm.nhp + (size_t)(stage + 5) / 2) * sizeof(float2);  // staging + 4 spare
+  hipError_t e = set_lds(k, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(kBlock), lds, s, args...);
   return hipGetLastError();
 }
 

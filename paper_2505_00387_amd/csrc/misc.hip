@@ -228,7 +228,8 @@ __global__ __launch_bounds__(kBlock) void k_model_c2r_grid(const float2* __restr
                                                            FftPlan fp, const Tap* __restrict__ vtap) {
   extern __shared__ float2 lds[];
   const size_t rid = blockIdx.x;
-  const float* xs = model_c2r_core<IP>(mhat, lds, lds + dm.nhp, tb, dm, fp, rid);
+  const auto twb = row_twiddles<IP>(tb);
+  const float* xs = model_c2r_core<IP>(mhat, lds, lds + dm.nhp, tb, dm, fp, rid, twb);
   const float sc = 1.0f / (float)dm.nfft;
   float* dst = m + rid * dm.ntau;
   for (int i = threadIdx.x; i < dm.ntau; i += kBlock) {
@@ -339,7 +340,7 @@ hipError_t launch_grid_adjoint(const Plan& p, const float* d, float* m, hipStrea
   hipLaunchKernelGGL(k_grid_polar, grid, dim3(kBlock), lds, s, p.dhat, p.mhat, p.gt, dm, p.fft_q, ft, ftl);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return launch_row(k_model_c2r_grid<1>, k_model_c2r_grid<2>, k_model_c2r_grid<0>, dm, 0, model_rows(dm), s, p.mhat, m, p.tb,
+  return launch_row(AAHRT_ROWK(k_model_c2r_grid), dm, 0, model_rows(dm), s, p.mhat, m, p.tb,
                     dm, p.fft_half, p.gt.vtap);
 }
 

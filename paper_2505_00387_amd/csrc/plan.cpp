@@ -812,6 +812,14 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
       dm.row_ip = row_plan_kind(alt);
     }
   }
+  // a plan that is also compiled in with constant sizes (kStaticRows) runs that instantiation
+  if (dm.row_ip == 1) {
+    for (const StaticRowSpec& sp : kStaticRows) {
+      bool same = sp.n == dm.nh && sp.npass == P.fft_half.npass;
+      for (int i = 0; same && i < sp.npass; ++i) same = sp.r[i] == P.fft_half.pass[i].r;
+      if (same) dm.row_ip = sp.ip;
+    }
+  }
 
   // nonuniform FFT parameters: the candidate (sigma, w, ft) list; the first one
   // is built now, the others are timed by the autotuner once the plan is complete

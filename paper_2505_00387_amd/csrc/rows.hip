@@ -32,11 +32,12 @@ __global__ __launch_bounds__(kBlock) void k_model_r2c(const float* __restrict__ 
   const size_t rid = blockIdx.x;
   const int l = (int)(rid % dm.nq);
   const float* src = m + rid * dm.ntau;
+  const auto twb = row_twiddles<IP>(tb);
   for (int i = threadIdx.x; i < dm.ntau; i += kBlock) row[i] = src[i];
   __syncthreads();
   stretch_pack(A, row, tb.deapod[l], tb, dm);
   __syncthreads();
-  const float2* X = row_fft<false, IP>(A, B, fp, tb, dm);
+  const float2* X = row_fft<false, IP>(A, B, fp, tb, dm, twb);
   store_real_spectrum(X, mhat + rid * dm.nf, tb, dm);
 }
 
@@ -47,7 +48,8 @@ __global__ __launch_bounds__(kBlock) void k_model_c2r(const float2* __restrict__
   extern __shared__ float2 lds[];
   const size_t rid = blockIdx.x;
   const int l = (int)(rid % dm.nq);
-  const float* xs = model_c2r_core<IP>(mhat, lds, lds + dm.nhp, tb, dm, fp, rid);
+  const auto twb = row_twiddles<IP>(tb);
+  const float* xs = model_c2r_core<IP>(mhat, lds, lds + dm.nhp, tb, dm, fp, rid, twb);
   const float sc = tb.deapod[l] / (float)dm.nfft;
   float* dst = m + rid * dm.ntau;
   for (int i = threadIdx.x; i < dm.ntau; i += kBlock) {
@@ -87,7 +89,8 @@ __global__ __launch_bounds__(kBlock) void k_model_c2r_update(float2* __restrict_
     yv[k] = i < dm.ntau ? yr[i] : 0.f;
     xv[k] = i < dm.ntau ? xr[i] : 0.f;
   }
-  const float* xs = model_c2r_core<IP>(mhat, A, B, tb, dm, fp, rid);
+  const auto twb = row_twiddles<IP>(tb);
+  const float* xs = model_c2r_core<IP>(mhat, A, B, tb, dm, fp, rid, twb);
   // the new y row is staged after A (in place) or in the buffer not holding xs
   float* stage = IP ? reinterpret_cast<float*>(B)
                     : reinterpret_cast<float*>(xs == reinterpret_cast<const float*>(A) ? B : A);
@@ -121,7 +124,7 @@ __global__ __launch_bounds__(kBlock) void k_model_c2r_update(float2* __restrict_
     float2* other = IP ? B : reinterpret_cast<float2*>(stage);
     stretch_pack(in, stage, tb.deapod[l], tb, dm);
     __syncthreads();
-    const float2* X = row_fft<false, IP>(in, other, fp, tb, dm);
+    const float2* X = row_fft<false, IP>(in, other, fp, tb, dm, twb);
     store_real_spectrum(X, mhat + rid * dm.nf, tb, dm);
   }
 }
@@ -155,9 +158,10 @@ __global__ __launch_bounds__(kBlock) void k_data_c2r(const float2* __restrict__ 
   float2* A = lds;
   float2* B = lds + dm.nhp;
   const size_t n = blockIdx.x;
+  const auto twb = row_twiddles<IP>(tb);
   load_packed_c2r(A, dhat + n * dm.nf, tb, dm);
   __syncthreads();
-  const float2* X = row_fft<true, IP>(A, B, fp, tb, dm);
+  const float2* X = row_fft<true, IP>(A, B, fp, tb, dm, twb);
   const float* xs = reinterpret_cast<const float*>(X);
   const float invN = 1.0f / (float)dm.nfft;
   float* dst = d + n * dm.nt;
@@ -192,6 +196,7 @@ __global__ __launch_bounds__(kBlock) void k_data_r2c(const float* __restrict__ d
   float* g = reinterpret_cast<float*>(B);
   const size_t n = blockIdx.x;
   const float* src = d + n * dm.nt;
+  const auto twb = row_twiddles<IP>(tb);
   if (!WAV) {
     for (int s = threadIdx.x; s < dm.nt; s += kBlock) g[s] = src[s];
   } else {
@@ -203,7 +208,7 @@ __global__ __launch_bounds__(kBlock) void k_data_r2c(const float* __restrict__ d
   __syncthreads();
   pack_transpose(A, g, tb, dm.nts, dm.nh);
   __syncthreads();
-  const float2* X = row_fft<false, IP>(A, B, fp, tb, dm);
+  const float2* X = row_fft<false, IP>(A, B, fp, tb, dm, twb);
   const float mx = block_max<kBlock>(store_real_spectrum(X, dhat + n * dm.nf, tb, dm), red);
   if (threadIdx.x == 0) tr_bound[n] = mx;
 }
@@ -228,9 +233,10 @@ __global__ __launch_bounds__(kBlock) void k_residual_r2c(float2* __restrict__ dh
     const int s = threadIdx.x + k * kBlock;
     ov[k] = (!WAV && s < dm.nt) ? ob[s] : 0.f;
   }
+  const auto twb = row_twiddles<IP>(tb);
   load_packed_c2r(A, dhat + n * dm.nf, tb, dm);
   __syncthreads();
-  float2* X = row_fft<true, IP>(A, B, fp, tb, dm);
+  float2* X = row_fft<true, IP>(A, B, fp, tb, dm, twb);
   float2* Y = (X == A) ? B : A;      // IP: the staging area after A
   const float* xs = reinterpret_cast<const float*>(X);
   float* g = reinterpret_cast<float*>(Y);
@@ -269,7 +275,7 @@ __global__ __launch_bounds__(kBlock) void k_residual_r2c(float2* __restrict__ dh
   __syncthreads();
   pack_transpose(X, g, tb, dm.nts, dm.nh);
   __syncthreads();
-  const float2* Z = row_fft<false, IP>(X, Y, fp, tb, dm);
+  const float2* Z = row_fft<false, IP>(X, Y, fp, tb, dm, twb);
   const float mx = block_max<kBlock>(store_real_spectrum(Z, dhat + n * dm.nf, tb, dm), red);
   if (threadIdx.x == 0) tr_bound[n] = mx;
   if (rss) {
@@ -281,18 +287,18 @@ __global__ __launch_bounds__(kBlock) void k_residual_r2c(float2* __restrict__ dh
 // ------------------------------------------------------------------ launchers
 hipError_t launch_model_r2c(const Plan& p, const float* m, float2* mhat, hipStream_t s) {
   const Dims& dm = p.dm;
-  return launch_row(k_model_r2c<1>, k_model_r2c<2>, k_model_r2c<0>, dm, dm.ntau, model_rows(dm), s, m, mhat, p.tb, dm,
+  return launch_row(AAHRT_ROWK(k_model_r2c), dm, dm.ntau, model_rows(dm), s, m, mhat, p.tb, dm,
                     p.fft_half);
 }
 
 hipError_t launch_rows_r2c(const Dims& dm, const Tables& tb, const FftPlan& fp, const float* in, float2* out,
                            unsigned nrows, hipStream_t s) {
-  return launch_row(k_model_r2c<1>, k_model_r2c<2>, k_model_r2c<0>, dm, dm.ntau, nrows, s, in, out, tb, dm, fp);
+  return launch_row(AAHRT_ROWK(k_model_r2c), dm, dm.ntau, nrows, s, in, out, tb, dm, fp);
 }
 
 hipError_t launch_model_c2r(const Plan& p, const float2* mhat, float* m, hipStream_t s) {
   const Dims& dm = p.dm;
-  return launch_row(k_model_c2r<1>, k_model_c2r<2>, k_model_c2r<0>, dm, 0, model_rows(dm), s, mhat, m, p.tb, dm,
+  return launch_row(AAHRT_ROWK(k_model_c2r), dm, 0, model_rows(dm), s, mhat, m, p.tb, dm,
                     p.fft_half);
 }
 
@@ -301,27 +307,27 @@ hipError_t launch_model_c2r_update(const Plan& p, float2* mhat, float* y, float*
                                    hipStream_t s) {
   const Dims& dm = p.dm;
   if (next)
-    return launch_row(k_model_c2r_update<1, true>, k_model_c2r_update<2, true>, k_model_c2r_update<0, true>, dm, dm.ntau,
+    return launch_row(AAHRT_ROWK(k_model_c2r_update, true), dm, dm.ntau,
                       model_rows(dm), s, mhat, y, x, p.tb, dm, p.fft_half, gam, lam, beta, ista, l1);
-  return launch_row(k_model_c2r_update<1, false>, k_model_c2r_update<2, false>, k_model_c2r_update<0, false>, dm, 0, model_rows(dm), s,
+  return launch_row(AAHRT_ROWK(k_model_c2r_update, false), dm, 0, model_rows(dm), s,
                     mhat, y, x, p.tb, dm, p.fft_half, gam, lam, beta, ista, l1);
 }
 
 hipError_t launch_data_c2r(const Plan& p, const float2* dhat, float* d, hipStream_t s) {
   const Dims& dm = p.dm;
   if (dm.nw > 0)
-    return launch_row(k_data_c2r<1, true>, k_data_c2r<2, true>, k_data_c2r<0, true>, dm, dm.nt, (unsigned)dm.ntr, s, dhat, d,
+    return launch_row(AAHRT_ROWK(k_data_c2r, true), dm, dm.nt, (unsigned)dm.ntr, s, dhat, d,
                       p.tb, dm, p.fft_half);
-  return launch_row(k_data_c2r<1, false>, k_data_c2r<2, false>, k_data_c2r<0, false>, dm, 0, (unsigned)dm.ntr, s, dhat, d, p.tb,
+  return launch_row(AAHRT_ROWK(k_data_c2r, false), dm, 0, (unsigned)dm.ntr, s, dhat, d, p.tb,
                     dm, p.fft_half);
 }
 
 hipError_t launch_data_r2c(const Plan& p, const float* d, float2* dhat, float* tr_bound, hipStream_t s) {
   const Dims& dm = p.dm;
   if (dm.nw > 0)
-    return launch_row(k_data_r2c<1, true>, k_data_r2c<2, true>, k_data_r2c<0, true>, dm, dm.nt, (unsigned)dm.ntr, s, d, dhat,
+    return launch_row(AAHRT_ROWK(k_data_r2c, true), dm, dm.nt, (unsigned)dm.ntr, s, d, dhat,
                       tr_bound, p.tb, dm, p.fft_half);
-  return launch_row(k_data_r2c<1, false>, k_data_r2c<2, false>, k_data_r2c<0, false>, dm, dm.nt, (unsigned)dm.ntr, s, d, dhat,
+  return launch_row(AAHRT_ROWK(k_data_r2c, false), dm, dm.nt, (unsigned)dm.ntr, s, d, dhat,
                     tr_bound, p.tb, dm, p.fft_half);
 }
 
@@ -329,9 +335,9 @@ hipError_t launch_residual_r2c(const Plan& p, float2* dhat, const float* dobs, f
                                hipStream_t s) {
   const Dims& dm = p.dm;
   if (dm.nw > 0)
-    return launch_row(k_residual_r2c<1, true>, k_residual_r2c<2, true>, k_residual_r2c<0, true>, dm, dm.nt, (unsigned)dm.ntr, s,
+    return launch_row(AAHRT_ROWK(k_residual_r2c, true), dm, dm.nt, (unsigned)dm.ntr, s,
                       dhat, dobs, rss, p.tr_bound, p.tb, dm, p.fft_half);
-  return launch_row(k_residual_r2c<1, false>, k_residual_r2c<2, false>, k_residual_r2c<0, false>, dm, dm.nt, (unsigned)dm.ntr, s,
+  return launch_row(AAHRT_ROWK(k_residual_r2c, false), dm, dm.nt, (unsigned)dm.ntr, s,
                     dhat, dobs, rss, p.tr_bound, p.tb, dm, p.fft_half);
 }
 
