@@ -60,7 +60,10 @@ typedef enum {
 
 typedef enum {
   AAHRT_GRID_F32 = 0,  /* oversampled q-grid of the nonuniform FFT held in FP32 */
-  AAHRT_GRID_F16 = 1,  /* ... stored in FP16, accumulated in FP32 */
+  AAHRT_GRID_F16 = 1,  /* ... stored in FP16, accumulated in FP32.  FP16 holds magnitudes up to 65504 only: a
+                          grid cell is a sum over the nq curvature modes of a model spectrum value (the DFT of a
+                          stretched model row) times its deapodisation factor, and a cell above that range
+                          becomes inf, unchecked.  Scale the model (L is linear) or use FP32/BF16 */
   AAHRT_GRID_BF16 = 2  /* ... stored in BF16, accumulated in FP32 */
 } aahrt_grid_dtype;
 
