@@ -108,13 +108,23 @@ __device__ __forceinline__ float grid_tap(float z, float cbeta) {
 template <int W, bool POLY>
 __device__ __forceinline__ void kernel_taps(float z0, float cbeta, float (&ph)[W]) {
   if constexpr (POLY) {
+    // taps t and W-1-t from the even and odd parts of one polynomial: E(y^2) +- y O(y^2)
     const float y = fmaf(z0, (float)W, 1.0f - (float)W);
+    const float y2 = y * y;
 #pragma unroll
-    for (int t = 0; t < W; ++t) {
-      float acc = EsPoly<W>::a[t][0];
+    for (int t = 0; t < (W + 1) / 2; ++t) {
+      float e = EsPoly<W>::e[t][0];
 #pragma unroll
-      for (int k = 1; k <= EsPoly<W>::D; ++k) acc = fmaf(acc, y, EsPoly<W>::a[t][k]);
-      ph[t] = acc;
+      for (int k = 1; k <= EsPoly<W>::DE; ++k) e = fmaf(e, y2, EsPoly<W>::e[t][k]);
+      if (2 * t + 1 == W) {
+        ph[t] = e;
+      } else {
+        float o = EsPoly<W>::o[t][0];
+#pragma unroll
+        for (int k = 1; k <= EsPoly<W>::DO; ++k) o = fmaf(o, y2, EsPoly<W>::o[t][k]);
+        ph[t] = fmaf(y, o, e);
+        ph[W - 1 - t] = fmaf(-y, o, e);
+      }
     }
   } else {
 #pragma unroll

@@ -66,8 +66,37 @@ __device__ __forceinline__ int mode_row(int m, const Dims& dm) {
   return -1;
 }
 
+// HALF (mg = 2 nq, nq even): cell m = t + L r of lane t holds a mode exactly when r < R1/4
+// (l = m + mg/4) or r >= 3 R1/4 (l = m - 3 mg/4), and output m = t C + i + R1 k2 is a kept mode
+// exactly when k2 < L/4 or k2 >= 3 L/4: the zero inputs and the dropped outputs are then
+// known at compile time and their arithmetic disappears.
+template <int R1, int L, bool HALF>
+__device__ __forceinline__ int mode_row_of(int t, int r, const Dims& dm) {
+  if constexpr (HALF) {
+    constexpr int mg = R1 * L;
+    if (r < R1 / 4) return t + L * r + mg / 4;
+    if (r >= 3 * R1 / 4) return t + L * r - 3 * mg / 4;
+    return -1;
+  } else {
+    return mode_row(t + L * r, dm);
+  }
+}
+template <int R1, int L, bool HALF>
+__device__ __forceinline__ int kept_mode_row(int t, int i, int k2, const Dims& dm) {
+  constexpr int C = R1 / L;
+  if constexpr (HALF) {
+    constexpr int mg = R1 * L;
+    const int m = t * C + i + R1 * k2;
+    if (k2 < L / 4) return m + mg / 4;
+    if (k2 >= 3 * L / 4) return m - 3 * mg / 4;
+    return -1;
+  } else {
+    return mode_row(t * C + i + R1 * k2, dm);
+  }
+}
+
 // Forward GFST map with resident slices (see above).
-template <int W, int R1, int L, bool POLY, int NT>
+template <int W, int R1, int L, bool POLY, int NT, bool HALF>
 __global__ __launch_bounds__(NT) void k_nufft_interp_res(const float2* __restrict__ mhat,
                                                               float2* __restrict__ dhat, Tables tb, Dims dm,
                                                               int ftl) {
@@ -96,7 +125,7 @@ __global__ __launch_bounds__(NT) void k_nufft_interp_res(const float2* __restric
     float2 v[R1];
 #pragma unroll
     for (int r = 0; r < R1; ++r) {
-      const int l = mode_row(t + L * r, dm);
+      const int l = mode_row_of<R1, L, HALF>(t, r, dm);
       v[r] = (l >= 0 && f < dm.nf) ? msrc[((size_t)sl * dm.nq + l) * dm.nf + f] : make_float2(0.f, 0.f);
     }
     float2* cell = slots + (size_t)row * ldr;
@@ -160,7 +189,7 @@ __global__ __launch_bounds__(NT) void k_nufft_interp_res(const float2* __restric
 // Transpose of k_nufft_interp_res: every slice cleared, every trace spread into its two
 // slices in fixed point (scale per slice, as k_nufft_spread), then per row: ghost cells
 // folded back, decoded, inverse DFT, the nq kept modes written to Mh[b][s][l][f].
-template <int W, int R1, int L, bool POLY, int NT>
+template <int W, int R1, int L, bool POLY, int NT, bool HALF>
 __global__ __launch_bounds__(NT) void k_nufft_spread_res(const float2* __restrict__ dhat,
                                                               const float* __restrict__ slice_scale,
                                                               float2* __restrict__ mhat, Tables tb, Dims dm,
@@ -250,7 +279,7 @@ __global__ __launch_bounds__(NT) void k_nufft_spread_res(const float2* __restric
       for (int i = 0; i < C; ++i) {
 #pragma unroll
         for (int k2 = 0; k2 < L; ++k2) {
-          const int l = mode_row(t * C + i + R1 * k2, dm);
+          const int l = kept_mode_row<R1, L, HALF>(t, i, k2, dm);
           if (l >= 0) mdst[((size_t)s * dm.nq + l) * dm.nf + f] = v[i * L + k2];
         }
       }
@@ -261,7 +290,7 @@ __global__ __launch_bounds__(NT) void k_nufft_spread_res(const float2* __restric
 // ------------------------------------------------------------------ launchers
 // Lane split of the q-grid transform by grid length (64 = 8 x 8, 128 = 16 x 8, 256 = 16 x 16)
 // and kernel taps by polynomial for widths of 5 and more at the sigma = 2 shape.
-template <int W, int R1, int L, int NT>
+template <int W, int R1, int L, int NT, bool HALF>
 static hipError_t launch_interp_res_w(const Plan& p, const Dims& dm, const float2* mhat, float2* dhat,
                                       hipStream_t s) {
   const size_t lds = res_lds_f2(dm.ft, dm.ldr, dm.ntheta, dm.mg) * sizeof(float2);
@@ -269,19 +298,19 @@ static hipError_t launch_interp_res_w(const Plan& p, const Dims& dm, const float
   const int ftl = ilog2(dm.ft);
   if constexpr (W >= 5) {
     if (dm.poly) {
-      hipError_t e = set_lds(k_nufft_interp_res<W, R1, L, true, NT>, lds);
+      hipError_t e = set_lds(k_nufft_interp_res<W, R1, L, true, NT, HALF>, lds);
       if (e != hipSuccess) return e;
-      hipLaunchKernelGGL((k_nufft_interp_res<W, R1, L, true, NT>), grid, block, lds, s, mhat, dhat, p.tb, dm, ftl);
+      hipLaunchKernelGGL((k_nufft_interp_res<W, R1, L, true, NT, HALF>), grid, block, lds, s, mhat, dhat, p.tb, dm, ftl);
       return hipGetLastError();
     }
   }
-  hipError_t e = set_lds(k_nufft_interp_res<W, R1, L, false, NT>, lds);
+  hipError_t e = set_lds(k_nufft_interp_res<W, R1, L, false, NT, HALF>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_nufft_interp_res<W, R1, L, false, NT>), grid, block, lds, s, mhat, dhat, p.tb, dm, ftl);
+  hipLaunchKernelGGL((k_nufft_interp_res<W, R1, L, false, NT, HALF>), grid, block, lds, s, mhat, dhat, p.tb, dm, ftl);
   return hipGetLastError();
 }
 
-template <int W, int R1, int L, int NT>
+template <int W, int R1, int L, int NT, bool HALF>
 static hipError_t launch_spread_res_w(const Plan& p, const Dims& dm, const float2* dhat, const float* slice_scale,
                                       float2* mhat, hipStream_t s) {
   const size_t lds = res_lds_f2(dm.ft, dm.ldr, dm.ntheta, dm.mg) * sizeof(float2) + dm.ntheta * sizeof(float);
@@ -289,34 +318,48 @@ static hipError_t launch_spread_res_w(const Plan& p, const Dims& dm, const float
   const int ftl = ilog2(dm.ft);
   if constexpr (W >= 5) {
     if (dm.poly) {
-      hipError_t e = set_lds(k_nufft_spread_res<W, R1, L, true, NT>, lds);
+      hipError_t e = set_lds(k_nufft_spread_res<W, R1, L, true, NT, HALF>, lds);
       if (e != hipSuccess) return e;
-      hipLaunchKernelGGL((k_nufft_spread_res<W, R1, L, true, NT>), grid, block, lds, s, dhat, slice_scale, mhat, p.tb,
+      hipLaunchKernelGGL((k_nufft_spread_res<W, R1, L, true, NT, HALF>), grid, block, lds, s, dhat, slice_scale, mhat, p.tb,
                          dm, ftl);
       return hipGetLastError();
     }
   }
-  hipError_t e = set_lds(k_nufft_spread_res<W, R1, L, false, NT>, lds);
+  hipError_t e = set_lds(k_nufft_spread_res<W, R1, L, false, NT, HALF>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_nufft_spread_res<W, R1, L, false, NT>), grid, block, lds, s, dhat, slice_scale, mhat, p.tb,
+  hipLaunchKernelGGL((k_nufft_spread_res<W, R1, L, false, NT, HALF>), grid, block, lds, s, dhat, slice_scale, mhat, p.tb,
                      dm, ftl);
   return hipGetLastError();
 }
 
+template <int W, int R1, int L, int NT>
+static hipError_t interp_res_half(const Plan& p, const Dims& dm, const float2* mhat, float2* dhat, hipStream_t s) {
+  if (2 * dm.nq == R1 * L && dm.nq % 2 == 0) return launch_interp_res_w<W, R1, L, NT, true>(p, dm, mhat, dhat, s);
+  return launch_interp_res_w<W, R1, L, NT, false>(p, dm, mhat, dhat, s);
+}
+
+template <int W, int R1, int L, int NT>
+static hipError_t spread_res_half(const Plan& p, const Dims& dm, const float2* dhat, const float* slice_scale,
+                                  float2* mhat, hipStream_t s) {
+  if (2 * dm.nq == R1 * L && dm.nq % 2 == 0)
+    return launch_spread_res_w<W, R1, L, NT, true>(p, dm, dhat, slice_scale, mhat, s);
+  return launch_spread_res_w<W, R1, L, NT, false>(p, dm, dhat, slice_scale, mhat, s);
+}
+
 template <int W, int NT>
 static hipError_t interp_res_mg(const Plan& p, const Dims& dm, const float2* mhat, float2* dhat, hipStream_t s) {
-  if (dm.mg == 64) return launch_interp_res_w<W, 8, 8, NT>(p, dm, mhat, dhat, s);
-  if (dm.mg == 128) return launch_interp_res_w<W, 16, 8, NT>(p, dm, mhat, dhat, s);
-  if (dm.mg == 256) return launch_interp_res_w<W, 16, 16, NT>(p, dm, mhat, dhat, s);
+  if (dm.mg == 64) return interp_res_half<W, 8, 8, NT>(p, dm, mhat, dhat, s);
+  if (dm.mg == 128) return interp_res_half<W, 16, 8, NT>(p, dm, mhat, dhat, s);
+  if (dm.mg == 256) return interp_res_half<W, 16, 16, NT>(p, dm, mhat, dhat, s);
   return hipErrorInvalidValue;
 }
 
 template <int W, int NT>
 static hipError_t spread_res_mg(const Plan& p, const Dims& dm, const float2* dhat, const float* slice_scale,
                                 float2* mhat, hipStream_t s) {
-  if (dm.mg == 64) return launch_spread_res_w<W, 8, 8, NT>(p, dm, dhat, slice_scale, mhat, s);
-  if (dm.mg == 128) return launch_spread_res_w<W, 16, 8, NT>(p, dm, dhat, slice_scale, mhat, s);
-  if (dm.mg == 256) return launch_spread_res_w<W, 16, 16, NT>(p, dm, dhat, slice_scale, mhat, s);
+  if (dm.mg == 64) return spread_res_half<W, 8, 8, NT>(p, dm, dhat, slice_scale, mhat, s);
+  if (dm.mg == 128) return spread_res_half<W, 16, 8, NT>(p, dm, dhat, slice_scale, mhat, s);
+  if (dm.mg == 256) return spread_res_half<W, 16, 16, NT>(p, dm, dhat, slice_scale, mhat, s);
   return hipErrorInvalidValue;
 }
 
