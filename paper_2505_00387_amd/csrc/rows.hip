@@ -98,6 +98,7 @@ __global__ __launch_bounds__(kBlock) void k_model_c2r_update(float2* __restrict_
   const float g = gam[b];
   const float thr = g * lam[b];
   float s1 = 0.f;
+  bool nonzero = false;
   auto step = [&](int i, float yo, float xo) {
     const float v = yo + g * (sc * lerp_transpose(i, tb.s_start, tb.s_w, xs));
     const float a = fabsf(v) - thr;
@@ -106,6 +107,7 @@ __global__ __launch_bounds__(kBlock) void k_model_c2r_update(float2* __restrict_
     yr[i] = yn;
     xr[i] = xn;
     if (NEXT) stage[i] = yn;
+    nonzero |= yn != 0.f;
     s1 += fabsf(xn);
   };
 #pragma unroll
@@ -119,7 +121,13 @@ __global__ __launch_bounds__(kBlock) void k_model_c2r_update(float2* __restrict_
     if (threadIdx.x == 0) l1[rid] = t;
   }
   if (NEXT) {
-    __syncthreads();  // S^T reads of xs done, new row staged
+    // S^T reads of xs done, new row staged; a row of y that the shrinkage left all zero has
+    // a zero spectrum, written without the transform (most rows of a sparse cube are)
+    if (!__syncthreads_or(nonzero ? 1 : 0)) {
+      float2* dst = mhat + rid * dm.nf;
+      for (int k = threadIdx.x; k < dm.nf; k += kBlock) dst[k] = make_float2(0.f, 0.f);
+      return;
+    }
     float2* in = IP ? A : (stage == reinterpret_cast<float*>(A) ? B : A);
     float2* other = IP ? B : reinterpret_cast<float2*>(stage);
     stretch_pack(in, stage, tb.deapod[l], tb, dm);
