@@ -272,19 +272,24 @@ FP32_FLOOR = 3e-7
 
 
 @pytest.mark.parametrize('sigma,tol,freq_tile', [(2.0, 1e-6, 64), (3.0, 1e-6, 1), (1.5, 2e-6, 4),
-                                                 (1.25, 1e-5, 32), (2.0, 1e-4, 16), (1.25, 1e-6, 8)])
+                                                 (1.25, 1e-5, 32), (2.0, 1e-4, 16), (1.25, 1e-6, 8),
+                                                 (4.0, 1e-6, 2)])
 def test_operator_error_meets_nufft_tol(sigma, tol, freq_tile):
     """Every (sigma, width) the width rule admits for a tolerance meets it against the oracle, to
     twice the tolerance above the FP32 floor of the rest of the pipeline.  A requested sigma that no
     width brings within the tolerance (1.25 at 1e-6: the FP32 rounding of its grid transform,
     amplified by the deapodisation, sits near 6e-6) reports an estimate above the tolerance and
-    stays within twice that estimate.  Extremes of the tile (1 and 64) are covered too."""
+    stays within twice that estimate.  Extremes of the tile (1 and 64) are covered too, and
+    sigma = 4 (a 128-cell grid for 32 curvatures) runs the resident-slice kernels on a grid whose
+    zero pattern is not the sigma = 2 one."""
     w = wl.config3(with_data=False)
     errs, info = _op_parity(w, seed=4, with_info=True, sigma=sigma, freq_tile=freq_tile, nufft_tol=tol)
     est = info['nufft_error_estimate']
     bound = 2.0 * max(tol, est) + FP32_FLOOR
     print(f'sigma {info["sigma"]} w {info["kernel_width"]} tol {tol:.0e} estimate {est:.2e}:',
           [f'{a:.1e}/{b:.1e}' for a, b in errs], f'bound {bound:.1e}')
+    if sigma == 4.0:
+        assert info['gfst_resident'] == 1 and info['grid_size'] == 128
     if est <= tol:
         assert bound <= 2.0 * tol + FP32_FLOOR
     else:
