@@ -496,7 +496,7 @@ __device__ __forceinline__ void load_plan_bases(float2* b, const float2* __restr
   if constexpr (NS > 1) {
     constexpr int NB = N / R, STRIDE = N / (NS * R);
     const int step = (j % NS) * STRIDE;
-    const bool act = NB >= 256 || j < NB;
+    const bool act = NB >= 256 || j < NB;  // 256 = kBlock, the threads of a row workgroup
 #pragma unroll
     for (int a = 0; a < twiddle_bases<R>(); ++a) b[a] = act ? tw[(a == 0 ? 1 : 4 * a) * step] : make_float2(1.f, 0.f);
   }
