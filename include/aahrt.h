@@ -88,7 +88,8 @@ typedef struct aahrt_params {
                             or, where none does at a requested sigma, the one of smallest estimate;
                             2 -> the paper's own step 3 (Section 3.4): linear interpolation in k on the
                             sigma-oversampled grid, no deapodisation (low accuracy, reported only) */
-  int32_t freq_tile;     /* frequencies per work item of the GFST stage (power of 2, 1..64); 0 -> autotune */
+  int32_t freq_tile;     /* frequencies per workgroup tile of the GFST kernels (power of 2, 1..64; halved until
+                            the tile fits LDS); 0 -> autotune */
   int32_t grid_dtype;    /* aahrt_grid_dtype */
   int32_t gfst_kind;     /* 0: GFST kernels with every azimuth slice of a frequency tile resident in LDS where
                             they apply (FP32 q-grid of 64, 128 or 256 cells that fits), else the slice sweep;
@@ -112,12 +113,12 @@ typedef struct aahrt_plan_info {
   int32_t kernel_width;  /* w */
   double sigma;          /* grid_size / nq */
   double beta;           /* kernel shape parameter */
-  int32_t freq_tile;     /* frequencies per work item of the forward GFST kernel (interpolation) */
+  int32_t freq_tile;     /* frequencies per workgroup tile of the forward GFST kernel (interpolation) */
   int64_t workspace_bytes;
   int32_t q_alias_ok;    /* 1 if nq >= 2 q_max f'_max h2max (Section 3.5 anti-alias rule), else 0 (informational) */
   int32_t autotune_candidates; /* GFST settings timed at plan creation (0: none, the setting was fixed) */
   double autotune_seconds;     /* wall time of that autotuning */
-  int32_t freq_tile_adjoint;   /* frequencies per work item of the adjoint GFST kernel (spreading) */
+  int32_t freq_tile_adjoint;   /* frequencies per workgroup tile of the adjoint GFST kernel (spreading) */
   int32_t gfst_resident;       /* 1 if the resident-slice GFST kernels run, 0 for the slice sweep */
   double nufft_error_estimate; /* estimated relative error of one q nonuniform FFT at the chosen setting
                                   (kernel truncation and FP32 rounding; 1 for kernel_width = 2) */
