@@ -119,3 +119,12 @@ def test_velocity_scan_shapes():
     assert np.allclose(np.unique(np.round(g.x, 9)), (np.arange(6) - 2.5) * 0.04)
     assert w.axes.dt == 0.004 and w.axes.ntheta == 90 and w.axes.nq == 8
     assert np.isfinite(g.data).all() and np.abs(g.data).max() > 0
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch):
+    """No CPU fallback: without the built HIP library the binding raises instead of computing."""
+    from paper_2505_00387_amd import _lib
+    monkeypatch.setattr(_lib, '_lib', None)
+    monkeypatch.setattr(_lib, 'LIB_PATH', os.path.join(ROOT, '_no_such_dir', 'libaahrt.so'))
+    with pytest.raises(ImportError, match='missing'):
+        _lib.load()
