@@ -91,6 +91,12 @@ __device__ __forceinline__ float lerp_transpose(int i, const int* __restrict__ s
   const int b = start[i], c = start[i + 1];
   const int a = i > 0 ? start[i - 1] : b;
   float acc = 0.f;
+  if (c - a <= 2) {
+    // most outputs have at most two inputs: the same products in the same order, unmasked
+    if (a < c) acc = fmaf(a < b ? w[a].y : w[a].x, x[a], acc);
+    if (a + 1 < c) acc = fmaf(a + 1 < b ? w[a + 1].y : w[a + 1].x, x[a + 1], acc);
+    return acc;
+  }
   for (int r0 = a; r0 < c; r0 += 4) {
     float2 wv[4];
     float xv[4];
