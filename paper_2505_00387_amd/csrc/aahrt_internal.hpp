@@ -41,10 +41,13 @@ __host__ __device__ constexpr int row_kmax(int r) { return r >= 15 ? 2 : (r == 5
 
 // Row transforms also compiled with their length and radices as constants (row_ip >= 3):
 // N/2 of the stretched axis and the radices in pass order (each pass one butterfly per thread).
+// half = 1: the plan also assumes nt' <= N/2, so that the second half of a forward
+// transform's packed input is zero padding and the second half of an inverse transform's
+// output is never read; both are left out of its first and last passes.
 struct StaticRowSpec {
-  int ip, n, npass, r[3];
+  int ip, n, npass, r[3], half;
 };
-constexpr StaticRowSpec kStaticRows[] = {{3, 2160, 3, {16, 15, 9}}, {4, 480, 3, {16, 15, 2}}};
+constexpr StaticRowSpec kStaticRows[] = {{3, 2160, 3, {16, 15, 9}, 1}, {4, 480, 3, {16, 15, 2}, 0}};
 constexpr int kRowKinds = 5;  // row_ip 0..4
 
 // Two-tap linear interpolation entry: value = w0 * x[i0] + w1 * x[i1] (dropped taps have weight 0).

@@ -416,11 +416,17 @@ __device__ __forceinline__ void fft_lds_ip(float2* buf, const FftPlan& pl, int n
 // arithmetic folds into LDS offsets.  Same butterflies and twiddle products as
 // fft_lds_ip, hence the same results.  Passes with a multiple of 16 between the
 // elements of a butterfly address the padded buffer as pad16(first) + r * (step + step/16).
-template <bool INV, int NT, int N, int NPASS, int S, int NS, int R, int... Rest>
+// HALF: inputs at and past N/2 of a forward transform are zero, outputs at and past N/2 of
+// an inverse transform are not needed: in the first forward pass the elements r with
+// r NB >= N/2 are not loaded (zero), in the last inverse pass those with r NS >= N/2 are
+// not stored, and the arithmetic feeding only them disappears.
+template <bool INV, int NT, int N, int NPASS, int S, int NS, bool HALF, int R, int... Rest>
 __device__ __forceinline__ void fft_static(float2* buf, const float2* twb) {
   constexpr int NB = N / R;
   constexpr bool PIN = NPASS >= 2 && S == 1;
   constexpr bool POUT = NPASS >= 2 && S == 0;
+  constexpr bool ZIN = HALF && !INV && S == 0;            // first pass of a forward transform
+  constexpr bool DROP = HALF && INV && S == NPASS - 1;    // last pass of an inverse transform
   static_assert(NB <= NT && N % R == 0, "one butterfly per thread");
   const int j = threadIdx.x;
   const bool act = NB == NT || j < NB;
@@ -437,7 +443,7 @@ __device__ __forceinline__ void fft_static(float2* buf, const float2* twb) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int i = j + r * NB;
-        v[r] = buf[PIN ? pad16(i) : i];
+        v[r] = (ZIN && r * NB >= N / 2) ? make_float2(0.f, 0.f) : buf[PIN ? pad16(i) : i];
       }
     }
     if constexpr (NS > 1) apply_twiddle_bases<R, INV>(v, twb);
@@ -458,27 +464,27 @@ __device__ __forceinline__ void fft_static(float2* buf, const float2* twb) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int i = o + r * NS;
-        buf[POUT ? pad16(i) : i] = v[r];
+        if (!(DROP && r * NS >= N / 2)) buf[POUT ? pad16(i) : i] = v[r];
       }
     }
   }
   __syncthreads();
   if constexpr (sizeof...(Rest) > 0)
-    fft_static<INV, NT, N, NPASS, S + 1, NS * R, Rest...>(buf, twb + (NS > 1 ? twiddle_bases<R>() : 0));
+    fft_static<INV, NT, N, NPASS, S + 1, NS * R, HALF, Rest...>(buf, twb + (NS > 1 ? twiddle_bases<R>() : 0));
 }
 
-template <int N, int... Rs>
+template <int N, bool HALF, int... Rs>
 struct RowPlan {};
 
 template <int IP>
 struct StaticRowPlan;
 template <>
 struct StaticRowPlan<3> {
-  using type = RowPlan<2160, 16, 15, 9>;
+  using type = RowPlan<2160, true, 16, 15, 9>;
 };
 template <>
 struct StaticRowPlan<4> {
-  using type = RowPlan<480, 16, 15, 2>;
+  using type = RowPlan<480, false, 16, 15, 2>;
 };
 
 // Twiddle bases of one thread for every pass of a compiled plan (the passes after the
@@ -505,8 +511,8 @@ __device__ __forceinline__ void load_plan_bases(float2* b, const float2* __restr
 
 template <typename P>
 struct RowTwiddles;
-template <int N, int... Rs>
-struct RowTwiddles<RowPlan<N, Rs...>> {
+template <int N, bool HALF, int... Rs>
+struct RowTwiddles<RowPlan<N, HALF, Rs...>> {
   static constexpr int count = plan_bases<N, 1, Rs...>();
   float2 b[count > 0 ? count : 1];
   __device__ __forceinline__ void load(const float2* __restrict__ tw) {
@@ -514,17 +520,17 @@ struct RowTwiddles<RowPlan<N, Rs...>> {
   }
 };
 
-template <bool INV, int NT, int N, int... Rs>
-__device__ __forceinline__ void fft_row_static(float2* buf, const RowTwiddles<RowPlan<N, Rs...>>& twb) {
-  fft_static<INV, NT, N, (int)sizeof...(Rs), 0, 1, Rs...>(buf, twb.b);
+template <bool INV, int NT, int N, bool HALF, int... Rs>
+__device__ __forceinline__ void fft_row_static(float2* buf, const RowTwiddles<RowPlan<N, HALF, Rs...>>& twb) {
+  fft_static<INV, NT, N, (int)sizeof...(Rs), 0, 1, HALF, Rs...>(buf, twb.b);
 }
 
 // The compiled plans agree with the host's table.
-template <int IP, int N, int... Rs>
-constexpr bool static_row_matches(RowPlan<N, Rs...>) {
+template <int IP, int N, bool HALF, int... Rs>
+constexpr bool static_row_matches(RowPlan<N, HALF, Rs...>) {
   constexpr int rs[] = {Rs...};
   const StaticRowSpec& sp = kStaticRows[IP - 3];
-  if (sp.ip != IP || sp.n != N || sp.npass != (int)sizeof...(Rs)) return false;
+  if (sp.ip != IP || sp.n != N || sp.npass != (int)sizeof...(Rs) || sp.half != (HALF ? 1 : 0)) return false;
   for (int i = 0; i < (int)sizeof...(Rs); ++i)
     if (sp.r[i] != rs[i]) return false;
   return true;

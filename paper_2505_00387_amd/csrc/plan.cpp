@@ -815,7 +815,7 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
   // a plan that is also compiled in with constant sizes (kStaticRows) runs that instantiation
   if (dm.row_ip == 1) {
     for (const StaticRowSpec& sp : kStaticRows) {
-      bool same = sp.n == dm.nh && sp.npass == P.fft_half.npass;
+      bool same = sp.n == dm.nh && sp.npass == P.fft_half.npass && (!sp.half || dm.nts <= dm.nh);
       for (int i = 0; same && i < sp.npass; ++i) same = sp.r[i] == P.fft_half.pass[i].r;
       if (same) dm.row_ip = sp.ip;
     }
