@@ -332,6 +332,31 @@ def test_frequency_tile_changes_no_result(kind):
         assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
 
 
+@pytest.mark.parametrize('nq,ntheta', [(128, 4), (32, 1)])
+def test_resident_grid_lengths_parity_and_tile_invariance(nq, ntheta):
+    """The resident-slice kernels on a 256-cell grid (nq = 128, 16 x 16 lanes per register row)
+    and on a single azimuth slice (nq = 32, 64 cells): every (tile, workgroup) setting gives
+    bitwise the same forward and adjoint, which meet the bound against the oracle."""
+    w = wl.small_case(nt=128, ntr=300, nq=nq, ntheta=ntheta, seed=nq + 7 * ntheta, dt=0.004,
+                      q_min=0.04, q_max=0.3, radius=1.5)
+    g = geoms(w)[0]
+    m = wl.random_model(w.axes, 1, 21)
+    d = wl.random_data(w.gathers[0].x.size, w.axes.nt, 21)
+    ref_d, ref_m = gfst.forward(m[0], g), gfst.adjoint(d, g)
+    outs = []
+    for ft, bs in ((1, 512), (2, 1024), (8, 512), (4, 1024)):
+        plan = make_plan(w, sigma=2.0, freq_tile=ft, block_threads=bs)
+        assert plan.info['gfst_resident'] == 1 and plan.info['grid_size'] == 2 * nq
+        assert plan.info['freq_tile'] == ft and plan.info['block_threads'] == bs
+        outs.append((to_host(plan.forward(to_dev(m))), to_host(plan.adjoint(to_dev(d)))))
+        plan.close()
+    ef, ea = rel(outs[0][0], ref_d), rel(outs[0][1][0], ref_m)
+    print(f'nq {nq} ntheta {ntheta}: forward {ef:.2e} adjoint {ea:.2e}')
+    assert ef < TOL and ea < TOL
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
+
+
 @pytest.mark.parametrize('config', [2, 3])
 def test_resident_and_sweep_kernels_agree(config):
     """The resident-slice GFST kernels and the slice sweep compute the same operator: they differ
