@@ -73,3 +73,22 @@ def test_tap_polynomials_match_the_kernel(w):
     assert worst <= 1.2 * _stated_error(w) + 1e-9, (w, worst)
     # the coefficients' magnitudes bound the FP32 Horner rounding the generator states (about 1e-7)
     assert max(sum(abs(c) for c in r) for r in e + o) < 2.0
+
+
+def test_radix_butterflies_match_a_direct_dft(tmp_path):
+    """Every radix butterfly of the LDS FFTs (2, 3, 4, 5, 8, 9, 15, 16; forward and inverse sign),
+    built for the host from the same header, against a direct DFT in double."""
+    import shutil
+    hipcc = shutil.which('hipcc') or '/opt/rocm/bin/hipcc'
+    if not os.path.exists(hipcc):
+        pytest.skip('hipcc not available')
+    exe = tmp_path / 'dft_check'
+    src = os.path.join(ROOT, 'tests', 'host', 'dft_check.cpp')
+    subprocess.run([hipcc, '-O2', '-std=c++17', '-x', 'hip', '--offload-arch=gfx950', '-I', CSRC, src, '-o',
+                    str(exe)], check=True, capture_output=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split('\n')
+    rows = [ln.split() for ln in out if ln.strip()]
+    assert len(rows) == 16
+    for r, inv, err in rows:
+        # a few FP32 roundings of magnitude-sqrt(R) sums of N(0,1) values
+        assert float(err) < 2e-5 * int(r), (r, inv, err)
