@@ -95,7 +95,7 @@ typedef struct aahrt_params {
                             they apply (FP32 q-grid of 64, 128 or 256 cells that fits), else the slice sweep;
                             1: always the slice sweep.  The two differ only in the FP32 rounding of the q-grid
                             transform; the tile changes no result within a kind */
-  int32_t block_threads; /* threads per workgroup of the resident-slice GFST kernels: 512 or 1024; 0 -> autotune
+  int32_t block_threads; /* threads per workgroup of the resident-slice GFST kernels: 512, 768 or 1024; 0 -> autotune
                             (the slice sweep always uses 512); changes no result */
 } aahrt_params;
 
@@ -149,7 +149,7 @@ const char* aahrt_last_error(void);
  * sigma = 1.25 above about 6e-6 and sigma = 1.5 above about 1.1e-6, so at the default
  * tolerance only sigma = 2 is admitted.  When sigma, freq_tile or block_threads is 0 it
  * then autotunes the GFST stage: every admissible setting (sigma in {2, 1.5, 1.25}; for the
- * resident-slice kernels freq_tile in {1, 2, 4, 8} and block_threads in {512, 1024}, for the
+ * resident-slice kernels freq_tile in {1, 2, 4, 8} and block_threads in {512, 768, 1024}, for the
  * slice sweep freq_tile in {4, 8, 16, 32}) is timed on the interpolation and on the
  * spreading launch over the batch (on zeroed spectra, in a stream of its own,
  * synchronously); each kernel keeps its fastest tile and workgroup size, and the sigma with

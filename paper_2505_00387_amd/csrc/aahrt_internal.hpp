@@ -111,7 +111,7 @@ struct Dims {
   int nw, wc;   // wavelet of the deconvolutive operator: taps and origin (nw = 0: none)
   int res;      // 1: GFST kernels with every azimuth slice resident in LDS (q-grid of 64, 128 or 256 cells)
   int poly;     // 1: kernel taps by the per-tap polynomials (w >= 5, sigma >= 2 shape)
-  int bsz;      // threads per workgroup of the resident GFST kernels (512 or 1024; set per launch)
+  int bsz;      // threads per workgroup of the resident GFST kernels (512, 768 or 1024; set per launch)
 };
 
 // Algorithm 2 of Section 3.2 on a regular offset grid x_m = x0 + m dx, y_n = y0 + n dy.

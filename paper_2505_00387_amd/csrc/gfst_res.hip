@@ -363,11 +363,12 @@ static hipError_t spread_res_mg(const Plan& p, const Dims& dm, const float2* dha
   return hipErrorInvalidValue;
 }
 
-// Workgroups of 512 or 1024 threads (dm.bsz): the larger one keeps more wavefronts per CU
-// when the tile's slices take most of the LDS.
+// Workgroups of 512, 768 or 1024 threads (dm.bsz): the larger ones keep more wavefronts per
+// CU when the tile's slices take most of the LDS.
 template <int W>
 static hipError_t interp_res_bs(const Plan& p, const Dims& dm, const float2* mhat, float2* dhat, hipStream_t s) {
   if (dm.bsz == 512) return interp_res_mg<W, 512>(p, dm, mhat, dhat, s);
+  if (dm.bsz == 768) return interp_res_mg<W, 768>(p, dm, mhat, dhat, s);
   if (dm.bsz == 1024) return interp_res_mg<W, 1024>(p, dm, mhat, dhat, s);
   return hipErrorInvalidValue;
 }
@@ -376,6 +377,7 @@ template <int W>
 static hipError_t spread_res_bs(const Plan& p, const Dims& dm, const float2* dhat, const float* slice_scale,
                                 float2* mhat, hipStream_t s) {
   if (dm.bsz == 512) return spread_res_mg<W, 512>(p, dm, dhat, slice_scale, mhat, s);
+  if (dm.bsz == 768) return spread_res_mg<W, 768>(p, dm, dhat, slice_scale, mhat, s);
   if (dm.bsz == 1024) return spread_res_mg<W, 1024>(p, dm, dhat, slice_scale, mhat, s);
   return hipErrorInvalidValue;
 }

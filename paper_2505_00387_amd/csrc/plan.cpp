@@ -307,8 +307,8 @@ int validate_params(const aahrt_params& q) {
   if (q.grid_dtype != AAHRT_GRID_F32 && q.grid_dtype != AAHRT_GRID_F16 && q.grid_dtype != AAHRT_GRID_BF16)
     return bad("grid_dtype must be 0, 1 or 2");
   if (q.gfst_kind < 0 || q.gfst_kind > 1) return bad("gfst_kind must be 0 or 1");
-  if (q.block_threads != 0 && q.block_threads != 512 && q.block_threads != 1024)
-    return bad("block_threads must be 0, 512 or 1024");
+  if (q.block_threads != 0 && q.block_threads != 512 && q.block_threads != 768 && q.block_threads != 1024)
+    return bad("block_threads must be 0, 512, 768 or 1024");
   return AAHRT_OK;
 }
 
@@ -324,7 +324,7 @@ struct NufftChoice {
   int mg, w, ft;
   double est;
   int res;  // 1: resident-slice kernels
-  int bs;   // threads per workgroup (512 or 1024 for the resident kernels, else kBlockG)
+  int bs;   // threads per workgroup (512, 768 or 1024 for the resident kernels, else kBlockG)
 };
 
 // Shape parameter of the exponential-of-semicircle kernel, beta = 0.98 pi (1 - 1/(2 sigma)) w:
@@ -477,18 +477,18 @@ int nufft_candidates(const aahrt_params& prm, const Dims& dm, std::vector<NufftC
     FftPlan fp;
     if (!make_grid_fft_plan(mg, fp)) continue;
     // the resident-slice kernels where they apply (unless the sweep is requested), with
-    // tiles of 4, 8, 2 or 1 frequencies in workgroups of 512 or 1024 threads; otherwise the
+    // tiles of 4, 8, 2 or 1 frequencies in workgroups of 512, 768 or 1024 threads; otherwise the
     // slice sweep with tiles of 4..32
     const bool res = prm.gfst_kind != 1 && res_fits(dm, mg, w, 1);
     if (res) {
       if (prm.freq_tile != 0) {
         int ft = prm.freq_tile;
         while (ft > 1 && !res_fits(dm, mg, w, ft)) ft /= 2;
-        for (int bs : {512, 1024})
+        for (int bs : {512, 768, 1024})
           if (prm.block_threads == 0 || prm.block_threads == bs) out.push_back({mg, w, ft, est, 1, bs});
       } else {
         for (int ft : {4, 8, 2, 1})
-          for (int bs : {512, 1024})
+          for (int bs : {512, 768, 1024})
             if (res_fits(dm, mg, w, ft) && (prm.block_threads == 0 || prm.block_threads == bs))
               out.push_back({mg, w, ft, est, 1, bs});
       }

@@ -320,7 +320,7 @@ def test_frequency_tile_changes_no_result(kind):
     m = to_dev(wl.random_model(w.axes, w.batch, 9))
     d = to_dev(wl.random_data(int(w.trace_ptr[-1]), w.axes.nt, 9))
     outs = []
-    cases = ((1, 512), (4, 1024), (8, 512), (8, 1024), (2, 1024)) if kind == 0 else ((4, 0), (16, 0), (32, 0))
+    cases = ((1, 512), (4, 1024), (8, 512), (8, 768), (2, 1024)) if kind == 0 else ((4, 0), (16, 0), (32, 0))
     for ft, bs in cases:
         plan = make_plan(w, sigma=2.0, freq_tile=ft, gfst_kind=kind, block_threads=bs)
         assert plan.info['freq_tile'] == ft and plan.info['autotune_candidates'] == 0
@@ -344,7 +344,7 @@ def test_resident_grid_lengths_parity_and_tile_invariance(nq, ntheta):
     d = wl.random_data(w.gathers[0].x.size, w.axes.nt, 21)
     ref_d, ref_m = gfst.forward(m[0], g), gfst.adjoint(d, g)
     outs = []
-    for ft, bs in ((1, 512), (2, 1024), (8, 512), (4, 1024)):
+    for ft, bs in ((1, 512), (2, 1024), (8, 768), (4, 1024)):
         plan = make_plan(w, sigma=2.0, freq_tile=ft, block_threads=bs)
         assert plan.info['gfst_resident'] == 1 and plan.info['grid_size'] == 2 * nq
         assert plan.info['freq_tile'] == ft and plan.info['block_threads'] == bs
@@ -395,7 +395,7 @@ def test_autotuner_times_the_candidates():
     assert info['nufft_error_estimate'] <= 1e-6
     tiles = (1, 2, 4, 8) if info['gfst_resident'] else (4, 8, 16, 32)
     assert info['freq_tile'] in tiles and info['freq_tile_adjoint'] in tiles
-    sizes = (512, 1024) if info['gfst_resident'] else (512,)
+    sizes = (512, 768, 1024) if info['gfst_resident'] else (512,)
     assert info['block_threads'] in sizes and info['block_threads_adjoint'] in sizes
     plan.close()
     # a looser tolerance admits the narrower grids, which are then timed as well
