@@ -117,16 +117,23 @@ __global__ __launch_bounds__(NT) void k_nufft_interp_res(const float2* __restric
 
   // q-grids of every (slice, frequency) row: modes from the model spectrum, DFT to the grid,
   // the first W - 1 cells repeated after the last (ghost cells)
+  // Offsets within a slice use 24-bit products (l < 256, and nf < 2^14 since a row transform
+  // fits LDS), which issue at the full
+  // VALU rate where 32- and 64-bit integer products take four times as long.
   const int t = threadIdx.x % L;
   const float2* msrc = mhat + (size_t)b * nt * dm.nq * dm.nf;
+  const unsigned qn = (unsigned)dm.nq * (unsigned)dm.nf;
   for (int row = threadIdx.x / L; row < nt * ft; row += NT / L) {
     const int sl = row >> ftl, fl = row & (ft - 1);
     const int f = f0 + fl;
+    // a row past the last frequency is built from the last one's modes and never read
+    const float2* src = msrc + (size_t)sl * qn + min(f, dm.nf - 1);
     float2 v[R1];
 #pragma unroll
     for (int r = 0; r < R1; ++r) {
       const int l = mode_row_of<R1, L, HALF>(t, r, dm);
-      v[r] = (l >= 0 && f < dm.nf) ? msrc[((size_t)sl * dm.nq + l) * dm.nf + f] : make_float2(0.f, 0.f);
+      const float2 x = src[__umul24((unsigned)max(l, 0), (unsigned)dm.nf)];
+      v[r] = l >= 0 ? x : make_float2(0.f, 0.f);
     }
     float2* cell = slots + (size_t)row * ldr;
     row_dft_lanes<R1, L, false>(v, t, cell, twl);
@@ -152,8 +159,8 @@ __global__ __launch_bounds__(NT) void k_nufft_interp_res(const float2* __restric
     if (f1 >= (unsigned)dm.nf) continue;
     const int j = tb.tr_bin[n];
     const int j1 = j + 1 == nt ? 0 : j + 1;
-    const float2* G0 = slots + (size_t)j * slab;
-    const float2* G1 = slots + (size_t)j1 * slab;
+    const float2* G0 = slots + __umul24((unsigned)j, (unsigned)slab);
+    const float2* G1 = slots + __umul24((unsigned)j1, (unsigned)slab);
     const unsigned long long bfix = tb.tr_b[n];
     unsigned long long tt = fix_mul(f1, bfix);
     const float2 rot = tb.tr_rot[n];
@@ -164,8 +171,8 @@ __global__ __launch_bounds__(NT) void k_nufft_interp_res(const float2* __restric
     for (int k = 0; k < kFptI; ++k) {
       if (fl0 + k >= 0 && fl0 + k < ft && f1 + k < (unsigned)dm.nf) {
         const KernelPoint kp = kernel_point<W>((unsigned)(tt >> 32), R1 * L);
-        const float2* g0 = G0 + (fl0 + k) * ldr + kp.base;
-        const float2* g1 = G1 + (fl0 + k) * ldr + kp.base;
+        const float2* g0 = G0 + __umul24((unsigned)(fl0 + k), (unsigned)ldr) + kp.base;
+        const float2* g1 = G1 + __umul24((unsigned)(fl0 + k), (unsigned)ldr) + kp.base;
         float2 a0 = make_float2(0.f, 0.f), a1 = make_float2(0.f, 0.f);
         float ph[W];
         kernel_taps<W, POLY>(kp.z0, dm.cbeta, ph);
@@ -200,7 +207,7 @@ __global__ __launch_bounds__(NT) void k_nufft_spread_res(const float2* __restric
   const int slab = ft * ldr;
   unsigned long long* slots = reinterpret_cast<unsigned long long*>(lds);   // [nt][ft][ldr]
   float2* twl = lds + (size_t)nt * slab;                                    // [mg]
-  float* sc = reinterpret_cast<float*>(twl + mg);                           // [nt]
+  float2* sc = twl + mg;                                                    // [nt]: (scale, 1/scale)
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int b = tile / dm.nftile;
   const int f0 = (tile - b * dm.nftile) * ft;
@@ -208,7 +215,10 @@ __global__ __launch_bounds__(NT) void k_nufft_spread_res(const float2* __restric
   const int c0 = bp[0], ntr = bp[nt] - bp[0];
   for (int i = threadIdx.x; i < nt * slab; i += NT) slots[i] = 0ull;
   for (int i = threadIdx.x; i < mg; i += NT) twl[i] = tb.tw_grid[i];
-  for (int i = threadIdx.x; i < nt; i += NT) sc[i] = slice_scale[(size_t)b * nt + i];
+  for (int i = threadIdx.x; i < nt; i += NT) {
+    const float v = slice_scale[(size_t)b * nt + i];
+    sc[i] = make_float2(v, 1.0f / v);
+  }
   __syncthreads();
 
   const int ld = dm.ldr;
@@ -232,9 +242,9 @@ __global__ __launch_bounds__(NT) void k_nufft_spread_res(const float2* __restric
     const float2 rot = make_float2(r.x, -r.y);
     float2 pre = pre_phase<1>(f1, tb.tr_a[n]);
     const float alpha = tb.tr_alpha[n];
-    const float sh = alpha * sc[j1], sl = (1.0f - alpha) * sc[j];
-    unsigned long long* lo = slots + (size_t)j * slab;
-    unsigned long long* hi = slots + (size_t)j1 * slab;
+    const float sh = alpha * sc[j1].x, sl = (1.0f - alpha) * sc[j].x;
+    unsigned long long* lo = slots + __umul24((unsigned)j, (unsigned)slab);
+    unsigned long long* hi = slots + __umul24((unsigned)j1, (unsigned)slab);
 #pragma unroll
     for (int k = 0; k < kFptS; ++k) {
       if (fl0 + k >= 0 && fl0 + k < ft && f1 + k < (unsigned)dm.nf) {
@@ -242,8 +252,8 @@ __global__ __launch_bounds__(NT) void k_nufft_spread_res(const float2* __restric
         const KernelPoint kp = kernel_point<W>((unsigned)(tt >> 32), R1 * L);
         const float2 s1 = cscale(sv, sh);
         const float2 s0 = cscale(sv, sl);
-        unsigned long long* g0 = lo + (fl0 + k) * ld + kp.base;
-        unsigned long long* g1 = hi + (fl0 + k) * ld + kp.base;
+        unsigned long long* g0 = lo + __umul24((unsigned)(fl0 + k), (unsigned)ld) + kp.base;
+        unsigned long long* g1 = hi + __umul24((unsigned)(fl0 + k), (unsigned)ld) + kp.base;
         float ph[W];
         kernel_taps<W, POLY>(kp.z0, dm.cbeta, ph);
 #pragma unroll
@@ -260,11 +270,12 @@ __global__ __launch_bounds__(NT) void k_nufft_spread_res(const float2* __restric
 
   const int t = threadIdx.x % L;
   float2* mdst = mhat + (size_t)b * nt * dm.nq * dm.nf;
+  const unsigned qn = (unsigned)dm.nq * (unsigned)dm.nf;
   for (int row = threadIdx.x / L; row < nt * ft; row += NT / L) {
     const int s = row >> ftl, fl = row & (ft - 1);
     const int f = f0 + fl;
     unsigned long long* cell = slots + (size_t)row * ldr;
-    const float inv = 1.0f / sc[s];
+    const float inv = sc[s].y;
     float2 v[R1];
 #pragma unroll
     for (int r = 0; r < R1; ++r) {
@@ -275,12 +286,13 @@ __global__ __launch_bounds__(NT) void k_nufft_spread_res(const float2* __restric
     }
     row_dft_lanes<R1, L, true>(v, t, reinterpret_cast<float2*>(cell), twl);
     if (f < dm.nf) {
+      float2* dst = mdst + (size_t)s * qn + f;
 #pragma unroll
       for (int i = 0; i < C; ++i) {
 #pragma unroll
         for (int k2 = 0; k2 < L; ++k2) {
           const int l = kept_mode_row<R1, L, HALF>(t, i, k2, dm);
-          if (l >= 0) mdst[((size_t)s * dm.nq + l) * dm.nf + f] = v[i * L + k2];
+          if (l >= 0) dst[__umul24((unsigned)l, (unsigned)dm.nf)] = v[i * L + k2];
         }
       }
     }
@@ -313,7 +325,7 @@ static hipError_t launch_interp_res_w(const Plan& p, const Dims& dm, const float
 template <int W, int R1, int L, int NT, bool HALF>
 static hipError_t launch_spread_res_w(const Plan& p, const Dims& dm, const float2* dhat, const float* slice_scale,
                                       float2* mhat, hipStream_t s) {
-  const size_t lds = res_lds_f2(dm.ft, dm.ldr, dm.ntheta, dm.mg) * sizeof(float2) + dm.ntheta * sizeof(float);
+  const size_t lds = res_lds_f2(dm.ft, dm.ldr, dm.ntheta, dm.mg) * sizeof(float2) + dm.ntheta * sizeof(float2);
   const dim3 grid((unsigned)dm.batch * dm.nftile), block(NT);
   const int ftl = ilog2(dm.ft);
   if constexpr (W >= 5) {

@@ -425,7 +425,7 @@ int res_row(int mg, int w) {
 // tile of ft frequencies fit the LDS of a CU.
 bool res_fits(const Dims& dm, int mg, int w, int ft) {
   if (dm.gdt != AAHRT_GRID_F32 || (mg != 64 && mg != 128 && mg != 256)) return false;
-  const size_t bytes = res_lds_f2(ft, res_row(mg, w), dm.ntheta, mg) * sizeof(float2) + dm.ntheta * sizeof(float);
+  const size_t bytes = res_lds_f2(ft, res_row(mg, w), dm.ntheta, mg) * sizeof(float2) + dm.ntheta * sizeof(float2);
   return bytes <= 160 * 1024;
 }
 
