@@ -385,6 +385,10 @@ def main():
                     help='instead of the solve: fwd+adj pairs on the other workloads')
     ap.add_argument('--table1', action='store_true',
                     help='instead of the solve: the velocity-scan timing at the paper\'s table shapes')
+    ap.add_argument('--gfst', default='',
+                    help='GFST setting as JSON (keys sigma, kernel_width, freq_tile, freq_tile_adjoint, '
+                         'block_threads, block_threads_adjoint) instead of autotuning it, e.g. to take '
+                         'counters on the setting a timed run chose')
     args = ap.parse_args()
     if args.gpus != 1:
         print('bench.py runs on one GPU only: the batched solve shards by gather, and this build '
@@ -412,7 +416,11 @@ def main():
           file=sys.stderr, flush=True)
 
     t0 = time.perf_counter()
-    plan = plan_from_workload(w, device=0)
+    pinned = json.loads(args.gfst) if args.gfst else {}
+    allowed = {'sigma', 'kernel_width', 'freq_tile', 'freq_tile_adjoint', 'block_threads', 'block_threads_adjoint'}
+    if set(pinned) - allowed:
+        raise SystemExit(f'--gfst: unknown keys {sorted(set(pinned) - allowed)}')
+    plan = plan_from_workload(w, device=0, **pinned)
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t0
     d = torch.tensor(w.data_all(), dtype=torch.float32, device=dev)

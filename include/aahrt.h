@@ -89,14 +89,21 @@ typedef struct aahrt_params {
                             2 -> the paper's own step 3 (Section 3.4): linear interpolation in k on the
                             sigma-oversampled grid, no deapodisation (low accuracy, reported only) */
   int32_t freq_tile;     /* frequencies per workgroup tile of the GFST kernels (power of 2, 1..64; halved until
-                            the tile fits LDS); 0 -> autotune */
+                            the tile fits LDS); 0 -> autotune.  The spreading kernel takes freq_tile_adjoint
+                            instead when that is set */
   int32_t grid_dtype;    /* aahrt_grid_dtype */
   int32_t gfst_kind;     /* 0: GFST kernels with every azimuth slice of a frequency tile resident in LDS where
                             they apply (FP32 q-grid of 64, 128 or 256 cells that fits), else the slice sweep;
                             1: always the slice sweep.  The two differ only in the FP32 rounding of the q-grid
                             transform; the tile changes no result within a kind */
   int32_t block_threads; /* threads per workgroup of the resident-slice GFST kernels: 512, 768 or 1024; 0 -> autotune
-                            (the slice sweep always uses 512); changes no result */
+                            (the slice sweep always uses 512); changes no result.  The spreading kernel takes
+                            block_threads_adjoint instead when that is set */
+  int32_t freq_tile_adjoint;     /* tile of the spreading (adjoint) GFST kernel alone, as freq_tile; 0 -> as
+                                    freq_tile.  With freq_tile and the two workgroup sizes this re-creates an
+                                    autotuned setting (aahrt_plan_info) without timing it again */
+  int32_t block_threads_adjoint; /* workgroup size of the spreading kernel alone, as block_threads; 0 -> as
+                                    block_threads */
 } aahrt_params;
 
 typedef struct aahrt_plan aahrt_plan;
@@ -147,13 +154,14 @@ const char* aahrt_last_error(void);
  * kernel's truncation error (computed in FP64 for white mode coefficients) and an FP32
  * rounding term that grows with the range of the deapodisation; in FP32 it keeps
  * sigma = 1.25 above about 6e-6 and sigma = 1.5 above about 1.1e-6, so at the default
- * tolerance only sigma = 2 is admitted.  When sigma, freq_tile or block_threads is 0 it
- * then autotunes the GFST stage: every admissible setting (sigma in {2, 1.5, 1.25}; for the
- * resident-slice kernels freq_tile in {1, 2, 4, 8} and block_threads in {512, 768, 1024}, for the
- * slice sweep freq_tile in {4, 8, 16, 32}) is timed on the interpolation and on the
- * spreading launch over the batch (on zeroed spectra, in a stream of its own,
- * synchronously); each kernel keeps its fastest tile and workgroup size, and the sigma with
- * the smallest sum is kept, the default sigma = 2 unless another is at least 5% faster.
+ * tolerance only sigma = 2 is admitted.  When a kernel has more than one admissible setting
+ * (sigma 0, or a tile or workgroup size that applies to it left at 0) it then autotunes the
+ * GFST stage: every admissible setting (sigma in {2, 1.5, 1.25}; for the resident-slice
+ * kernels freq_tile in {1, 2, 4, 8} and block_threads in {512, 768, 1024}, for the slice sweep
+ * freq_tile in {4, 8, 16, 32}, each narrowed by the requested values) is timed on the
+ * interpolation and on the spreading launch over the batch (on zeroed spectra, in a stream
+ * of its own, synchronously); each kernel keeps its fastest tile and workgroup size, and the
+ * sigma with the smallest sum is kept, the default sigma = 2 unless another is at least 5% faster.
  * Tiles and workgroup sizes change no result; sigma changes results within the tolerance.
  */
 int aahrt_plan_create(aahrt_plan** out, const aahrt_params* p, int32_t batch,

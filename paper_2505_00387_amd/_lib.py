@@ -35,7 +35,8 @@ class Params(ctypes.Structure):
                 ('nufft_tol', ctypes.c_double), ('sigma', ctypes.c_double),
                 ('kernel_width', ctypes.c_int32), ('freq_tile', ctypes.c_int32),
                 ('grid_dtype', ctypes.c_int32), ('gfst_kind', ctypes.c_int32),
-                ('block_threads', ctypes.c_int32)]
+                ('block_threads', ctypes.c_int32), ('freq_tile_adjoint', ctypes.c_int32),
+                ('block_threads_adjoint', ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):

@@ -43,14 +43,16 @@ class Plan:
 
     def __init__(self, axes, trace_ptr, x_km, y_km, nfft: int = 0, nufft_tol: float = 0.0,
                  sigma: float = 0.0, kernel_width: int = 0, freq_tile: int = 0, grid_dtype: int = 0,
-                 gfst_kind: int = 0, block_threads: int = 0, device: int = 0):
+                 gfst_kind: int = 0, block_threads: int = 0, freq_tile_adjoint: int = 0,
+                 block_threads_adjoint: int = 0, device: int = 0):
         lib = _lib.load()
         self._lib = lib
         p = _lib.Params(nt=axes.nt, dt=axes.dt, ntau=axes.ntau, dtau=axes.dtau, nq=axes.nq,
                         q_min=axes.q_min, q_max=axes.q_max, ntheta=axes.ntheta,
                         stretch=getattr(axes, 'stretch', 2), nfft=nfft, nufft_tol=nufft_tol,
                         sigma=sigma, kernel_width=kernel_width, freq_tile=freq_tile,
-                        grid_dtype=grid_dtype, gfst_kind=gfst_kind, block_threads=block_threads)
+                        grid_dtype=grid_dtype, gfst_kind=gfst_kind, block_threads=block_threads,
+                        freq_tile_adjoint=freq_tile_adjoint, block_threads_adjoint=block_threads_adjoint)
         tp = np.ascontiguousarray(trace_ptr, dtype=np.int64)
         xs = np.ascontiguousarray(x_km, dtype=np.float64)
         ys = np.ascontiguousarray(y_km, dtype=np.float64)
@@ -177,7 +179,8 @@ class Plan:
         other = Plan(self.axes, tp, np.concatenate(x_km), np.concatenate(y_km), nfft=0,
                      nufft_tol=self._params.nufft_tol, sigma=self.info['sigma'],
                      kernel_width=self._params.kernel_width, gfst_kind=self._params.gfst_kind,
-                     block_threads=self._params.block_threads, device=self.device)
+                     block_threads=self._params.block_threads,
+                     block_threads_adjoint=self._params.block_threads_adjoint, device=self.device)
         try:
             if getattr(self, '_wavelet', None) is not None:
                 other.set_wavelet(*self._wavelet)

@@ -133,7 +133,7 @@ __global__ __launch_bounds__(NT) void k_nufft_interp_res(const float2* __restric
     for (int r = 0; r < R1; ++r) {
       const int l = mode_row_of<R1, L, HALF>(t, r, dm);
       const float2 x = src[__umul24((unsigned)max(l, 0), (unsigned)dm.nf)];
-      v[r] = l >= 0 ? x : make_float2(0.f, 0.f);
+      v[r] = l >= 0 ? x : make_float2(-0.f, -0.f);  // -0: the additive identity, folded away
     }
     float2* cell = slots + (size_t)row * ldr;
     row_dft_lanes<R1, L, false>(v, t, cell, twl);

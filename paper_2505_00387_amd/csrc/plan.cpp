@@ -309,6 +309,12 @@ int validate_params(const aahrt_params& q) {
   if (q.gfst_kind < 0 || q.gfst_kind > 1) return bad("gfst_kind must be 0 or 1");
   if (q.block_threads != 0 && q.block_threads != 512 && q.block_threads != 768 && q.block_threads != 1024)
     return bad("block_threads must be 0, 512, 768 or 1024");
+  if (q.freq_tile_adjoint != 0 &&
+      (q.freq_tile_adjoint < 1 || q.freq_tile_adjoint > 64 || (q.freq_tile_adjoint & (q.freq_tile_adjoint - 1))))
+    return bad("freq_tile_adjoint must be 0 or a power of two in 1..64");
+  if (q.block_threads_adjoint != 0 && q.block_threads_adjoint != 512 && q.block_threads_adjoint != 768 &&
+      q.block_threads_adjoint != 1024)
+    return bad("block_threads_adjoint must be 0, 512, 768 or 1024");
   return AAHRT_OK;
 }
 
@@ -325,6 +331,7 @@ struct NufftChoice {
   double est;
   int res;  // 1: resident-slice kernels
   int bs;   // threads per workgroup (512, 768 or 1024 for the resident kernels, else kBlockG)
+  bool fwd = true, adj = true;  // a setting the interpolation (fwd) / spreading (adj) kernel may take
 };
 
 // Shape parameter of the exponential-of-semicircle kernel, beta = 0.98 pi (1 - 1/(2 sigma)) w:
@@ -439,6 +446,39 @@ bool choice_fits(const Dims& dm, int mg, int w, int ft) {
   return grid_lds(ft, slot_row(mg, w), dm.ntheta, mg, dm.gdt) <= 160 * 1024 && dm.nq * ft <= kPrefetchCells;
 }
 
+// The (tile, workgroup) settings of one grid shape.  Each kernel takes its requested tile
+// (freq_tile; for spreading freq_tile_adjoint when set), halved until it fits, or any of
+// `free_ft` that fits, and its requested workgroup size (block_threads, block_threads_adjoint;
+// the resident-slice kernels only) or any of 512, 768 and 1024.  A setting is listed once, marked
+// with the kernels that may take it.
+template <class Fits>
+void add_tile_choices(const aahrt_params& prm, int mg, int w, double est, int res, const std::vector<int>& free_ft,
+                      Fits fits, std::vector<NufftChoice>& out) {
+  auto pinned = [&](int ft) {
+    while (ft > 1 && !fits(ft)) ft /= 2;
+    return fits(ft) ? ft : 0;
+  };
+  const int ft_f = prm.freq_tile != 0 ? pinned(prm.freq_tile) : -1;
+  const int ft_a = prm.freq_tile_adjoint != 0 ? pinned(prm.freq_tile_adjoint) : ft_f;
+  const int bs_f = res ? prm.block_threads : 0;
+  const int bs_a = res ? (prm.block_threads_adjoint != 0 ? prm.block_threads_adjoint : prm.block_threads) : 0;
+  std::vector<int> tiles;
+  for (int ft : {ft_f, ft_a})
+    if (ft > 0 && std::find(tiles.begin(), tiles.end(), ft) == tiles.end()) tiles.push_back(ft);
+  if (ft_f < 0 || ft_a < 0)
+    for (int ft : free_ft)
+      if (fits(ft) && std::find(tiles.begin(), tiles.end(), ft) == tiles.end()) tiles.push_back(ft);
+  const std::vector<int> sizes = res ? std::vector<int>{512, 768, 1024} : std::vector<int>{kBlockG};
+  for (int ft : tiles) {
+    for (int bs : sizes) {
+      NufftChoice c{mg, w, ft, est, res, bs};
+      c.fwd = (ft_f < 0 || ft == ft_f) && (bs_f == 0 || bs == bs_f);
+      c.adj = (ft_a < 0 || ft == ft_a) && (bs_a == 0 || bs == bs_a);
+      if (c.fwd || c.adj) out.push_back(c);
+    }
+  }
+}
+
 // Candidates: the requested sigma (or 2, 1.5 and 1.25 when it is free) with the narrowest
 // width whose estimated error meets the tolerance (or the requested width), and the
 // requested tile (or 4..32 when free).  A free sigma that no width brings within the
@@ -451,9 +491,7 @@ int nufft_candidates(const aahrt_params& prm, const Dims& dm, std::vector<NufftC
   std::vector<double> sig;
   if (prm.sigma != 0.0) sig.push_back(prm.sigma);
   else sig = {2.0, 1.5, 1.25};
-  std::vector<int> fts;
-  if (prm.freq_tile != 0) fts.push_back(prm.freq_tile);
-  else fts = {16, 8, 32, 4};
+  const std::vector<int> fts = {16, 8, 32, 4};
   out.clear();
   std::vector<int> seen_mg;
   NufftChoice fallback{0, 0, 0, 1e300, 0, kBlockG};
@@ -481,40 +519,21 @@ int nufft_candidates(const aahrt_params& prm, const Dims& dm, std::vector<NufftC
     // slice sweep with tiles of 4..32
     const bool res = prm.gfst_kind != 1 && res_fits(dm, mg, w, 1);
     if (res) {
-      if (prm.freq_tile != 0) {
-        int ft = prm.freq_tile;
-        while (ft > 1 && !res_fits(dm, mg, w, ft)) ft /= 2;
-        for (int bs : {512, 768, 1024})
-          if (prm.block_threads == 0 || prm.block_threads == bs) out.push_back({mg, w, ft, est, 1, bs});
-      } else {
-        for (int ft : {4, 8, 2, 1})
-          for (int bs : {512, 768, 1024})
-            if (res_fits(dm, mg, w, ft) && (prm.block_threads == 0 || prm.block_threads == bs))
-              out.push_back({mg, w, ft, est, 1, bs});
-      }
+      add_tile_choices(prm, mg, w, est, 1, {4, 8, 2, 1}, [&](int ft) { return res_fits(dm, mg, w, ft); }, out);
       continue;
     }
-    if (prm.freq_tile != 0) {
-      // a requested tile is halved until it fits
-      int ft = prm.freq_tile;
+    const size_t before = out.size();
+    add_tile_choices(prm, mg, w, est, 0, fts, [&](int ft) { return choice_fits(dm, mg, w, ft); }, out);
+    if (out.size() == before) {
+      int ft = 16;
       while (ft > 1 && !choice_fits(dm, mg, w, ft)) ft /= 2;
       if (choice_fits(dm, mg, w, ft)) out.push_back({mg, w, ft, est, 0, kBlockG});
-    } else {
-      for (int ft : fts)
-        if (choice_fits(dm, mg, w, ft)) out.push_back({mg, w, ft, est, 0, kBlockG});
-      if (out.empty() || out.back().mg != mg) {
-        int ft = 16;
-        while (ft > 1 && !choice_fits(dm, mg, w, ft)) ft /= 2;
-        if (choice_fits(dm, mg, w, ft)) out.push_back({mg, w, ft, est, 0, kBlockG});
-      }
     }
   }
   if (out.empty() && fallback.mg != 0) {
     // no free sigma meets the tolerance: the setting with the smallest estimate
-    int ft = prm.freq_tile != 0 ? prm.freq_tile : 16;
-    while (ft > 1 && !choice_fits(dm, fallback.mg, fallback.w, ft)) ft /= 2;
-    if (choice_fits(dm, fallback.mg, fallback.w, ft))
-      out.push_back({fallback.mg, fallback.w, ft, fallback.est, 0, kBlockG});
+    add_tile_choices(prm, fallback.mg, fallback.w, fallback.est, 0, {16},
+                     [&](int ft) { return choice_fits(dm, fallback.mg, fallback.w, ft); }, out);
   }
   if (out.empty()) return fail(AAHRT_E_UNSUPPORTED, "q-grid too large for LDS");
   return AAHRT_OK;
@@ -608,14 +627,20 @@ int autotune_nufft(Plan& P, const std::vector<NufftChoice>& cands) {
       size_t j = i;
       float bi = 0.f, bs = 0.f;
       int fi = 0, fs = 0, ni = kBlockG, ns = kBlockG;
+      bool have_i = false, have_s = false;
       for (; j < cands.size() && cands[j].mg == cands[i].mg && rc == AAHRT_OK; ++j) {
         if ((rc = set_nufft(P, cands[j])) != AAHRT_OK) break;
-        float ti = 0.f, ts = 0.f;
-        if ((rc = run(0, &ti)) != AAHRT_OK || (rc = run(1, &ts)) != AAHRT_OK) break;
-        P.tune_ms.push_back(ti);
-        P.tune_ms.push_back(ts);
-        if (j == i || ti < bi) { bi = ti; fi = cands[j].ft; ni = cands[j].bs; }
-        if (j == i || ts < bs) { bs = ts; fs = cands[j].ft; ns = cands[j].bs; }
+        float t = 0.f;
+        if (cands[j].fwd) {
+          if ((rc = run(0, &t)) != AAHRT_OK) break;
+          P.tune_ms.push_back(t);
+          if (!have_i || t < bi) { bi = t; fi = cands[j].ft; ni = cands[j].bs; have_i = true; }
+        }
+        if (cands[j].adj) {
+          if ((rc = run(1, &t)) != AAHRT_OK) break;
+          P.tune_ms.push_back(t);
+          if (!have_s || t < bs) { bs = t; fs = cands[j].ft; ns = cands[j].bs; have_s = true; }
+        }
       }
       if (rc != AAHRT_OK) break;
       // another oversampling (which changes results within the tolerance) replaces the
@@ -988,7 +1013,17 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
 
   TRY(build_grid_tables(P, trace_ptr, x, y));
   TRY(set_nufft(P, cands[0]));
-  if (cands.size() > 1) TRY(autotune_nufft(P, cands));
+  // timed only when a kernel has a choice; otherwise each kernel takes its one setting
+  const auto n_fwd = std::count_if(cands.begin(), cands.end(), [](const NufftChoice& c) { return c.fwd; });
+  const auto n_adj = std::count_if(cands.begin(), cands.end(), [](const NufftChoice& c) { return c.adj; });
+  if (n_fwd > 1 || n_adj > 1) {
+    TRY(autotune_nufft(P, cands));
+  } else {
+    for (const NufftChoice& c : cands) {
+      if (c.fwd) { P.ft_interp = c.ft; P.bs_interp = c.bs; }
+      if (c.adj) { P.ft_spread = c.ft; P.bs_spread = c.bs; }
+    }
+  }
   return AAHRT_OK;
 }
 

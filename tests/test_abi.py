@@ -74,6 +74,7 @@ def _create(p, trace_ptr=(0, 3), x=(0.1, 0.2, 0.3), y=(0.0, 0.1, -0.2), batch=No
     (dict(nfft=129), 'nfft'), (dict(nfft=14), 'nfft'), (dict(sigma=1.1), 'sigma'),
     (dict(kernel_width=1), 'kernel_width'), (dict(kernel_width=13), 'kernel_width'), (dict(freq_tile=3), 'freq_tile'), (dict(grid_dtype=7), 'grid_dtype'),
     (dict(gfst_kind=2), 'gfst_kind'), (dict(block_threads=256), 'block_threads'), (dict(block_threads=640), 'block_threads'),
+    (dict(freq_tile_adjoint=3), 'freq_tile_adjoint'), (dict(block_threads_adjoint=256), 'block_threads_adjoint'),
 ])
 def test_invalid_params_are_rejected(kw, needle):
     rc, msg = _create(_params(**kw))

@@ -328,8 +328,30 @@ def test_frequency_tile_changes_no_result(kind):
         assert plan.info['block_threads'] == (bs or 512) == plan.info['block_threads_adjoint']
         outs.append((to_host(plan.forward(m)), to_host(plan.adjoint(d))))
         plan.close()
+    # the spreading kernel pinned apart from the interpolation, as an autotuned plan reports them
+    split = dict(freq_tile=8, block_threads=768, freq_tile_adjoint=2 if kind == 0 else 16,
+                 block_threads_adjoint=1024 if kind == 0 else 0)
+    plan = make_plan(w, sigma=2.0, gfst_kind=kind, **split)
+    info = plan.info
+    assert info['autotune_candidates'] == 0
+    assert (info['freq_tile'], info['freq_tile_adjoint']) == (8, split['freq_tile_adjoint'])
+    assert (info['block_threads'], info['block_threads_adjoint']) == ((768, 1024) if kind == 0 else (512, 512))
+    outs.append((to_host(plan.forward(m)), to_host(plan.adjoint(d))))
+    plan.close()
     for o in outs[1:]:
         assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
+
+
+def test_adjoint_tile_pins_narrow_the_autotuner():
+    """A pinned spreading tile and workgroup size leave only the interpolation kernel to be
+    timed (tiles 1, 2, 4, 8 by sizes 512, 768, 1024), and the plan keeps the pinned values."""
+    w = wl.config3(with_data=False)
+    plan = make_plan(w, sigma=2.0, freq_tile_adjoint=4, block_threads_adjoint=512)
+    info = plan.info
+    assert info['gfst_resident'] == 1
+    assert (info['freq_tile_adjoint'], info['block_threads_adjoint']) == (4, 512)
+    assert info['autotune_candidates'] == 12 + 1
+    plan.close()
 
 
 @pytest.mark.parametrize('nq,ntheta', [(128, 4), (32, 1)])
