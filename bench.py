@@ -391,7 +391,7 @@ def main():
                          'counters on the setting a timed run chose')
     args = ap.parse_args()
     if args.gpus != 1:
-        print('bench.py runs on one GPU only: the batched solve shards by gather, and this build '
+        print('bench.py runs on one GPU only: the batched solve shards by gather, and this bench '
               'measures one GPU\'s share (use --gpus 1).', file=sys.stderr)
         sys.exit(2)
 

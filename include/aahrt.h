@@ -55,7 +55,7 @@ typedef enum {
   AAHRT_E_INVALID = -1,     /* bad argument; nothing enqueued */
   AAHRT_E_HIP = -2,         /* HIP runtime error */
   AAHRT_E_NOMEM = -3,       /* device allocation failed */
-  AAHRT_E_UNSUPPORTED = -4  /* valid but not supported by this build */
+  AAHRT_E_UNSUPPORTED = -4  /* valid but not supported by this library */
 } aahrt_status;
 
 typedef enum {
