@@ -56,6 +56,17 @@ struct __attribute__((aligned(16))) Tap {
   float w0, w1;
 };
 
+// One output of the transpose U^T, read with a single 16-byte load: its inputs a and a + 1
+// with their weights w0, w1 (n = 0, 1 or 2 of them), or n = -1 where more than two inputs
+// reach the output (the general gather over the start table then runs).  Past t = 0 the
+// data samples are sparse on the stretched axis, so nearly every output takes this form; S^T,
+// whose outputs gather up to eight inputs, keeps the start table alone.
+struct __attribute__((aligned(16))) LerpRec {
+  int a;
+  float w0, w1;
+  int n;
+};
+
 // Device tables of one plan.  Per-trace arrays are stored in "bin order":
 // within a gather, traces are grouped by their lower azimuth bin j_n.
 struct Tables {
@@ -71,6 +82,7 @@ struct Tables {
   // first time sample whose lower tap is >= r (r <= nt')
   const int* u_start;
   const float2* u_w;
+  const LerpRec* u_rec;   // [nt']
   // deapodisation 1/Phi(2 pi k/Mg), k = l - nq/2, per curvature sample l
   const float* deapod;
   // twiddles

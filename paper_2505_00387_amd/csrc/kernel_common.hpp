@@ -112,13 +112,50 @@ __device__ __forceinline__ float lerp_transpose(int i, const int* __restrict__ s
   return acc;
 }
 
+// The same output from its record: one 16-byte load where at most two inputs reach it (the same
+// products in the same order as above), the general gather otherwise.
+__device__ __forceinline__ float lerp_transpose(int i, const LerpRec* __restrict__ rec, const int* __restrict__ start,
+                                                const float2* __restrict__ w, const float* x) {
+  const LerpRec r = rec[i];
+  if (r.n < 0) return lerp_transpose(i, start, w, x);
+  float acc = 0.f;
+  if (r.n > 0) acc = fmaf(r.w0, x[r.a], acc);
+  if (r.n > 1) acc = fmaf(r.w1, x[r.a + 1], acc);
+  return acc;
+}
+
+// S^T output i as X_i + Y_{i-1}: X_j and Y_j sum the lower- and upper-tap weights of the inputs
+// whose lower tap is j (those of [start[j], start[j+1])), so every input is read once.  The
+// lanes of a wavefront hold consecutive outputs (i = threadIdx.x + k kBlock): Y_{i-1} comes
+// from the lane before, and the first lane of the wavefront sums it itself.  All lanes of a
+// wavefront that hold an output call this together.
+static_assert(kBlock % 64 == 0, "row workgroups are whole wavefronts");
+__device__ __forceinline__ float stretch_transpose(int i, const int* __restrict__ start, const float2* __restrict__ w,
+                                                   const float* x) {
+  const int b = start[i], c = start[i + 1];
+  float xs = 0.f, ys = 0.f;
+  for (int r = b; r < c; ++r) {
+    const float2 wr = w[r];
+    const float v = x[r];
+    xs = fmaf(wr.x, v, xs);
+    ys = fmaf(wr.y, v, ys);
+  }
+  float yp = __shfl_up(ys, 1);
+  if ((threadIdx.x & 63) == 0) {
+    yp = 0.f;
+    if (i > 0)
+      for (int r = start[i - 1]; r < b; ++r) yp = fmaf(w[r].y, x[r], yp);
+  }
+  return xs + yp;
+}
+
 // Pack x[r] = (U^T g)[r] (r < nts, zero beyond) as z[p] = x[2p] + i x[2p+1], i.e. x
 // written in order over the floats of buf.  One output per thread and pass: the
 // first outputs gather the most inputs (t' = t^2 is flat near t = 0).
 __device__ __forceinline__ void pack_transpose(float2* buf, const float* g, const Tables& tb, int nts, int nh) {
   float* xf = reinterpret_cast<float*>(buf);
   for (int r = threadIdx.x; r < 2 * nh; r += kBlock)
-    xf[r] = r < nts ? lerp_transpose(r, tb.u_start, tb.u_w, g) : 0.f;
+    xf[r] = r < nts ? lerp_transpose(r, tb.u_rec, tb.u_start, tb.u_w, g) : 0.f;
 }
 
 // ------------------------------------------------------------------ model side

@@ -334,6 +334,21 @@ struct NufftChoice {
   bool fwd = true, adj = true;  // a setting the interpolation (fwd) / spreading (adj) kernel may take
 };
 
+// Per-output records of the transpose U^T from its start table and per-input weights:
+// output i takes the inputs [start[i-1], start[i+1]), those below start[i] by their upper
+// weight (.y) and the others by their lower one (.x).
+std::vector<LerpRec> lerp_records(const std::vector<int>& start, const std::vector<float2>& w, int nout) {
+  std::vector<LerpRec> rec(nout);
+  for (int i = 0; i < nout; ++i) {
+    const int b = start[i], c = start[i + 1], a = i > 0 ? start[i - 1] : b;
+    LerpRec r{a, 0.f, 0.f, c - a <= 2 ? c - a : -1};
+    if (r.n >= 1) r.w0 = a < b ? w[a].y : w[a].x;
+    if (r.n >= 2) r.w1 = a + 1 < b ? w[a + 1].y : w[a + 1].x;
+    rec[i] = r;
+  }
+  return rec;
+}
+
 // Shape parameter of the exponential-of-semicircle kernel, beta = 0.98 pi (1 - 1/(2 sigma)) w:
 // the rule of Barnett, Magland and af Klinteberg (SIAM J. Sci. Comput. 41, 2019) for the
 // width of the kernel's spectrum at oversampling sigma (2.31 w at sigma = 2).  Above
@@ -972,6 +987,7 @@ int build_plan(Plan& P, const aahrt_params& prm, int32_t batch, const int64_t* t
   TRY(upload(P, s_start, &tb.s_start)); TRY(upload(P, s_w, &tb.s_w));
   TRY(upload(P, u_tap, &tb.u_tap));
   TRY(upload(P, u_start, &tb.u_start)); TRY(upload(P, u_w, &tb.u_w));
+  TRY(upload(P, lerp_records(u_start, u_w, dm.nts), &tb.u_rec));
   TRY(upload(P, tw_half, &tb.tw_half)); TRY(upload(P, tw_real, &tb.tw_real));
   {
     int mg_cap = 0;

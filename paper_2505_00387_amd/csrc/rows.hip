@@ -53,7 +53,7 @@ __global__ __launch_bounds__(kBlock) void k_model_c2r(const float2* __restrict__
   const float sc = tb.deapod[l] / (float)dm.nfft;
   float* dst = m + rid * dm.ntau;
   for (int i = threadIdx.x; i < dm.ntau; i += kBlock) {
-    dst[i] = sc * lerp_transpose(i, tb.s_start, tb.s_w, xs);
+    dst[i] = sc * stretch_transpose(i, tb.s_start, tb.s_w, xs);
   }
 }
 
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(kBlock) void k_model_c2r_update(float2* __restrict_
   float s1 = 0.f;
   bool nonzero = false;
   auto step = [&](int i, float yo, float xo) {
-    const float v = yo + g * (sc * lerp_transpose(i, tb.s_start, tb.s_w, xs));
+    const float v = yo + g * (sc * stretch_transpose(i, tb.s_start, tb.s_w, xs));
     const float a = fabsf(v) - thr;
     const float xn = a > 0.f ? copysignf(a, v) : 0.f;
     const float yn = ista ? xn : xn + beta * (xn - xo);
