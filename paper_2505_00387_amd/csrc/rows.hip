@@ -167,7 +167,7 @@ __global__ __launch_bounds__(kBlock) void k_data_c2r(const float2* __restrict__ 
   float2* B = lds + dm.nhp;
   const size_t n = blockIdx.x;
   const auto twb = row_twiddles<IP>(tb);
-  load_packed_c2r(A, dhat + n * dm.nf, tb, dm);
+  load_packed_c2r_pairs(A, dhat + n * dm.nf, tb, dm);
   __syncthreads();
   const float2* X = row_fft<true, IP>(A, B, fp, tb, dm, twb);
   const float* xs = reinterpret_cast<const float*>(X);
