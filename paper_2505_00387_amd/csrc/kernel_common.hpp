@@ -86,8 +86,8 @@ __device__ __forceinline__ void load_packed_c2r(float2* buf, const float2* __res
 
 // The same, with bins k and N/2 - k formed by one thread, so that each spectrum value and
 // twiddle is read once (the twiddle of bin N/2 - k, exp(-2 pi i (N/2 - k)/N) = (-c, s), follows
-// from that of bin k, (c, s)).  Measured faster where the row transform is all that follows
-// (the data side of L); in the kernels with more work after the transform the form above is.
+// from that of bin k, (c, s)).  It measured faster in the data-side C2R kernel and slower in
+// the model-side and fused kernels, which keep the form above.
 __device__ __forceinline__ void load_packed_c2r_pairs(float2* buf, const float2* __restrict__ src,
                                                       const Tables& tb, const Dims& dm) {
 #pragma unroll 2
