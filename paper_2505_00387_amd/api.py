@@ -82,6 +82,14 @@ class Plan:
     def data_shape(self):
         return (self.ntraces, self.axes.nt)
 
+    def gfst_setting(self) -> dict:
+        """The GFST setting this plan runs (autotuned or requested), as keyword arguments that
+        re-create it on another Plan without timing it again."""
+        i = self.info
+        return {'sigma': i['sigma'], 'kernel_width': i['kernel_width'], 'freq_tile': i['freq_tile'],
+                'freq_tile_adjoint': i['freq_tile_adjoint'], 'block_threads': i['block_threads'],
+                'block_threads_adjoint': i['block_threads_adjoint']}
+
     def close(self):
         if getattr(self, '_h', None) is not None and self._h.value:
             self._lib.aahrt_plan_destroy(self._h)

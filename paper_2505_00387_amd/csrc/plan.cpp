@@ -511,7 +511,8 @@ int nufft_candidates(const aahrt_params& prm, const Dims& dm, std::vector<NufftC
   std::vector<int> seen_mg;
   NufftChoice fallback{0, 0, 0, 1e300, 0, kBlockG};
   for (double sg : sig) {
-    const int mg0 = next_smooth_even((long)std::ceil(sg * dm.nq));
+    // (less a rounding margin, so that a sigma reported as mg/nq gives back mg)
+    const int mg0 = next_smooth_even((long)std::ceil(sg * dm.nq - 1e-9));
     int w = prm.kernel_width, mg = mg0;
     double est = 0.0;
     if (w != 0) {

@@ -351,6 +351,15 @@ def test_adjoint_tile_pins_narrow_the_autotuner():
     assert info['gfst_resident'] == 1
     assert (info['freq_tile_adjoint'], info['block_threads_adjoint']) == (4, 512)
     assert info['autotune_candidates'] == 12 + 1
+    # the reported setting re-creates the plan without timing, bitwise equal in result
+    again = make_plan(w, **plan.gfst_setting())
+    assert again.info['autotune_candidates'] == 0
+    assert {k: again.info[k] for k in plan.gfst_setting()} == plan.gfst_setting()
+    m = to_dev(wl.random_model(w.axes, w.batch, 4))
+    d = to_dev(wl.random_data(int(w.trace_ptr[-1]), w.axes.nt, 4))
+    assert np.array_equal(to_host(plan.forward(m)), to_host(again.forward(m)))
+    assert np.array_equal(to_host(plan.adjoint(d)), to_host(again.adjoint(d)))
+    again.close()
     plan.close()
 
 
