@@ -41,6 +41,19 @@ __device__ __forceinline__ float block_max(float v, float* red) {
   return s;
 }
 
+// Stores of row outputs that no later step of the same kernel reads (spectra, model and data
+// rows, the iterates): nontemporal, so that they do not displace the tables and inputs the
+// other workgroups still read from L2 (1-4% faster row kernels).  The GFST kernels keep
+// ordinary stores: theirs cover 32-64 bytes of a line and rely on L2 combining them.
+typedef float v2f_nt __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void store_nt(float2* p, float2 x) {
+  v2f_nt v;
+  v.x = x.x;
+  v.y = x.y;
+  __builtin_nontemporal_store(v, reinterpret_cast<v2f_nt*>(p));
+}
+__device__ __forceinline__ void store_nt(float* p, float x) { __builtin_nontemporal_store(x, p); }
+
 // Spectrum of a real sequence of length N from the FFT Z of the packed
 // complex sequence z[p] = x[2p] + i x[2p+1] (length N/2), bins k < N/2.
 // Returns this thread's max over its bins of |Re| + |Im|.
@@ -56,7 +69,7 @@ __device__ __forceinline__ float store_real_spectrum(const float2* buf, float2* 
     const float2 dz = make_float2(0.5f * (z.x - zc.x), 0.5f * (z.y - zc.y));
     const float2 zo = make_float2(dz.y, -dz.x);  // dz / i
     const float2 X = cadd(ze, cmul(tb.tw_real[k], zo));
-    dst[k] = X;
+    store_nt(dst + k, X);
     mx = fmaxf(mx, fabsf(X.x) + fabsf(X.y));
   }
   return mx;

@@ -53,7 +53,7 @@ __global__ __launch_bounds__(kBlock) void k_model_c2r(const float2* __restrict__
   const float sc = tb.deapod[l] / (float)dm.nfft;
   float* dst = m + rid * dm.ntau;
   for (int i = threadIdx.x; i < dm.ntau; i += kBlock) {
-    dst[i] = sc * stretch_transpose(i, tb.s_start, tb.s_w, xs);
+    store_nt(dst + i, sc * stretch_transpose(i, tb.s_start, tb.s_w, xs));
   }
 }
 
@@ -104,8 +104,8 @@ __global__ __launch_bounds__(kBlock) void k_model_c2r_update(float2* __restrict_
     const float a = fabsf(v) - thr;
     const float xn = a > 0.f ? copysignf(a, v) : 0.f;
     const float yn = ista ? xn : xn + beta * (xn - xo);
-    yr[i] = yn;
-    xr[i] = xn;
+    store_nt(yr + i, yn);
+    store_nt(xr + i, xn);
     if (NEXT) stage[i] = yn;
     nonzero |= yn != 0.f;
     s1 += fabsf(xn);
@@ -125,7 +125,7 @@ __global__ __launch_bounds__(kBlock) void k_model_c2r_update(float2* __restrict_
     // a zero spectrum, written without the transform (most rows of a sparse cube are)
     if (!__syncthreads_or(nonzero ? 1 : 0)) {
       float2* dst = mhat + rid * dm.nf;
-      for (int k = threadIdx.x; k < dm.nf; k += kBlock) dst[k] = make_float2(0.f, 0.f);
+      for (int k = threadIdx.x; k < dm.nf; k += kBlock) store_nt(dst + k, make_float2(0.f, 0.f));
       return;
     }
     float2* in = IP ? A : (stage == reinterpret_cast<float*>(A) ? B : A);
@@ -177,7 +177,7 @@ __global__ __launch_bounds__(kBlock) void k_data_c2r(const float2* __restrict__ 
 #pragma unroll 4
     for (int s = threadIdx.x; s < dm.nt; s += kBlock) {
       const Tap t = tb.u_tap[s];
-      dst[s] = invN * (t.w0 * xs[t.i0] + t.w1 * xs[t.i1]);
+      store_nt(dst + s, invN * (t.w0 * xs[t.i0] + t.w1 * xs[t.i1]));
     }
   } else {
     float* v = reinterpret_cast<float*>(X == A ? B : A);  // IP: the staging area after A
@@ -186,7 +186,7 @@ __global__ __launch_bounds__(kBlock) void k_data_c2r(const float2* __restrict__ 
       v[s] = invN * (t.w0 * xs[t.i0] + t.w1 * xs[t.i1]);
     }
     __syncthreads();
-    for (int s = threadIdx.x; s < dm.nt; s += kBlock) dst[s] = wav_conv(v, s, tb, dm);
+    for (int s = threadIdx.x; s < dm.nt; s += kBlock) store_nt(dst + s, wav_conv(v, s, tb, dm));
   }
 }
 
