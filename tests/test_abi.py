@@ -129,3 +129,35 @@ def test_binding_fails_loudly_without_the_library(monkeypatch):
     monkeypatch.setattr(_lib, 'LIB_PATH', os.path.join(ROOT, '_no_such_dir', 'libaahrt.so'))
     with pytest.raises(ImportError, match='missing'):
         _lib.load()
+
+
+@pytest.mark.parametrize('cstruct,pyname', [('aahrt_params', 'Params'), ('aahrt_plan_info', 'PlanInfo')])
+def test_binding_structs_match_the_header_layout(tmp_path, cstruct, pyname):
+    """The ctypes mirrors of the header's structs have the same fields, in the same order, at the
+    same offsets and with the same total size as a C compiler lays them out from the header."""
+    import ctypes
+    import re
+    import shutil
+    cc = shutil.which('gcc') or shutil.which('cc')
+    if cc is None:
+        pytest.skip('no C compiler')
+    L = _lib()
+    py = getattr(L, pyname)
+    hdr = open(os.path.join(ROOT, 'include', 'aahrt.h')).read()
+    body = hdr[hdr.index(f'typedef struct {cstruct} {{'):]
+    body = body[:body.index(f'}} {cstruct};')]
+    body = re.sub(r'/\*.*?\*/', '', body, flags=re.S)
+    names = [n.strip() for decl in re.findall(r'\b(?:int32_t|int64_t|double)\s+([^;]+);', body)
+             for n in decl.split(',')]
+    assert names == [n for n, _ in py._fields_]
+    src = tmp_path / 'layout.c'
+    lines = [f'#include "{os.path.join(ROOT, "include", "aahrt.h")}"', '#include <stdio.h>', '#include <stddef.h>',
+             'int main(void) {', f'  printf("%zu\\n", sizeof({cstruct}));']
+    lines += [f'  printf("%zu\\n", offsetof({cstruct}, {n}));' for n in names]
+    lines += ['  return 0;', '}']
+    src.write_text('\n'.join(lines) + '\n')
+    exe = tmp_path / 'layout'
+    subprocess.run([cc, '-std=c99', str(src), '-o', str(exe)], check=True, capture_output=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert vals[0] == ctypes.sizeof(py)
+    assert vals[1:] == [getattr(py, n).offset for n in names]
